@@ -1,0 +1,227 @@
+"""FP64 CPU oracle — TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the HIP path; the two meet only in
+the seeded input generators, which hold none of the method's arithmetic.
+
+Contents
+  * ctypes wrappers over ``liboracle.so`` (plain C, FP64, single-threaded):
+    DG differentiation and its adjoint, the mixed-order form, the five-point
+    stencil, square matmul, BF16 / FP8-E4M3FN encoders and decoders, the
+    quantiser with power-of-two scales, and the brute-force feature enumerator.
+  * ``model``: the least-squares calibration and prediction of the paper's
+    Sections "Computing Model Parameters" and "Predicting Cost", in FP64.
+  * ``metrics``: error measures used by the parity tests.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        _lib = ctypes.CDLL(_build.LIB)
+        _declare(_lib)
+    return _lib
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i8p = ctypes.POINTER(ctypes.c_int8)
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int
+
+
+def _declare(L):
+    L.orc_dg_forward.argtypes = [_i32, _i64, _i32, _dp, _dp, _dp]
+    L.orc_dg_forward_select.argtypes = [_i32, _i32, _dp, _dp, _i64, _i64p, _dp]
+    L.orc_dg_batched.argtypes = [_i32, _i64, _i8p, _i64p, _dp, _i64p, _dp, _dp]
+    L.orc_dg_adjoint.argtypes = [_i32, _i64, _i32, _dp, _dp, _dp, ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_stencil5.argtypes = [_i64, _dp, _i64, _dp, _i64]
+    L.orc_stencil5_select.argtypes = [_i64, _dp, _i64, _i64, _i64p, _i64p, _dp]
+    L.orc_matmul.argtypes = [_i64, _dp, _dp, _dp]
+    L.orc_matmul_select.argtypes = [_i64, _dp, _dp, _i64, _i64p, _i64p, _dp]
+    L.orc_bf16_encode.argtypes = [ctypes.c_float]
+    L.orc_bf16_encode.restype = ctypes.c_uint16
+    L.orc_bf16_decode.argtypes = [ctypes.c_uint16]
+    L.orc_bf16_decode.restype = ctypes.c_float
+    L.orc_e4m3_encode.argtypes = [ctypes.c_double]
+    L.orc_e4m3_encode.restype = ctypes.c_uint8
+    L.orc_e4m3_decode.argtypes = [ctypes.c_uint8]
+    L.orc_e4m3_decode.restype = ctypes.c_double
+    L.orc_pow2_scale.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.orc_pow2_scale.restype = ctypes.c_double
+    L.orc_quantize.argtypes = [_i32, _i64, _i64, _i32, _fp, ctypes.c_void_p, _fp]
+    if hasattr(L, "orc_features"):
+        L.orc_features.argtypes = [_i32, _i32, _i64, _i64, _i64, _i32, _i32, _i32, _i32, _i64p]
+        L.orc_features.restype = _i32
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+# ------------------------------------------------------------------ DG family
+
+def dg_forward(D, u):
+    """out[m][e][i] = sum_j D[m][i][j] u[e][j]  (FP64)."""
+    D, u = _f64(D), _f64(u)
+    nmat, nunit, _ = D.shape
+    nelem = u.shape[0]
+    assert u.shape == (nelem, nunit)
+    out = np.empty((nmat, nelem, nunit), dtype=np.float64)
+    lib().orc_dg_forward(nmat, nelem, nunit, _ptr(D), _ptr(u), _ptr(out))
+    return out
+
+
+def dg_forward_select(D, u, elems):
+    """Forward for the listed elements only; returns [nsel][nmat][nunit]."""
+    D, u = _f64(D), _f64(u)
+    nmat, nunit, _ = D.shape
+    el = np.ascontiguousarray(elems, dtype=np.int64)
+    assert el.min(initial=0) >= 0 and el.max(initial=0) < u.shape[0]
+    out = np.empty((len(el), nmat, nunit), dtype=np.float64)
+    lib().orc_dg_forward_select(nmat, nunit, _ptr(D), _ptr(u), len(el), _ptr(el, _i64p), _ptr(out))
+    return out
+
+
+def dg_batched(order, offsets, D_sets, u_packed, nmat=3):
+    """Mixed-order forward.  D_sets: dict p -> [nmat][(p+1)^3][(p+1)^3]."""
+    order = np.ascontiguousarray(order, dtype=np.int8)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    nelem = len(order)
+    flat, doff = [], np.zeros(9, dtype=np.int64)
+    pos = 0
+    for p in range(0, 9):
+        doff[p] = pos
+        if p in D_sets:
+            a = _f64(D_sets[p]).ravel()
+            flat.append(a)
+            pos += a.size
+    flat = np.ascontiguousarray(np.concatenate(flat)) if flat else np.zeros(1)
+    u = _f64(u_packed)
+    out = np.empty(nmat * int(off[-1]), dtype=np.float64)
+    lib().orc_dg_batched(nmat, nelem, _ptr(order, _i8p), _ptr(off, _i64p), _ptr(flat),
+                         _ptr(doff, _i64p), _ptr(u), _ptr(out))
+    return out.reshape(nmat, -1)
+
+
+def dg_adjoint(D, u, g, want_u=True, want_D=True):
+    """(grad_u, grad_D) of L = <g, dg_forward(D, u)>  (FP64)."""
+    D, u, g = _f64(D), _f64(u), _f64(g)
+    nmat, nunit, _ = D.shape
+    nelem = u.shape[0]
+    assert g.shape == (nmat, nelem, nunit)
+    gu = np.empty((nelem, nunit)) if want_u else None
+    gD = np.empty((nmat, nunit, nunit)) if want_D else None
+    lib().orc_dg_adjoint(nmat, nelem, nunit, _ptr(D), _ptr(u), _ptr(g),
+                         gu.ctypes.data if gu is not None else None,
+                         gD.ctypes.data if gD is not None else None)
+    return gu, gD
+
+
+# ------------------------------------------------------------------ companions
+
+def stencil5(u):
+    """res[i][j] of the five-point stencil for an (n+2)x(n+2) input."""
+    u = _f64(u)
+    n = u.shape[0] - 2
+    assert u.shape[1] >= n + 2
+    res = np.empty((n, n))
+    lib().orc_stencil5(n, _ptr(u), u.shape[1], _ptr(res), n)
+    return res
+
+
+def stencil5_select(u, ii, jj):
+    u = _f64(u)
+    n = u.shape[0] - 2
+    ii = np.ascontiguousarray(ii, dtype=np.int64)
+    jj = np.ascontiguousarray(jj, dtype=np.int64)
+    assert len(ii) == len(jj) and (ii.size == 0 or (ii.max() < n and jj.max() < n and min(ii.min(), jj.min()) >= 0))
+    out = np.empty(len(ii))
+    lib().orc_stencil5_select(n, _ptr(u), u.shape[1], len(ii), _ptr(ii, _i64p), _ptr(jj, _i64p), _ptr(out))
+    return out
+
+
+def matmul(a, b):
+    a, b = _f64(a), _f64(b)
+    n = a.shape[0]
+    assert a.shape == (n, n) and b.shape == (n, n)
+    c = np.empty((n, n))
+    lib().orc_matmul(n, _ptr(a), _ptr(b), _ptr(c))
+    return c
+
+
+def matmul_select(a, b, ii, jj):
+    a, b = _f64(a), _f64(b)
+    n = a.shape[0]
+    ii = np.ascontiguousarray(ii, dtype=np.int64)
+    jj = np.ascontiguousarray(jj, dtype=np.int64)
+    out = np.empty(len(ii))
+    lib().orc_matmul_select(n, _ptr(a), _ptr(b), len(ii), _ptr(ii, _i64p), _ptr(jj, _i64p), _ptr(out))
+    return out
+
+
+# ------------------------------------------------------------------ encodings
+
+def bf16_encode(x: float) -> int:
+    return int(lib().orc_bf16_encode(float(x)))
+
+
+def bf16_decode(h: int) -> float:
+    return float(lib().orc_bf16_decode(int(h)))
+
+
+def e4m3_encode(x: float) -> int:
+    return int(lib().orc_e4m3_encode(float(x)))
+
+
+def e4m3_decode(c: int) -> float:
+    return float(lib().orc_e4m3_decode(int(c)))
+
+
+def pow2_scale(amax: float, fmax: float = 448.0) -> float:
+    return float(lib().orc_pow2_scale(float(amax), float(fmax)))
+
+
+def quantize(x, to: str, per_row: bool):
+    """Quantise an FP32 [rows][cols] matrix to 'bf16' or 'e4m3'.
+    Returns (codes, inv_scale) with inv_scale of length rows (per_row) or 1."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    rows, cols = x.shape
+    if to == "bf16":
+        q = np.empty((rows, cols), dtype=np.uint16)
+        t = 0
+    elif to == "e4m3":
+        q = np.empty((rows, cols), dtype=np.uint8)
+        t = 1
+    else:
+        raise ValueError(to)
+    inv = np.empty(rows if per_row else 1, dtype=np.float32)
+    lib().orc_quantize(t, rows, cols, int(per_row), _ptr(x, _fp), q.ctypes.data, _ptr(inv, _fp))
+    return q, inv
+
+
+def bf16_decode_array(q):
+    q = np.ascontiguousarray(q, dtype=np.uint16)
+    return (q.astype(np.uint32) << 16).view(np.float32)
+
+
+def e4m3_decode_array(q):
+    table = np.array([e4m3_decode(c) for c in range(256)], dtype=np.float64)
+    return table[np.asarray(q, dtype=np.uint8)]

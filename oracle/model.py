@@ -1,0 +1,67 @@
+"""Oracle for the paper's calibration and prediction steps (FP64, test only).
+
+Calibration (Section "Computing Model Parameters"): with feature rows f_k and
+measured times t_k, the parameters minimise the Euclidean norm of the residual
+t - g(p).  For the linear model g_k(p) = f_k . p the least-squares minimiser is
+reached exactly by a direct solve (the paper's Levenberg-Marquardt iteration
+converges to the same point for a linear g).  With relative scaling
+(the paper's ``scale_features_by_output``) every row is first divided by its
+t_k and the right-hand side becomes 1.
+
+Reading adopted where the paper is silent: the columns are equilibrated to unit
+2-norm before the solve, singular values below 1e-12 * sigma_max are treated as
+zero, and the minimum-norm solution is taken in the equilibrated coordinates;
+the parameters are then un-scaled.  A library SVD least-squares routine
+(numpy.linalg.lstsq) is the solve step.
+
+Prediction (Section "Predicting Cost"): t_hat = f . p for new feature rows.
+Error statistics: the mean absolute percentage error and the geometric mean of
+relative error (Section "Results").
+"""
+from __future__ import annotations
+
+import numpy as np
+
+RCOND = 1e-12
+
+
+def fit(F, t, relative: bool = True):
+    """Returns dict(p, resid, rank, cond, negative)."""
+    F = np.array(F, dtype=np.float64, copy=True)
+    t = np.array(t, dtype=np.float64, copy=True)
+    if F.ndim != 2 or F.shape[0] == 0 or F.shape[0] != t.shape[0]:
+        raise ValueError("bad shapes")
+    if not (np.all(np.isfinite(F)) and np.all(np.isfinite(t))):
+        raise ValueError("non-finite input")
+    if relative:
+        if np.any(t <= 0):
+            raise ValueError("relative fit needs t > 0")
+        A = F / t[:, None]
+        b = np.ones_like(t)
+    else:
+        A, b = F, t
+    norms = np.linalg.norm(A, axis=0)
+    scale = np.where(norms > 0, 1.0 / np.where(norms > 0, norms, 1.0), 0.0)
+    As = A * scale[None, :]
+    y, _, rank, sv = np.linalg.lstsq(As, b, rcond=RCOND)
+    p = y * scale
+    r = b - A @ p
+    nz = sv[sv > RCOND * sv[0]] if sv.size and sv[0] > 0 else sv[:0]
+    cond = float(nz[0] / nz[-1]) if nz.size else float("inf")
+    return {"p": p, "resid": float(np.linalg.norm(r)), "rank": int(rank), "cond": cond,
+            "negative": [int(k) for k in np.nonzero(p < 0)[0]]}
+
+
+def predict(F, p):
+    return np.asarray(F, dtype=np.float64) @ np.asarray(p, dtype=np.float64)
+
+
+def mape(pred, meas):
+    pred, meas = np.asarray(pred, np.float64), np.asarray(meas, np.float64)
+    return float(np.mean(np.abs(pred - meas) / meas))
+
+
+def geomean_rel_err(pred, meas, floor: float = 1e-6):
+    pred, meas = np.asarray(pred, np.float64), np.asarray(meas, np.float64)
+    r = np.maximum(np.abs(pred - meas) / meas, floor)
+    return float(np.exp(np.mean(np.log(r))))

@@ -1,0 +1,67 @@
+"""Pins of the oracle's least-squares calibration, prediction and error
+statistics (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import model as M
+
+
+def test_fit_recovers_consistent_parameters():
+    rng = np.random.default_rng(0)
+    F = rng.uniform(1.0, 10.0, size=(40, 6)) * np.array([1e9, 1e6, 1e3, 1.0, 1e-3, 1e7])
+    p_true = np.array([2e-12, 3e-9, 1e-6, 5e-3, 7.0, 4e-11])
+    t = F @ p_true
+    for rel in (True, False):
+        out = M.fit(F, t, relative=rel)
+        np.testing.assert_allclose(out["p"], p_true, rtol=1e-10)
+        assert out["rank"] == 6
+        assert out["resid"] < 1e-10 * (1 if rel else np.linalg.norm(t))
+        assert out["negative"] == []
+
+
+def test_fit_relative_is_row_scaled_least_squares():
+    """Relative fit minimises sum_k (1 - f_k.p / t_k)^2: check the normal
+    equations (gradient zero) at the solution of a noisy, full-rank system."""
+    rng = np.random.default_rng(1)
+    F = rng.uniform(1, 5, size=(30, 3))
+    t = F @ np.array([1.0, 2.0, 3.0]) * rng.uniform(0.9, 1.1, size=30)
+    p = M.fit(F, t, relative=True)["p"]
+    A = F / t[:, None]
+    grad = A.T @ (A @ p - 1.0)
+    assert np.max(np.abs(grad)) < 1e-10
+
+
+def test_fit_rank_deficient_min_norm():
+    """Duplicated column: the solution splits the weight evenly (min-norm in
+    the equilibrated coordinates) and the rank is reported."""
+    rng = np.random.default_rng(2)
+    a = rng.uniform(1, 2, size=20)
+    b = rng.uniform(1, 2, size=20)
+    F = np.stack([a, a, b], axis=1)
+    t = 4.0 * a + 1.0 * b
+    out = M.fit(F, t, relative=False)
+    assert out["rank"] == 2
+    np.testing.assert_allclose(out["p"], [2.0, 2.0, 1.0], rtol=1e-10)
+
+
+def test_fit_flags_negative_and_rejects_bad_input():
+    F = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    t = np.array([1.0, -0.5, 0.5])
+    assert M.fit(F, t, relative=False)["negative"] == [1]
+    with pytest.raises(ValueError):
+        M.fit(F, t, relative=True)            # t <= 0
+    with pytest.raises(ValueError):
+        M.fit(np.zeros((0, 2)), np.zeros(0))
+    with pytest.raises(ValueError):
+        M.fit(np.array([[np.nan, 1.0]]), np.array([1.0]))
+
+
+def test_predict_mape_geomean():
+    F = np.array([[1.0, 2.0], [3.0, 4.0]])
+    p = np.array([0.5, 0.25])
+    np.testing.assert_allclose(M.predict(F, p), [1.0, 2.5])
+    assert M.mape([1.1, 1.8], [1.0, 2.0]) == pytest.approx(0.1)
+    assert M.geomean_rel_err([1.1, 1.8], [1.0, 2.0]) == pytest.approx(0.1)
+    assert M.geomean_rel_err([1.0, 2.2], [1.0, 2.0]) == pytest.approx(math.sqrt(1e-6 * 0.1))
