@@ -1,0 +1,89 @@
+/*
+ * dgdiff.h — C ABI of libdgdiff.so: the DG differentiation kernel family of
+ * Stevens & Kloeckner, "A mechanism for balancing accuracy and scope in
+ * cross-machine black-box GPU performance modeling" (arXiv 1904.09538), its
+ * companion calibration kernels, and the paper's black-box performance model.
+ *
+ * Conventions for every entry point
+ *   - Array pointers are DEVICE pointers unless the comment says [host].
+ *   - Arrays are dense and row-major.  The caller owns every buffer; the
+ *     library never allocates or frees caller memory.
+ *   - Device calls are asynchronous and ordered on the given HIP stream
+ *     (0 = the null stream).  A device fault surfaces at the caller's next
+ *     synchronisation.
+ *   - Outputs are overwritten, never accumulated, and may not overlap any
+ *     input (DG_EINVAL).
+ *   - No exception crosses the ABI.  On failure the status is returned and a
+ *     message is available from dg_last_error() on the calling thread.
+ *   - All functions are reentrant.
+ */
+#ifndef DGDIFF_H
+#define DGDIFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* dg_stream_t; /* a hipStream_t */
+
+typedef enum {
+    DG_OK = 0,
+    DG_EINVAL = 1,        /* bad argument: negative size, NULL array, overlap, bad enum */
+    DG_EUNSUPPORTED = 2,  /* valid but not provided: nunit > 512, nmat > 8, dtype pair */
+    DG_EHIP = 3,          /* a HIP runtime call failed; see dg_last_error() */
+    DG_ENOMEM = 4
+} dg_status;
+
+typedef enum {
+    DG_F64 = 0,
+    DG_F32 = 1,
+    DG_BF16 = 2,
+    DG_FP8E4M3 = 3        /* OCP OFP8 E4M3FN: bias 7, max 448, no infinities */
+} dg_dtype;
+
+/* Launch shape of the DG kernels (all fields 0 = tuned default).
+     elems_per_wave  element columns owned by one wave per tile: 16 or 32
+                     (one or two 16-wide MFMA column blocks)
+     waves           waves (64 lanes each) per work-group: 1..8
+     groups_per_cu   resident work-groups per compute unit of the persistent
+                     grid; 0 = the occupancy maximum
+     d_panels        16-row panels of the operator stack staged in LDS at a
+                     time; 0 = as many as fit the LDS budget                 */
+typedef struct {
+    int32_t elems_per_wave;
+    int32_t waves;
+    int32_t groups_per_cu;
+    int32_t d_panels;
+} dg_tile;
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* dg_last_error(void);
+
+/* DG differentiation (Section "DG Differentiation" of the paper: the kernel
+   res[m,k,i] = sum_j diff_mat[m,i,j] * u[k,j] for nmatrices operators):
+
+       out[m][e][i] = inv_sD[m] * inv_su[e] * sum_{j<nunit} D[m][i][j] * u[e][j]
+
+   D    [nmat][nunit][nunit] of in_t   (operator stack)
+   u    [nelem][nunit]       of in_t   (element-major nodal data)
+   out  [nmat][nelem][nunit] of out_t  (one contiguous slab per operator)
+   inv_sD [nmat], inv_su [nelem] (FP32): inverse power-of-two scales of
+        quantised inputs; NULL means 1.  Required for DG_FP8E4M3 input, must
+        be NULL for FP32/FP64 input.
+   Supported (in_t, out_t): (F64,F64), (F32,F32), (BF16,F32), (FP8E4M3,F32).
+   Products are accumulated in out_t precision (FP32 for BF16 and FP8).
+   nelem == 0 returns DG_OK without a launch.  1 <= nunit <= 512,
+   1 <= nmat <= 8, else DG_EUNSUPPORTED.  tile may be NULL.               */
+dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nelem,
+                       int32_t nunit, const void* D, const void* u, void* out,
+                       const float* inv_sD, const float* inv_su,
+                       const dg_tile* tile, dg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGDIFF_H */

@@ -1,0 +1,120 @@
+"""ctypes binding of libdgdiff.so (argument marshalling only).
+
+Every computation behind these functions runs in the library's HIP kernels;
+this module only turns torch tensors into device pointers and sizes, passes
+torch's current HIP stream, and raises on a non-OK status.  If the built
+library is missing the import fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdgdiff.so")
+
+DG_OK, DG_EINVAL, DG_EUNSUPPORTED, DG_EHIP, DG_ENOMEM = range(5)
+DG_F64, DG_F32, DG_BF16, DG_FP8E4M3 = range(4)
+_STATUS = {0: "DG_OK", 1: "DG_EINVAL", 2: "DG_EUNSUPPORTED", 3: "DG_EHIP", 4: "DG_ENOMEM"}
+
+
+class DGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class dg_tile(ctypes.Structure):
+    _fields_ = [("elems_per_wave", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32), ("d_panels", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "(hipcc --offload-arch=gfx950) first")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+def _declare(L):
+    L.dg_last_error.restype = ctypes.c_char_p
+    L.dg_last_error.argtypes = []
+    L.dgdiff_apply.restype = _i32
+    L.dgdiff_apply.argtypes = [_i32, _i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp,
+                               ctypes.POINTER(dg_tile), _vp]
+
+
+def check(status: int):
+    if status != DG_OK:
+        raise DGError(status, lib().dg_last_error().decode())
+
+
+def _dtype_code(t: torch.dtype) -> int:
+    if t == torch.float64:
+        return DG_F64
+    if t == torch.float32:
+        return DG_F32
+    if t == torch.bfloat16:
+        return DG_BF16
+    if t == torch.float8_e4m3fn:
+        return DG_FP8E4M3
+    raise TypeError(f"unsupported dtype {t}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_tile(tile):
+    if tile is None:
+        return None
+    if isinstance(tile, dg_tile):
+        return ctypes.byref(tile)
+    t = dg_tile(*[int(tile.get(k, 0)) for k in ("elems_per_wave", "waves", "groups_per_cu", "d_panels")])
+    return ctypes.byref(t)
+
+
+def dgdiff_apply(D, u, out=None, inv_sD=None, inv_su=None, tile=None, out_dtype=None, stream=None):
+    """out[m][e][i] = inv_sD[m] inv_su[e] sum_j D[m][i][j] u[e][j] on the GPU.
+
+    D: [nmat][nunit][nunit], u: [nelem][nunit] (same dtype); returns out
+    [nmat][nelem][nunit] (FP32 for BF16/FP8 inputs)."""
+    nmat, nunit, nunit2 = D.shape
+    nelem = u.shape[0]
+    if nunit2 != nunit or u.shape[1:] != (nunit,):
+        raise ValueError("shape mismatch")
+    if D.dtype != u.dtype:
+        raise TypeError("D and u must share a dtype")
+    in_t = _dtype_code(u.dtype)
+    if out_dtype is None:
+        out_dtype = u.dtype if u.dtype in (torch.float32, torch.float64) else torch.float32
+    if out is None:
+        out = torch.empty((nmat, nelem, nunit), dtype=out_dtype, device=u.device)
+    check(lib().dgdiff_apply(in_t, _dtype_code(out.dtype), nmat, nelem, nunit, _ptr(D), _ptr(u),
+                             _ptr(out), _ptr(inv_sD), _ptr(inv_su), make_tile(tile), _stream(stream)))
+    return out

@@ -1,0 +1,82 @@
+// extern "C" entry points of libdgdiff: argument validation and dispatch.
+// Every device-side step runs in the library's own HIP kernels.
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace dg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+dg_status fail(dg_status st, const std::string& msg) {
+    set_error(msg);
+    return st;
+}
+
+dg_status hip_fail(hipError_t err, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(err));
+    return DG_EHIP;
+}
+
+dg_status current_device(DeviceInfo* out) {
+    static std::mutex mu;
+    static std::vector<DeviceInfo> cache;
+    int dev = -1;
+    DG_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    for (const DeviceInfo& d : cache)
+        if (d.device == dev) {
+            *out = d;
+            return DG_OK;
+        }
+    hipDeviceProp_t prop;
+    DG_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+    DeviceInfo d;
+    d.device = dev;
+    d.num_cu = prop.multiProcessorCount;
+    d.warp_size = prop.warpSize;
+    d.lds_per_block = prop.sharedMemPerBlock;
+    std::strncpy(d.arch, prop.gcnArchName, sizeof(d.arch) - 1);
+    if (d.warp_size != 64) return fail(DG_EUNSUPPORTED, "device is not wave64 (gfx950 expected)");
+    cache.push_back(d);
+    *out = d;
+    return DG_OK;
+}
+
+}  // namespace dg
+
+using namespace dg;
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_last_error.c_str(); }
+
+dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nelem, int32_t nunit,
+                       const void* D, const void* u, void* out, const float* inv_sD,
+                       const float* inv_su, const dg_tile* tile, dg_stream_t stream) {
+    set_error("");
+    if (in_t < DG_F64 || in_t > DG_FP8E4M3 || out_t < DG_F64 || out_t > DG_FP8E4M3)
+        return fail(DG_EINVAL, "dgdiff_apply: unknown dtype");
+    if (nelem < 0 || nmat < 1 || nunit < 1) return fail(DG_EINVAL, "dgdiff_apply: sizes must be positive");
+    if (nmat > 8 || nunit > 512) return fail(DG_EUNSUPPORTED, "dgdiff_apply: nmat <= 8 and nunit <= 512");
+    const bool fp = (in_t == DG_F32 && out_t == DG_F32) || (in_t == DG_F64 && out_t == DG_F64);
+    if (!fp) return fail(DG_EUNSUPPORTED, "dgdiff_apply: unsupported (in_t, out_t) pair");
+    if (inv_sD || inv_su) return fail(DG_EINVAL, "dgdiff_apply: scales are only for quantised input");
+    if (nelem == 0) return DG_OK;
+    if (!D || !u || !out) return fail(DG_EINVAL, "dgdiff_apply: NULL array");
+    const size_t es = dtype_size(in_t), os = dtype_size(out_t);
+    const size_t nD = (size_t)nmat * nunit * nunit * es;
+    const size_t nu = (size_t)nelem * nunit * es;
+    const size_t no = (size_t)nmat * nelem * nunit * os;
+    if (overlaps(out, no, D, nD) || overlaps(out, no, u, nu))
+        return fail(DG_EINVAL, "dgdiff_apply: out overlaps an input");
+    return launch_dg_forward_fp(in_t, nmat, nelem, nunit, D, u, out, tile,
+                                reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

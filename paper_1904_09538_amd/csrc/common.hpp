@@ -1,0 +1,67 @@
+// Shared host/device helpers of libdgdiff (internal; not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "../../include/dgdiff.h"
+
+namespace dg {
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const std::string& msg);
+dg_status fail(dg_status st, const std::string& msg);
+dg_status hip_fail(hipError_t err, const char* what);
+
+#define DG_HIP_CHECK(expr)                                   \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return ::dg::hip_fail(_e, #expr); \
+    } while (0)
+
+// ------------------------------------------------------------------ device info
+
+struct DeviceInfo {
+    int device = -1;
+    int num_cu = 0;
+    int warp_size = 64;
+    size_t lds_per_block = 0;
+    char arch[64] = {0};
+};
+
+// Properties of the current device (cached per device id).
+dg_status current_device(DeviceInfo* out);
+
+// True if [a, a+na) and [b, b+nb) overlap (byte ranges).
+inline bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b || na == 0 || nb == 0) return false;
+    uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+inline size_t dtype_size(dg_dtype t) {
+    switch (t) {
+        case DG_F64: return 8;
+        case DG_F32: return 4;
+        case DG_BF16: return 2;
+        case DG_FP8E4M3: return 1;
+    }
+    return 0;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// ------------------------------------------------------------------ launchers
+
+// DG forward, FP32 or FP64 in and out (T chosen by dtype).  Arguments already
+// validated; nelem > 0.
+dg_status launch_dg_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit,
+                               const void* D, const void* u, void* out,
+                               const dg_tile* tile, hipStream_t s);
+
+}  // namespace dg

@@ -1,0 +1,160 @@
+"""GPU parity of dgdiff_apply (FP32 / FP64) against the FP64 oracle.
+
+Tolerances (normwise max relative error): 1e-12 for FP64, 1e-5 for FP32.
+Inputs come from the seeded generators; FP32 runs feed the oracle the
+FP32-rounded values widened to FP64, so the error measures the kernel.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1904_09538_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_1904_09538_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def _dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda:0", dtype=dtype)
+
+
+def _run(ops, D, u, dtype, tile=None):
+    out = ops.dgdiff_apply(_dev(D, dtype), _dev(u, dtype), tile=tile)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+def _as(x, dtype):
+    return x.astype(np.float32).astype(np.float64) if dtype == torch.float32 else x
+
+
+def _check(orc, ops, D, u, dtype, tile=None):
+    D, u = _as(D, dtype), _as(u, dtype)
+    got = _run(ops, D, u, dtype, tile)
+    ref = orc.dg_forward(D, u)
+    from oracle.metrics import normwise_rel
+    err = normwise_rel(got, ref)
+    assert err <= TOL[dtype], f"normwise error {err:.3e}"
+    return err
+
+
+@pytest.mark.parametrize("dkind", ["gll", "random"])
+def test_fp64_hex_p3_4096_elements(orc, ops, dkind):
+    D = I.gll_dmats(3) if dkind == "gll" else I.random_dmats(64)
+    u = I.uniform_u(4096, 64)
+    _check(orc, ops, D, u, torch.float64)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("nunit", [1, 5, 8, 17, 27, 64, 100, 125, 216, 343, 512])
+def test_sweep_nunit_ragged(orc, ops, dtype, nunit):
+    for nmat, nelem in ((3, 300), (1, 33), (2, 1)):
+        D = I.random_dmats(nunit, nmat=nmat)
+        u = I.uniform_u(nelem, nunit)
+        _check(orc, ops, D, u, dtype)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_gll_operators_fp32(orc, ops, p):
+    D = I.gll_dmats(p)
+    u = I.uniform_u(1000, (p + 1) ** 3)
+    _check(orc, ops, D, u, torch.float32)
+
+
+@pytest.mark.parametrize("nunit", [64, 216])
+@pytest.mark.parametrize("tile", [dict(elems_per_wave=16), dict(elems_per_wave=32),
+                                  dict(waves=1), dict(waves=2, elems_per_wave=16),
+                                  dict(d_panels=1), dict(d_panels=3, waves=3),
+                                  dict(groups_per_cu=1)])
+def test_tile_variants(orc, ops, nunit, tile):
+    D = I.random_dmats(nunit)
+    u = I.uniform_u(777, nunit)
+    _check(orc, ops, D, u, torch.float32, tile=tile)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_integer_data_bit_exact(orc, ops, dtype):
+    rng = np.random.default_rng(12)
+    for nunit in (27, 64, 125):
+        D = rng.integers(-3, 4, size=(3, nunit, nunit)).astype(np.float64)
+        u = rng.integers(-7, 8, size=(150, nunit)).astype(np.float64)
+        got = _run(ops, D, u, dtype)
+        np.testing.assert_array_equal(got, orc.dg_forward(D, u))
+
+
+def test_deterministic_and_guard_band(ops):
+    nunit, nelem = 125, 1500
+    D = _dev(I.random_dmats(nunit), torch.float32)
+    u = _dev(I.uniform_u(nelem, nunit), torch.float32)
+    n = 3 * nelem * nunit
+    buf = torch.full((n + 2048,), 12345.0, device="cuda:0")
+    out = buf[1024:1024 + n].view(3, nelem, nunit)
+    ops.dgdiff_apply(D, u, out=out)
+    first = out.clone()
+    ops.dgdiff_apply(D, u, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(first, out)
+    assert torch.all(buf[:1024] == 12345.0) and torch.all(buf[1024 + n:] == 12345.0)
+
+
+def test_unaligned_pointers(orc, ops):
+    """Views that start one element into a buffer take the scalar path."""
+    nunit, nelem = 64, 200
+    D = I.random_dmats(nunit)
+    u = _as(I.uniform_u(nelem, nunit), torch.float32)
+    ub = torch.zeros(nelem * nunit + 1, device="cuda:0")
+    ub[1:] = _dev(u, torch.float32).reshape(-1)
+    uv = ub[1:].view(nelem, nunit)
+    ob = torch.zeros(3 * nelem * nunit + 1, device="cuda:0")
+    ov = ob[1:].view(3, nelem, nunit)
+    ops.dgdiff_apply(_dev(_as(D, torch.float32), torch.float32), uv, out=ov)
+    torch.cuda.synchronize()
+    from oracle.metrics import normwise_rel
+    assert normwise_rel(ov.double().cpu().numpy(), orc.dg_forward(_as(D, torch.float32), u)) <= 1e-5
+
+
+def test_nan_propagates_to_its_element_only(orc, ops):
+    nunit, nelem = 27, 64
+    D = I.random_dmats(nunit)
+    u = I.uniform_u(nelem, nunit)
+    u[5, 3] = np.nan
+    got = _run(ops, D, u, torch.float32)
+    assert np.all(np.isnan(got[:, 5, :]))
+    mask = np.ones(nelem, bool)
+    mask[5] = False
+    ref = orc.dg_forward(_as(D, torch.float32), _as(u, torch.float32))
+    from oracle.metrics import normwise_rel
+    assert normwise_rel(got[:, mask, :], ref[:, mask, :]) <= 1e-5
+
+
+def test_empty_is_noop(ops):
+    D = torch.zeros(3, 64, 64, device="cuda:0")
+    u = torch.zeros(0, 64, device="cuda:0")
+    out = ops.dgdiff_apply(D, u)
+    assert out.shape == (3, 0, 64)
+
+
+@pytest.mark.parametrize("nunit,nelem", [(64, 1 << 21), (216, 1 << 20)])
+def test_full_size_sampled(orc, ops, nunit, nelem):
+    """Full-size launch (the benchmark's configuration), checked on a seeded
+    sample of elements including the first and last 64."""
+    p = round(nunit ** (1 / 3)) - 1
+    D = _as(I.gll_dmats(p), torch.float32)
+    u32 = np.asarray(I.uniform_u(nelem, nunit), dtype=np.float32)
+    out = ops.dgdiff_apply(_dev(D, torch.float32), torch.from_numpy(u32).cuda())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(99)
+    sel = np.unique(np.concatenate([np.arange(64), np.arange(nelem - 64, nelem),
+                                    rng.integers(0, nelem, 1024)]))
+    ref = orc.dg_forward_select(D, u32.astype(np.float64), sel)        # [nsel][3][n]
+    got = out[:, torch.from_numpy(sel).cuda(), :].permute(1, 0, 2).double().cpu().numpy()
+    from oracle.metrics import normwise_rel
+    assert normwise_rel(got, ref) <= 1e-5
