@@ -45,19 +45,24 @@ typedef enum {
 } dg_dtype;
 
 /* Launch shape of the DG kernels (all fields 0 = tuned default).
-     elems_per_wave  element columns owned by one wave per tile: 16 or 32
-                     (one or two 16-wide MFMA column blocks)
-     waves           waves (64 lanes each) per work-group: 1..8
+     elems_per_wave  element columns owned by one wave per tile: 16, 32 or 64
+                     (1, 2 or 4 16-wide MFMA column blocks; 64 only while
+                     nunit <= 128 in FP32 / nunit <= 64 in FP64)
+     waves           waves (64 lanes each) per work-group: 1..4
      groups_per_cu   resident work-groups per compute unit of the persistent
                      grid; 0 = the occupancy maximum
      d_panels        16-row panels of the operator stack staged in LDS at a
-                     time; 0 = as many as fit the LDS budget                 */
+                     time; 0 = as many as fit the LDS budget
+     flags           DG_TILE_* bits                                          */
 typedef struct {
     int32_t elems_per_wave;
     int32_t waves;
     int32_t groups_per_cu;
     int32_t d_panels;
+    int32_t flags;
 } dg_tile;
+
+#define DG_TILE_NT_STORE 1  /* write outputs with non-temporal (streaming) stores */
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* dg_last_error(void);

@@ -28,7 +28,11 @@ class DGError(RuntimeError):
 
 class dg_tile(ctypes.Structure):
     _fields_ = [("elems_per_wave", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("groups_per_cu", ctypes.c_int32), ("d_panels", ctypes.c_int32)]
+                ("groups_per_cu", ctypes.c_int32), ("d_panels", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+DG_TILE_NT_STORE = 1
 
 
 _lib = None
@@ -95,7 +99,8 @@ def make_tile(tile):
         return None
     if isinstance(tile, dg_tile):
         return ctypes.byref(tile)
-    t = dg_tile(*[int(tile.get(k, 0)) for k in ("elems_per_wave", "waves", "groups_per_cu", "d_panels")])
+    t = dg_tile(*[int(tile.get(k, 0)) for k in ("elems_per_wave", "waves", "groups_per_cu",
+                                                 "d_panels", "flags")])
     return ctypes.byref(t)
 
 

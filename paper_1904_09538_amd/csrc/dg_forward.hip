@@ -24,13 +24,23 @@
 // matching row order, so either way a lane's four results are the consecutive
 // nodes i0+4g .. i0+4g+3.
 //
-// Operator staging.  The stack has nmat*ceil(nunit/16) panels of 16 rows.  If
-// they fit the LDS budget they are loaded once per persistent work-group;
-// otherwise they are streamed through LDS in groups of `panels_lds` for every
-// element tile (they stay hot in L2, 4 MB per XCD).
+// Operator residency.  The stack has nmat*ceil(nunit/16) panels of 16 rows.
+// They are split into `ngroups` groups of at most `ppg` panels, each small
+// enough for LDS; a work-group stages ONE group once and keeps it for its whole
+// life, computing only those output rows for every element tile it visits.
+// Operators are never re-staged inside the tile loop.
 //
-// Grid.  Persistent: min(#tiles, CUs * resident groups); work-group b takes
-// tiles b, b+grid, ...  Every wave owns 16*CB elements of a tile.
+// Grid (persistent, XCD-aware).  Work-groups are dispatched round-robin over
+// the 8 XCDs (block b lands on XCD b % 8).  Block b takes panel group
+// pg = (b/8) % ngroups and tile stream (b/8)/ngroups * 8 + b % 8, so the
+// ngroups blocks that need the same element tile sit on the same XCD and walk
+// the same tile sequence: the tile is fetched from HBM once and re-read from
+// that XCD's L2 by the other groups.
+//
+// Unaligned rows.  When nunit is not a multiple of the 16-byte vector (or u is
+// not 16-byte aligned) a wave copies its contiguous slab of element data into
+// a wave-private LDS area with aligned 16-byte loads and reads its fragments
+// from there.
 #include "common.hpp"
 
 namespace dg {
@@ -77,10 +87,17 @@ struct FwdArgs {
     int nunit;
     int mblk;          // 16-row panels per operator: ceil(nunit/16)
     int panels_total;  // nmat * mblk
-    int panels_lds;    // panels held in LDS at once
+    int ppg;           // panels per resident group
+    int ngroups;       // ceil(panels_total / ppg)
+    int nstreams;      // tile streams: 8 * (blocks per XCD per group)
     int vec_in;        // u rows may be read as 16-byte vectors
+    int u_aligned;     // u itself is 16-byte aligned
+    int use_slab;      // unaligned rows go through the wave-private LDS slab
     int vec_out;       // out rows may be written as 16-byte vectors
+    int nt_store;      // streaming (non-temporal) output stores
 };
+
+__device__ inline int round_up_dev(int x, int v) { return (x + v - 1) / v * v; }
 
 template <typename T, int KQ>
 __device__ inline void stage_panels(const T* __restrict__ D, T* dl, int p0, int np,
@@ -105,6 +122,47 @@ __device__ inline void stage_panels(const T* __restrict__ D, T* dl, int p0, int 
     }
 }
 
+// B fragments of one 16-element column block straight from global memory:
+// KQ contiguous nodes of the lane's element from node g*KQ; zero beyond nunit
+// or nelem.  Requires 16-byte aligned rows (vec_in).
+template <typename T, int KQ>
+__device__ inline void load_b_global(const T* __restrict__ u, int64_t e, int g, const FwdArgs& a,
+                                     T (&b)[KQ]) {
+    typedef typename Mma<T>::vec_t vec_t;
+    constexpr int V = Mma<T>::V;
+    const bool ev = e < a.nelem;
+    const T* src = u + (ev ? e : 0) * a.nunit + g * KQ;
+#pragma unroll
+    for (int s = 0; s < KQ; s += V) {
+        vec_t v = vec_t(T(0));
+        if (ev && g * KQ + s < a.nunit) v = *reinterpret_cast<const vec_t*>(src + s);
+#pragma unroll
+        for (int t = 0; t < V; ++t) b[s + t] = v[t];
+    }
+}
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Copy the wave's contiguous slab of nel elements (nel*nunit values starting
+// at element ew0, whose start is 16-byte aligned) into wave-private LDS.
+template <typename T>
+__device__ inline void stage_slab(const T* __restrict__ u, int64_t ew0, int nel, int nunit,
+                                  bool aligned, T* slab, int lane) {
+    typedef typename Mma<T>::vec_t vec_t;
+    constexpr int V = Mma<T>::V;
+    const int len = nel * nunit;
+    const T* src = u + ew0 * nunit;
+    // ew0 is a multiple of 16, so the slab starts 16-byte aligned iff u does
+    const int nvec = aligned ? len / V : 0;
+    for (int q = lane; q < nvec; q += 64)
+        reinterpret_cast<vec_t*>(slab)[q] = reinterpret_cast<const vec_t*>(src)[q];
+    for (int f = nvec * V + lane; f < len; f += 64) slab[f] = src[f];
+}
+
 template <typename T, int KQ, int CB>
 __global__ void __launch_bounds__(256) dg_fwd_kernel(FwdArgs a) {
     typedef typename Mma<T>::acc_t acc_t;
@@ -125,86 +183,96 @@ __global__ void __launch_bounds__(256) dg_fwd_kernel(FwdArgs a) {
     const int c = lane & 15;  // MFMA column: the element within a 16-block
     const int g = lane >> 4;  // MFMA k index: which quarter of the nodes
     const int nunit = a.nunit;
-    const bool resident = a.panels_lds >= a.panels_total;
 
-    if (resident) {
-        stage_panels<T, KQ>(D, dl, 0, a.panels_total, nunit, a.mblk);
-        __syncthreads();
-    }
+    // XCD-aware placement: see the file comment.
+    const int xcd = blockIdx.x & 7;
+    const int k = blockIdx.x >> 3;
+    const int pg = k % a.ngroups;
+    const int64_t stream = (int64_t)(k / a.ngroups) * 8 + xcd;
+    const int p_lo = pg * a.ppg;
+    const int np = min(a.ppg, a.panels_total - p_lo);
+
+    stage_panels<T, KQ>(D, dl, p_lo, np, nunit, a.mblk);
+    // wave-private slab for unaligned element rows, after the operator panels
+    T* slab = dl + (size_t)a.ppg * 16 * LD + (size_t)wave * round_up_dev(16 * CB * nunit, V);
+    __syncthreads();
 
     const int64_t tile_elems = (int64_t)nw * 16 * CB;
-    for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    for (int64_t tile = stream; tile < a.ntiles; tile += a.nstreams) {
         const int64_t e0 = tile * tile_elems + (int64_t)wave * 16 * CB;
+        if (e0 >= a.nelem) continue;  // whole wave past the end (no block-level sync below)
 
-        // B fragments: KQ contiguous nodes of this lane's element(s).
         T b[CB][KQ];
+        if (a.vec_in) {
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int64_t e = e0 + cb * 16 + c;
-            const bool ev = e < a.nelem;
-            const T* src = u + (ev ? e : 0) * nunit + g * KQ;
-            if (a.vec_in) {
+            for (int cb = 0; cb < CB; ++cb) load_b_global<T, KQ>(u, e0 + cb * 16 + c, g, a, b[cb]);
+        } else if (!a.use_slab) {
+            // unaligned rows too long for a wave slab: masked scalar loads
 #pragma unroll
-                for (int s = 0; s < KQ; s += V) {
-                    vec_t v = vec_t(T(0));
-                    if (ev && g * KQ + s < nunit) v = *reinterpret_cast<const vec_t*>(src + s);
-#pragma unroll
-                    for (int t = 0; t < V; ++t) b[cb][s + t] = v[t];
-                }
-            } else {
+            for (int cb = 0; cb < CB; ++cb) {
+                const int64_t e = e0 + cb * 16 + c;
+                const T* row = u + (e < a.nelem ? e : 0) * nunit + g * KQ;
 #pragma unroll
                 for (int s = 0; s < KQ; ++s)
-                    b[cb][s] = (ev && g * KQ + s < nunit) ? src[s] : T(0);
+                    b[cb][s] = (e < a.nelem && g * KQ + s < nunit) ? row[s] : T(0);
             }
+        } else {
+            const int nel = (int)min<int64_t>(16 * CB, a.nelem - e0);
+            stage_slab<T>(u, e0, nel, nunit, a.u_aligned, slab, lane);
+            wave_lds_sync();
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int el = cb * 16 + c;
+                const T* row = slab + el * nunit + g * KQ;
+#pragma unroll
+                for (int s = 0; s < KQ; ++s)
+                    b[cb][s] = (el < nel && g * KQ + s < nunit) ? row[s] : T(0);
+            }
+            wave_lds_sync();  // slab reads done before the next tile overwrites it
         }
 
-        for (int p0 = 0; p0 < a.panels_total; p0 += a.panels_lds) {
-            const int np = min(a.panels_lds, a.panels_total - p0);
-            if (!resident) {
-                __syncthreads();  // previous group fully consumed
-                stage_panels<T, KQ>(D, dl, p0, np, nunit, a.mblk);
-                __syncthreads();
+        for (int pp = 0; pp < np; ++pp) {
+            const int panel = p_lo + pp;
+            const int m = panel / a.mblk;
+            const int i0 = (panel % a.mblk) * 16;
+            acc_t acc[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[cb] = acc_t(T(0));
+            const T* arow = dl + (pp * 16 + c) * LD + g * KQ;
+#pragma unroll
+            for (int s = 0; s < KQ; s += V) {
+                const vec_t av = *reinterpret_cast<const vec_t*>(arow + s);
+#pragma unroll
+                for (int t = 0; t < V; ++t)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        acc[cb] = Mma<T>::step(av[t], b[cb][s + t], acc[cb]);
             }
-            for (int pp = 0; pp < np; ++pp) {
-                const int panel = p0 + pp;
-                const int m = panel / a.mblk;
-                const int i0 = (panel % a.mblk) * 16;
-                acc_t acc[CB];
+            // Lane holds the results for nodes i0+4g .. i0+4g+3 of element column c.
+            const int i = i0 + 4 * g;
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) acc[cb] = acc_t(T(0));
-                const T* arow = dl + (pp * 16 + c) * LD + g * KQ;
-#pragma unroll
-                for (int s = 0; s < KQ; s += V) {
-                    const vec_t av = *reinterpret_cast<const vec_t*>(arow + s);
-#pragma unroll
-                    for (int t = 0; t < V; ++t)
-#pragma unroll
-                        for (int cb = 0; cb < CB; ++cb)
-                            acc[cb] = Mma<T>::step(av[t], b[cb][s + t], acc[cb]);
-                }
-                // Lane holds C^T rows 4g..4g+3 (nodes i0+4g+r) of element column c.
-                const int i = i0 + 4 * g;
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    const int64_t e = e0 + cb * 16 + c;
-                    if (e >= a.nelem) continue;
-                    T* dst = out + ((int64_t)m * a.nelem + e) * nunit + i;
-                    if (a.vec_out) {
-                        if (i < nunit) {
-                            if constexpr (V == 4) {
+            for (int cb = 0; cb < CB; ++cb) {
+                const int64_t e = e0 + cb * 16 + c;
+                if (e >= a.nelem) continue;
+                T* dst = out + ((int64_t)m * a.nelem + e) * nunit + i;
+                if (a.vec_out) {
+                    if (i < nunit) {
+                        if constexpr (V == 4) {
+                            if (a.nt_store)
+                                __builtin_nontemporal_store(acc[cb], reinterpret_cast<f32x4*>(dst));
+                            else
                                 *reinterpret_cast<f32x4*>(dst) = acc[cb];
-                            } else {
-                                f64x2 lo = {acc[cb][0], acc[cb][1]};
-                                f64x2 hi = {acc[cb][2], acc[cb][3]};
-                                reinterpret_cast<f64x2*>(dst)[0] = lo;
-                                reinterpret_cast<f64x2*>(dst)[1] = hi;
-                            }
+                        } else {
+                            f64x2 lo = {acc[cb][0], acc[cb][1]};
+                            f64x2 hi = {acc[cb][2], acc[cb][3]};
+                            reinterpret_cast<f64x2*>(dst)[0] = lo;
+                            reinterpret_cast<f64x2*>(dst)[1] = hi;
                         }
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (i + r < nunit) dst[r] = acc[cb][r];
                     }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (i + r < nunit) dst[r] = acc[cb][r];
                 }
             }
         }
@@ -226,8 +294,10 @@ static const int kKQ[] = {
 
 template <typename T, int CB>
 fwd_fn pick_kernel(int kq) {
-#define X(k) \
-    if (kq == k) return dg_fwd_kernel<T, k, CB>;
+#define X(k)                                                   \
+    if constexpr (CB < 4 || k * sizeof(T) <= 32 * 4) {         \
+        if (kq == k) return dg_fwd_kernel<T, k, CB>;           \
+    }
     DG_KQ_LIST(X)
 #undef X
     return nullptr;
@@ -256,25 +326,51 @@ dg_status launch_t(int nmat, int64_t nelem, int nunit, const void* D, const void
     int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : 0;
     if (waves < 1 || waves > 4) return fail(DG_EINVAL, "tile.waves must be in 1..4");
     int cb;
-    if (epw == 0) cb = (kq * (int)sizeof(T) <= 64 * 4) ? 2 : 1;
+    const bool rows_aligned = (nunit % Mma<T>::V == 0) && (reinterpret_cast<uintptr_t>(u) % 16 == 0);
+    if (epw == 0) {
+        // measured defaults (FP32, 2^21 elements): aligned short rows favour one
+        // column block per wave (more waves in flight); otherwise more column
+        // blocks per wave, as registers allow
+        const int w = kq * (int)sizeof(T) / 4;  // KQ in 32-bit registers
+        if (rows_aligned && w <= 16) cb = 1;
+        else if (w <= 32) cb = 4;
+        else if (w <= 64) cb = 2;
+        else cb = 1;
+    }
     else if (epw == 16) cb = 1;
     else if (epw == 32) cb = 2;
-    else return fail(DG_EINVAL, "tile.elems_per_wave must be 16 or 32");
+    else if (epw == 64 && kq * (int)sizeof(T) <= 32 * 4) cb = 4;
+    else return fail(DG_EINVAL, "tile.elems_per_wave must be 16 or 32 (or 64 for nunit <= 128 in FP32)");
 
     const int mblk = (int)ceil_div(nunit, 16);
     const int panels_total = nmat * mblk;
     const size_t panel_bytes = (size_t)16 * (4 * kq + Mma<T>::V) * sizeof(T);
-    int panels_lds;
+    const bool vec_in = (nunit % Mma<T>::V == 0) && (reinterpret_cast<uintptr_t>(u) % 16 == 0);
+    size_t slab_bytes =
+        vec_in ? 0 : (size_t)waves * round_up(16 * cb * nunit, Mma<T>::V) * sizeof(T);
+    const bool use_slab = slab_bytes > 0 && slab_bytes + panel_bytes <= kLdsMax / 2;
+    if (!use_slab) slab_bytes = 0;
+    int ppg;
     if (tile && tile->d_panels > 0) {
-        panels_lds = std::min(tile->d_panels, panels_total);
+        ppg = std::min(tile->d_panels, panels_total);
     } else {
-        size_t budget = std::max(kLdsBudget, panel_bytes);
-        panels_lds = (int)std::min<size_t>(panels_total, budget / panel_bytes);
+        // Whole stack if it fits the default budget; else the fewest groups
+        // (balanced) whose panels fit the LDS next to the slabs.
+        const size_t budget = kLdsBudget > slab_bytes ? kLdsBudget - slab_bytes : 0;
+        if ((size_t)panels_total * panel_bytes <= budget) {
+            ppg = panels_total;
+        } else {
+            const size_t room = kLdsMax - slab_bytes;
+            const int fit = std::max<int>(1, (int)(room / panel_bytes));
+            const int groups = (int)ceil_div(panels_total, fit);
+            ppg = (int)ceil_div(panels_total, groups);
+        }
     }
-    const size_t smem = panels_lds * panel_bytes;
+    const int ngroups = (int)ceil_div(panels_total, ppg);
+    const size_t smem = (size_t)ppg * panel_bytes + slab_bytes;
     if (smem > kLdsMax) return fail(DG_EINVAL, "tile.d_panels exceeds the 160 KB LDS");
 
-    fwd_fn fn = (cb == 2) ? pick_kernel<T, 2>(kq) : pick_kernel<T, 1>(kq);
+    fwd_fn fn = (cb == 4) ? pick_kernel<T, 4>(kq) : (cb == 2) ? pick_kernel<T, 2>(kq) : pick_kernel<T, 1>(kq);
     if (!fn) return fail(DG_EUNSUPPORTED, "no DG kernel instance for this nunit");
     DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
@@ -288,7 +384,11 @@ dg_status launch_t(int nmat, int64_t nelem, int nunit, const void* D, const void
             &per_cu, reinterpret_cast<const void*>(fn), block, smem));
         if (per_cu < 1) per_cu = 1;
     }
-    const int64_t grid = std::min<int64_t>(ntiles, (int64_t)per_cu * dev.num_cu);
+    // blocks per XCD per group: fill the resident capacity, but no more
+    // streams than tiles.
+    const int64_t cap = std::max<int64_t>(1, (int64_t)per_cu * dev.num_cu / (8 * ngroups));
+    const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(ntiles, 8)));
+    const int64_t grid = 8 * ngroups * slots;
 
     FwdArgs a;
     a.D = D;
@@ -300,9 +400,14 @@ dg_status launch_t(int nmat, int64_t nelem, int nunit, const void* D, const void
     a.nunit = nunit;
     a.mblk = mblk;
     a.panels_total = panels_total;
-    a.panels_lds = panels_lds;
-    a.vec_in = (nunit % Mma<T>::V == 0) && (reinterpret_cast<uintptr_t>(u) % 16 == 0);
+    a.ppg = ppg;
+    a.ngroups = ngroups;
+    a.nstreams = (int)(8 * slots);
+    a.vec_in = vec_in;
+    a.u_aligned = reinterpret_cast<uintptr_t>(u) % 16 == 0;
+    a.use_slab = use_slab;
     a.vec_out = (nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    a.nt_store = (tile && (tile->flags & DG_TILE_NT_STORE)) ? 1 : 0;
     hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), smem, s, a);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;

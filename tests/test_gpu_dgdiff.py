@@ -73,8 +73,14 @@ def test_gll_operators_fp32(orc, ops, p):
 @pytest.mark.parametrize("tile", [dict(elems_per_wave=16), dict(elems_per_wave=32),
                                   dict(waves=1), dict(waves=2, elems_per_wave=16),
                                   dict(d_panels=1), dict(d_panels=3, waves=3),
-                                  dict(groups_per_cu=1)])
+                                  dict(groups_per_cu=1), dict(elems_per_wave=64, flags=1),
+                                  dict(flags=1)])
 def test_tile_variants(orc, ops, nunit, tile):
+    if tile.get("elems_per_wave") == 64 and nunit > 128:
+        with pytest.raises(ops.DGError):
+            ops.dgdiff_apply(_dev(I.random_dmats(nunit), torch.float32),
+                             _dev(I.uniform_u(8, nunit), torch.float32), tile=tile)
+        return
     D = I.random_dmats(nunit)
     u = I.uniform_u(777, nunit)
     _check(orc, ops, D, u, torch.float32, tile=tile)
