@@ -87,6 +87,25 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
                        const float* inv_sD, const float* inv_su,
                        const dg_tile* tile, dg_stream_t stream);
 
+/* Five-point stencil (Section "Finite Differences"):
+       res[i][j] = u[i][j+1] + u[i+1][j] - 4 u[i+1][j+1] + u[i+1][j+2] + u[i+2][j+1]
+   for 0 <= i, j < n.
+   u   [(n+2)][ld_u] of t, ld_u >= n+2 (the input grid with its one-point halo)
+   res [n][ld_res]   of t, ld_res >= n
+   t is DG_F32 or DG_F64.  The fast path needs FP32, n and both leading
+   dimensions multiples of 4 and 16-byte aligned arrays; any other layout takes
+   a slower scalar kernel with the same result.  n == 0 is a no-op.         */
+dg_status stencil5_apply(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,
+                         int64_t ld_res, dg_stream_t stream);
+
+/* Square matrix multiplication (Section "Kernel Creation and Transformation"):
+       c[i][j] = sum_k a[i][k] b[k][j],   a, b, c [n][n] row-major FP32.
+   t must be DG_F32 (DG_EUNSUPPORTED otherwise).  The fast path needs n a
+   multiple of 16 and 16-byte aligned arrays; other n run a masked variant
+   of the same kernel.  n == 0 is a no-op.                                  */
+dg_status matmul_apply(dg_dtype t, int64_t n, const void* a, const void* b, void* c,
+                       dg_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,6 +61,10 @@ def _declare(L):
     L.dgdiff_apply.restype = _i32
     L.dgdiff_apply.argtypes = [_i32, _i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp,
                                ctypes.POINTER(dg_tile), _vp]
+    L.stencil5_apply.restype = _i32
+    L.stencil5_apply.argtypes = [_i32, _i64, _vp, _i64, _vp, _i64, _vp]
+    L.matmul_apply.restype = _i32
+    L.matmul_apply.argtypes = [_i32, _i64, _vp, _vp, _vp, _vp]
 
 
 def check(status: int):
@@ -123,3 +127,32 @@ def dgdiff_apply(D, u, out=None, inv_sD=None, inv_su=None, tile=None, out_dtype=
     check(lib().dgdiff_apply(in_t, _dtype_code(out.dtype), nmat, nelem, nunit, _ptr(D), _ptr(u),
                              _ptr(out), _ptr(inv_sD), _ptr(inv_su), make_tile(tile), _stream(stream)))
     return out
+
+
+def stencil5_apply(u, res=None, n=None, stream=None):
+    """Five-point stencil of an (n+2) x ld_u grid (leading dimension = u.stride(0));
+    returns res [n][ld_res] (a fresh [n][n] tensor unless res is given)."""
+    if u.dim() != 2 or u.stride(1) != 1:
+        raise ValueError("u must be 2-D with unit column stride")
+    if n is None:
+        n = u.shape[0] - 2
+    if u.shape[0] < n + 2 or u.shape[1] < n + 2:
+        raise ValueError("u must hold (n+2) x (n+2) values")
+    if res is None:
+        res = torch.empty((n, n), dtype=u.dtype, device=u.device)
+    if res.dim() != 2 or res.stride(1) != 1 or res.shape[0] < n or res.shape[1] < n:
+        raise ValueError("res must be 2-D [>=n][>=n] with unit column stride")
+    check(lib().stencil5_apply(_dtype_code(u.dtype), n, ctypes.c_void_p(u.data_ptr()), u.stride(0),
+                               ctypes.c_void_p(res.data_ptr()), res.stride(0), _stream(stream)))
+    return res
+
+
+def matmul_apply(a, b, c=None, stream=None):
+    """c = a @ b for square FP32 matrices on the GPU."""
+    n = a.shape[0]
+    if a.shape != (n, n) or b.shape != (n, n):
+        raise ValueError("square matrices expected")
+    if c is None:
+        c = torch.empty((n, n), dtype=a.dtype, device=a.device)
+    check(lib().matmul_apply(_dtype_code(a.dtype), n, _ptr(a), _ptr(b), _ptr(c), _stream(stream)))
+    return c

@@ -79,4 +79,32 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
                                 reinterpret_cast<hipStream_t>(stream));
 }
 
+dg_status stencil5_apply(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,
+                         int64_t ld_res, dg_stream_t stream) {
+    set_error("");
+    if (t != DG_F32 && t != DG_F64) return fail(DG_EUNSUPPORTED, "stencil5_apply: FP32 or FP64 only");
+    if (n < 0) return fail(DG_EINVAL, "stencil5_apply: n must be >= 0");
+    if (n == 0) return DG_OK;
+    if (ld_u < n + 2 || ld_res < n) return fail(DG_EINVAL, "stencil5_apply: leading dimension too small");
+    if (!u || !res) return fail(DG_EINVAL, "stencil5_apply: NULL array");
+    const size_t es = dtype_size(t);
+    if (overlaps(res, (size_t)n * ld_res * es, u, (size_t)(n + 2) * ld_u * es))
+        return fail(DG_EINVAL, "stencil5_apply: res overlaps u");
+    return launch_stencil5(t, n, u, ld_u, res, ld_res, reinterpret_cast<hipStream_t>(stream));
+}
+
+dg_status matmul_apply(dg_dtype t, int64_t n, const void* a, const void* b, void* c,
+                       dg_stream_t stream) {
+    set_error("");
+    if (t != DG_F32) return fail(DG_EUNSUPPORTED, "matmul_apply: FP32 only");
+    if (n < 0) return fail(DG_EINVAL, "matmul_apply: n must be >= 0");
+    if (n == 0) return DG_OK;
+    if (n > (int64_t)1 << 20) return fail(DG_EUNSUPPORTED, "matmul_apply: n too large");
+    if (!a || !b || !c) return fail(DG_EINVAL, "matmul_apply: NULL array");
+    const size_t bytes = (size_t)n * n * 4;
+    if (overlaps(c, bytes, a, bytes) || overlaps(c, bytes, b, bytes))
+        return fail(DG_EINVAL, "matmul_apply: c overlaps an input");
+    return launch_matmul(n, a, b, c, reinterpret_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -53,8 +53,8 @@ inline size_t dtype_size(dg_dtype t) {
     return 0;
 }
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 // ------------------------------------------------------------------ launchers
 
@@ -63,5 +63,14 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 dg_status launch_dg_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit,
                                const void* D, const void* u, void* out,
                                const dg_tile* tile, hipStream_t s);
+
+dg_status launch_stencil5(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,
+                          int64_t ld_res, hipStream_t s);
+bool stencil5_vector_ok(dg_dtype t, int64_t n, const void* u, int64_t ld_u, const void* res,
+                        int64_t ld_res);
+int stencil5_rows_per_strip(int64_t n);
+
+dg_status launch_matmul(int64_t n, const void* a, const void* b, void* c, hipStream_t s);
+bool matmul_vector_ok(int64_t n, const void* a, const void* b, const void* c);
 
 }  // namespace dg

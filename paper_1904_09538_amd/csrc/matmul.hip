@@ -1,0 +1,161 @@
+// Square matrix multiplication c = a b, FP32, on v_mfma_f32_16x16x4 (the
+// paper's first example kernel, Section "Kernel Creation and Transformation").
+//
+// The matrix cores are fed the transposed product C^T = B^T A^T: the MFMA "A"
+// operand comes from the b tile and its "B" operand from the a tile, so that
+// the accumulator rows land on consecutive *columns* of c and every lane
+// writes four consecutive floats of one c row (a 16-byte store).
+//
+// Tiling.  A work-group of 4 waves owns a 128x128 block of c (2x2 waves of
+// 64x64 = 4x4 MFMA blocks each).  K advances in chunks of 16: the a chunk is
+// staged in LDS as [row][k] and the b chunk transposed as [col][k], so both
+// operands are read with 16-byte LDS loads (lane group g takes k = 4g..4g+3
+// of the chunk, k-step s = 0..3 — any order of the contraction is exact up to
+// rounding).  The next chunk is loaded from global memory into registers while
+// the current one is multiplied; LDS is double-buffered with one barrier per
+// chunk.
+#include "common.hpp"
+
+namespace dg {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128;    // block rows / cols
+constexpr int BK = 16;     // k chunk
+constexpr int LDK = BK + 4;  // LDS row stride (floats): 16-byte pad against bank conflicts
+
+template <bool VEC>
+__device__ inline void load_chunk(const float* __restrict__ a, const float* __restrict__ b,
+                                  int64_t n, int64_t row0, int64_t col0, int64_t k0, int t,
+                                  f32x4 (&ra)[2], f32x4 (&rb)[2]) {
+    // a: thread t loads row row0 + t/2, k = k0 + 8*(t%2) .. +7
+    const int64_t ar = row0 + (t >> 1);
+    const int64_t ak = k0 + 8 * (t & 1);
+    // b: thread t loads k = k0 + t/16, cols col0 + 8*(t%16) .. +7
+    const int64_t bk = k0 + (t >> 4);
+    const int64_t bc = col0 + 8 * (t & 15);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if constexpr (VEC) {
+            ra[h] = (ar < n) ? *reinterpret_cast<const f32x4*>(a + ar * n + ak + 4 * h)
+                             : f32x4{0.f, 0.f, 0.f, 0.f};
+            rb[h] = (bc + 4 * h < n) ? *reinterpret_cast<const f32x4*>(b + bk * n + bc + 4 * h)
+                                     : f32x4{0.f, 0.f, 0.f, 0.f};
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t kk = ak + 4 * h + q;
+                ra[h][q] = (ar < n && kk < n) ? a[ar * n + kk] : 0.f;
+                const int64_t cc = bc + 4 * h + q;
+                rb[h][q] = (bk < n && cc < n) ? b[bk * n + cc] : 0.f;
+            }
+        }
+    }
+}
+
+__device__ inline void store_chunk(float* As, float* Bt, int t, const f32x4 (&ra)[2],
+                                   const f32x4 (&rb)[2]) {
+    float* arow = As + (t >> 1) * LDK + 8 * (t & 1);
+    reinterpret_cast<f32x4*>(arow)[0] = ra[0];
+    reinterpret_cast<f32x4*>(arow)[1] = ra[1];
+    const int k = t >> 4;
+    const int c0 = 8 * (t & 15);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Bt[(c0 + 4 * h + q) * LDK + k] = rb[h][q];
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(256) matmul_kernel(const float* __restrict__ a,
+                                                     const float* __restrict__ b,
+                                                     float* __restrict__ c, int64_t n) {
+    __shared__ __attribute__((aligned(16))) float lds[2][2][BM * LDK];  // [buf][a|bt]
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int cl = lane & 15;
+    const int g = lane >> 4;
+    const int wr = wave >> 1;  // wave row (64 rows of c)
+    const int wc = wave & 1;   // wave col (64 cols of c)
+    const int64_t row0 = (int64_t)blockIdx.y * BM;
+    const int64_t col0 = (int64_t)blockIdx.x * BM;
+    const int64_t nk = ceil_div(n, BK);
+
+    f32x4 acc[4][4];  // [row block][col block]
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    f32x4 ra[2], rb[2];
+    load_chunk<VEC>(a, b, n, row0, col0, 0, t, ra, rb);
+    store_chunk(lds[0][0], lds[0][1], t, ra, rb);
+    __syncthreads();
+
+    for (int64_t kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nk) load_chunk<VEC>(a, b, n, row0, col0, (kc + 1) * BK, t, ra, rb);
+        const float* As = lds[buf][0];
+        const float* Bt = lds[buf][1];
+        f32x4 av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            av[i] = *reinterpret_cast<const f32x4*>(As + (wr * 64 + i * 16 + cl) * LDK + 4 * g);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bv[j] = *reinterpret_cast<const f32x4*>(Bt + (wc * 64 + j * 16 + cl) * LDK + 4 * g);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j][s], av[i][s], acc[i][j],
+                                                                     0, 0, 0);
+        if (kc + 1 < nk) store_chunk(lds[buf ^ 1][0], lds[buf ^ 1][1], t, ra, rb);
+        __syncthreads();
+    }
+
+    // lane holds c[row][col .. col+3] with row = .. + cl, col = .. + 4g
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t r = row0 + wr * 64 + i * 16 + cl;
+        if (r >= n) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t col = col0 + wc * 64 + j * 16 + 4 * g;
+            if constexpr (VEC) {
+                if (col < n) *reinterpret_cast<f32x4*>(c + r * n + col) = acc[i][j];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (col + q < n) c[r * n + col + q] = acc[i][j][q];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+bool matmul_vector_ok(int64_t n, const void* a, const void* b, const void* c) {
+    return n % BK == 0 && reinterpret_cast<uintptr_t>(a) % 16 == 0 &&
+           reinterpret_cast<uintptr_t>(b) % 16 == 0 && reinterpret_cast<uintptr_t>(c) % 16 == 0;
+}
+
+dg_status launch_matmul(int64_t n, const void* a, const void* b, void* c, hipStream_t s) {
+    dim3 grid((unsigned)ceil_div(n, BM), (unsigned)ceil_div(n, BM));
+    if (matmul_vector_ok(n, a, b, c))
+        hipLaunchKernelGGL(matmul_kernel<true>, grid, dim3(256), 0, s,
+                           static_cast<const float*>(a), static_cast<const float*>(b),
+                           static_cast<float*>(c), n);
+    else
+        hipLaunchKernelGGL(matmul_kernel<false>, grid, dim3(256), 0, s,
+                           static_cast<const float*>(a), static_cast<const float*>(b),
+                           static_cast<float*>(c), n);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+}  // namespace dg

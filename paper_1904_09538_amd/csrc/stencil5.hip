@@ -1,0 +1,130 @@
+// Five-point stencil (paper, Section "Finite Differences"):
+//     res[i][j] = u[i][j+1] + u[i+1][j] - 4 u[i+1][j+1] + u[i+1][j+2] + u[i+2][j+1]
+// for 0 <= i, j < n; u has n+2 rows (leading dimension ld_u), res n rows.
+//
+// The operation moves ~8 bytes per 5 flops, so it is HBM-bound; the design
+// goal is one read of u and one write of res with full-width accesses.
+//
+// Vector path (FP32, n and both leading dimensions multiples of 4, 16-byte
+// aligned arrays).  A lane owns four consecutive output columns j0..j0+3 and
+// walks down a strip of R output rows keeping a sliding window of three u rows
+// in registers, so each u row of the strip is loaded once (strip overlap adds
+// 2/R).  Each u row is read as one 16-byte vector per lane; the two values to
+// the right of a lane's vector (columns j0+4, j0+5) are the first two values
+// of the next lane's vector and are taken with a wave shuffle — only the last
+// lane of a wave, or a lane whose right neighbour is past column n, loads them
+// itself.  A work-group is four waves side by side (1024 columns).
+//
+// Scalar path (any other layout, and FP64): one output per thread.
+#include "common.hpp"
+
+namespace dg {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct Row6 {
+    float v[6];
+};
+
+__device__ inline Row6 load_row6(const float* __restrict__ row, int64_t j0, bool active,
+                                 bool self_halo) {
+    Row6 r;
+    f32x4 q = {0.f, 0.f, 0.f, 0.f};
+    if (active) q = *reinterpret_cast<const f32x4*>(row + j0);
+    r.v[0] = q[0];
+    r.v[1] = q[1];
+    r.v[2] = q[2];
+    r.v[3] = q[3];
+    // columns j0+4, j0+5 live in the next lane's vector
+    float h0 = __shfl_down(q[0], 1, 64);
+    float h1 = __shfl_down(q[1], 1, 64);
+    if (active && self_halo) {
+        h0 = row[j0 + 4];
+        h1 = row[j0 + 5];
+    }
+    r.v[4] = h0;
+    r.v[5] = h1;
+    return r;
+}
+
+__global__ void __launch_bounds__(256) stencil5_vec_kernel(const float* __restrict__ u, int64_t ld_u,
+                                                           float* __restrict__ res, int64_t ld_res,
+                                                           int64_t n, int rows_per_strip) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * 256 + 4 * lane;
+    const bool active = j0 < n;
+    // the right neighbour's vector is missing for the wave's last lane and
+    // for the last active lane at the right edge of the grid
+    const bool self_halo = (lane == 63) || (j0 + 4 >= n);
+    const int64_t i_lo = (int64_t)blockIdx.y * rows_per_strip;
+    const int64_t i_hi = min<int64_t>(n, i_lo + rows_per_strip);
+    if (i_lo >= n) return;
+
+    Row6 top = load_row6(u + i_lo * ld_u, j0, active, self_halo);
+    Row6 mid = load_row6(u + (i_lo + 1) * ld_u, j0, active, self_halo);
+    for (int64_t i = i_lo; i < i_hi; ++i) {
+        Row6 bot = load_row6(u + (i + 2) * ld_u, j0, active, self_halo);
+        f32x4 o;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            o[k] = top.v[k + 1] + mid.v[k] - 4.0f * mid.v[k + 1] + mid.v[k + 2] + bot.v[k + 1];
+        if (active) __builtin_nontemporal_store(o, reinterpret_cast<f32x4*>(res + i * ld_res + j0));
+        top = mid;
+        mid = bot;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) stencil5_scalar_kernel(const T* __restrict__ u, int64_t ld_u,
+                                                              T* __restrict__ res, int64_t ld_res,
+                                                              int64_t n) {
+    const int64_t j = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int64_t i = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= n || j >= n) return;
+    const T* r0 = u + i * ld_u;
+    const T* r1 = r0 + ld_u;
+    const T* r2 = r1 + ld_u;
+    res[i * ld_res + j] = r0[j + 1] + r1[j] - T(4) * r1[j + 1] + r1[j + 2] + r2[j + 1];
+}
+
+}  // namespace
+
+int stencil5_rows_per_strip(int64_t n) {
+    if (n >= 8192) return 32;
+    if (n >= 4096) return 16;
+    if (n >= 2048) return 8;
+    return 4;
+}
+
+bool stencil5_vector_ok(dg_dtype t, int64_t n, const void* u, int64_t ld_u, const void* res,
+                        int64_t ld_res) {
+    return t == DG_F32 && n % 4 == 0 && ld_u % 4 == 0 && ld_res % 4 == 0 &&
+           reinterpret_cast<uintptr_t>(u) % 16 == 0 && reinterpret_cast<uintptr_t>(res) % 16 == 0;
+}
+
+dg_status launch_stencil5(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,
+                          int64_t ld_res, hipStream_t s) {
+    if (stencil5_vector_ok(t, n, u, ld_u, res, ld_res)) {
+        const int R = stencil5_rows_per_strip(n);
+        dim3 grid((unsigned)ceil_div(n, 1024), (unsigned)ceil_div(n, R));
+        hipLaunchKernelGGL(stencil5_vec_kernel, grid, dim3(256), 0, s,
+                           static_cast<const float*>(u), ld_u, static_cast<float*>(res), ld_res, n,
+                           R);
+    } else {
+        dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(n, 4));
+        if (t == DG_F32)
+            hipLaunchKernelGGL(stencil5_scalar_kernel<float>, grid, dim3(256), 0, s,
+                               static_cast<const float*>(u), ld_u, static_cast<float*>(res), ld_res,
+                               n);
+        else
+            hipLaunchKernelGGL(stencil5_scalar_kernel<double>, grid, dim3(256), 0, s,
+                               static_cast<const double*>(u), ld_u, static_cast<double*>(res),
+                               ld_res, n);
+    }
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+}  // namespace dg
