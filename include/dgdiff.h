@@ -62,7 +62,11 @@ typedef struct {
     int32_t flags;
 } dg_tile;
 
-#define DG_TILE_NT_STORE 1  /* write outputs with non-temporal (streaming) stores */
+#define DG_TILE_NT_STORE 1   /* write outputs with non-temporal (streaming) stores */
+#define DG_TILE_FP8_NATIVE 2 /* FP8 input: multiply on the native FP8 matrix instruction,
+                                whose internal 32-product sums are coarser than FP32
+                                (default: widen FP8 exactly to BF16 and use the BF16
+                                matrix cores, with true FP32 accumulation) */
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* dg_last_error(void);
@@ -86,6 +90,21 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
                        int32_t nunit, const void* D, const void* u, void* out,
                        const float* inv_sD, const float* inv_su,
                        const dg_tile* tile, dg_stream_t stream);
+
+/* Quantise an FP32 [rows][cols] array for the low-precision DG path.
+     to = DG_BF16:     q (uint16 [rows][cols]) = round-to-nearest-even BF16 of x;
+                       inv_scale, if not NULL, is filled with 1.
+     to = DG_FP8E4M3:  q (uint8 [rows][cols]) = RNE E4M3FN of x * s, with s the
+                       largest power of two such that amax * s <= 448 (amax
+                       over the row if per_row_scale, else over the whole
+                       array; s = 1 for amax 0 or not finite; s <= 2^127;
+                       NaN entries ignored for amax), magnitudes past 448
+                       saturate, NaN stays NaN; inv_scale [rows] (or [1])
+                       receives 1/s (required).
+   Used per operator (rows = nmat, cols = nunit^2) and per element
+   (rows = nelem, cols = nunit).  rows or cols == 0 is a no-op.             */
+dg_status dgdiff_quantize(dg_dtype to, int64_t rows, int64_t cols, int32_t per_row_scale,
+                          const float* x, void* q, float* inv_scale, dg_stream_t stream);
 
 /* Five-point stencil (Section "Finite Differences"):
        res[i][j] = u[i][j+1] + u[i+1][j] - 4 u[i+1][j+1] + u[i+1][j+2] + u[i+2][j+1]

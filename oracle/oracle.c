@@ -252,13 +252,15 @@ uint8_t orc_e4m3_encode(double x) {
 }
 
 /* Power-of-two scale that brings amax just inside the format maximum:
-   s = 2^floor(log2(fmax / amax)), s = 1 when amax is 0 (or not finite). */
+   s = 2^floor(log2(fmax / amax)), s = 1 when amax is 0 (or not finite); the
+   exponent is capped at 127 so that s stays a finite FP32 number. */
 double orc_pow2_scale(double amax, double fmax) {
     if (!(amax > 0.0) || isinf(amax)) return 1.0;
     double t = fmax / amax;
     int e;
     double f = frexp(t, &e);                /* t = f 2^e, f in [0.5,1): floor(log2 t) = e-1 */
     (void)f;
+    if (e - 1 > 127) return ldexp(1.0, 127);
     return ldexp(1.0, e - 1);
 }
 

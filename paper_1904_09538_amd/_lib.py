@@ -33,6 +33,7 @@ class dg_tile(ctypes.Structure):
 
 
 DG_TILE_NT_STORE = 1
+DG_TILE_FP8_NATIVE = 2
 
 
 _lib = None
@@ -61,6 +62,8 @@ def _declare(L):
     L.dgdiff_apply.restype = _i32
     L.dgdiff_apply.argtypes = [_i32, _i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp,
                                ctypes.POINTER(dg_tile), _vp]
+    L.dgdiff_quantize.restype = _i32
+    L.dgdiff_quantize.argtypes = [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp]
     L.stencil5_apply.restype = _i32
     L.stencil5_apply.argtypes = [_i32, _i64, _vp, _i64, _vp, _i64, _vp]
     L.matmul_apply.restype = _i32
@@ -156,3 +159,23 @@ def matmul_apply(a, b, c=None, stream=None):
         c = torch.empty((n, n), dtype=a.dtype, device=a.device)
     check(lib().matmul_apply(_dtype_code(a.dtype), n, _ptr(a), _ptr(b), _ptr(c), _stream(stream)))
     return c
+
+
+def dgdiff_quantize(x, to, per_row=True, stream=None):
+    """Quantise an FP32 [rows][cols] tensor to BF16 (torch.bfloat16) or FP8
+    E4M3FN (torch.float8_e4m3fn) with power-of-two scales; returns (q, inv_scale)."""
+    if x.dtype != torch.float32 or x.dim() != 2:
+        raise TypeError("x must be a 2-D float32 tensor")
+    rows, cols = x.shape
+    if to in ("bf16", torch.bfloat16):
+        q = torch.empty((rows, cols), dtype=torch.bfloat16, device=x.device)
+        code = DG_BF16
+    elif to in ("e4m3", "fp8", torch.float8_e4m3fn):
+        q = torch.empty((rows, cols), dtype=torch.float8_e4m3fn, device=x.device)
+        code = DG_FP8E4M3
+    else:
+        raise ValueError(to)
+    inv = torch.empty(rows if per_row else 1, dtype=torch.float32, device=x.device)
+    check(lib().dgdiff_quantize(code, rows, cols, int(per_row), _ptr(x), _ptr(q), _ptr(inv),
+                                _stream(stream)))
+    return q, inv

@@ -65,18 +65,42 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
     if (nelem < 0 || nmat < 1 || nunit < 1) return fail(DG_EINVAL, "dgdiff_apply: sizes must be positive");
     if (nmat > 8 || nunit > 512) return fail(DG_EUNSUPPORTED, "dgdiff_apply: nmat <= 8 and nunit <= 512");
     const bool fp = (in_t == DG_F32 && out_t == DG_F32) || (in_t == DG_F64 && out_t == DG_F64);
-    if (!fp) return fail(DG_EUNSUPPORTED, "dgdiff_apply: unsupported (in_t, out_t) pair");
-    if (inv_sD || inv_su) return fail(DG_EINVAL, "dgdiff_apply: scales are only for quantised input");
+    const bool lowp = (in_t == DG_BF16 || in_t == DG_FP8E4M3) && out_t == DG_F32;
+    if (!fp && !lowp) return fail(DG_EUNSUPPORTED, "dgdiff_apply: unsupported (in_t, out_t) pair");
+    if (fp && (inv_sD || inv_su)) return fail(DG_EINVAL, "dgdiff_apply: scales are only for quantised input");
+    if (in_t == DG_FP8E4M3 && (!inv_sD || !inv_su))
+        return fail(DG_EINVAL, "dgdiff_apply: FP8 input needs both inverse scale arrays");
     if (nelem == 0) return DG_OK;
     if (!D || !u || !out) return fail(DG_EINVAL, "dgdiff_apply: NULL array");
     const size_t es = dtype_size(in_t), os = dtype_size(out_t);
     const size_t nD = (size_t)nmat * nunit * nunit * es;
     const size_t nu = (size_t)nelem * nunit * es;
     const size_t no = (size_t)nmat * nelem * nunit * os;
-    if (overlaps(out, no, D, nD) || overlaps(out, no, u, nu))
+    if (overlaps(out, no, D, nD) || overlaps(out, no, u, nu) ||
+        overlaps(out, no, inv_sD, (size_t)nmat * 4) || overlaps(out, no, inv_su, (size_t)nelem * 4))
         return fail(DG_EINVAL, "dgdiff_apply: out overlaps an input");
+    if (lowp)
+        return launch_dg_forward_lowp(in_t, nmat, nelem, nunit, D, u, out, inv_sD, inv_su, tile,
+                                      reinterpret_cast<hipStream_t>(stream));
     return launch_dg_forward_fp(in_t, nmat, nelem, nunit, D, u, out, tile,
                                 reinterpret_cast<hipStream_t>(stream));
+}
+
+dg_status dgdiff_quantize(dg_dtype to, int64_t rows, int64_t cols, int32_t per_row_scale,
+                          const float* x, void* q, float* inv_scale, dg_stream_t stream) {
+    set_error("");
+    if (to != DG_BF16 && to != DG_FP8E4M3)
+        return fail(DG_EUNSUPPORTED, "dgdiff_quantize: target must be BF16 or FP8E4M3");
+    if (rows < 0 || cols < 0) return fail(DG_EINVAL, "dgdiff_quantize: negative size");
+    if (rows == 0 || cols == 0) return DG_OK;
+    if (!x || !q) return fail(DG_EINVAL, "dgdiff_quantize: NULL array");
+    if (to == DG_FP8E4M3 && !inv_scale) return fail(DG_EINVAL, "dgdiff_quantize: FP8 needs inv_scale");
+    const size_t nx = (size_t)rows * cols * 4, nq = (size_t)rows * cols * dtype_size(to);
+    const size_t ns = (size_t)(per_row_scale ? rows : 1) * 4;
+    if (overlaps(q, nq, x, nx) || overlaps(inv_scale, ns, x, nx) || overlaps(inv_scale, ns, q, nq))
+        return fail(DG_EINVAL, "dgdiff_quantize: outputs overlap");
+    return launch_quantize(to, rows, cols, per_row_scale ? 1 : 0, x, q, inv_scale,
+                           reinterpret_cast<hipStream_t>(stream));
 }
 
 dg_status stencil5_apply(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,

@@ -64,6 +64,13 @@ dg_status launch_dg_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit,
                                const void* D, const void* u, void* out,
                                const dg_tile* tile, hipStream_t s);
 
+dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nunit, const void* D,
+                                 const void* u, void* out, const float* inv_sD,
+                                 const float* inv_su, const dg_tile* tile, hipStream_t s);
+
+dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, const float* x,
+                          void* q, float* inv_scale, hipStream_t s);
+
 dg_status launch_stencil5(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,
                           int64_t ld_res, hipStream_t s);
 bool stencil5_vector_ok(dg_dtype t, int64_t n, const void* u, int64_t ld_u, const void* res,

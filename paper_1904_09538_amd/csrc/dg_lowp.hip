@@ -1,0 +1,334 @@
+// DG differentiation with BF16 or FP8-E4M3FN operands and FP32 accumulation:
+//     out[m][e][i] = inv_sD[m] * inv_su[e] * sum_j qD[m][i][j] * qu[e][j]
+// where qD, qu are the quantised operators and element data and inv_s* the
+// inverse power-of-two scales of the quantiser (exact de-scaling).
+//
+// Same scheme as the FP32/FP64 kernel (C^T = D_stack U^T on 16x16 MFMA tiles,
+// resident operator panel groups, XCD-aware tile streams), on
+// v_mfma_f32_16x16x32_bf16 (and, opt-in, v_mfma_f32_16x16x32_fp8_fp8): each
+// lane feeds eight consecutive nodes per k-step.  Lane group g owns nodes
+// [g*KQ, (g+1)*KQ) and k-step s covers g*KQ + 8s .. g*KQ + 8s + 7, so the
+// element data arrive as 16-byte (BF16) or 8-byte (FP8) vector loads and the
+// operator rows as LDS reads of the same width.  The 16x16 FP32 accumulator
+// layout is that of the FP32 instruction: lane group g holds rows 4g..4g+3.
+#include "common.hpp"
+
+namespace dg {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Operand formats.  G = element type in HBM, L = element type staged in LDS,
+// F = the 8-value MFMA operand fragment of one lane.
+//   0  BF16 in HBM, BF16 MFMA.
+//   1  FP8 in HBM, native FP8 MFMA (v_mfma_f32_16x16x32_fp8_fp8).  Measured on
+//      gfx950: the instruction's internal sum of its 32 products drops terms
+//      about 2^13 below the largest, short of FP32 accumulation, so this is
+//      opt-in (DG_TILE_FP8_NATIVE).
+//   2  FP8 in HBM, widened exactly to BF16 in registers / at LDS staging and
+//      multiplied on the BF16 matrix cores: FP8 bandwidth, exact products,
+//      FP32 accumulation.  Default for FP8 input.
+template <int FMT>
+struct LP;
+
+template <>
+struct LP<0> {
+    typedef uint16_t G;
+    typedef uint16_t L;
+    typedef u32x4 GF;  // 8 values as loaded from HBM
+    typedef u32x4 F;
+    __device__ static inline F widen(GF v) { return v; }
+    __device__ static inline L widen1(G v) { return v; }
+    __device__ static inline f32x4 mma(F a, F b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    }
+};
+
+template <>
+struct LP<1> {
+    typedef uint8_t G;
+    typedef uint8_t L;
+    typedef u32x2 GF;
+    typedef u32x2 F;
+    __device__ static inline F widen(GF v) { return v; }
+    __device__ static inline L widen1(G v) { return v; }
+    __device__ static inline f32x4 mma(F a, F b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a),
+                                                          __builtin_bit_cast(long, b), c, 0, 0, 0);
+    }
+};
+
+// Exact E4M3FN -> BF16: every E4M3 value (subnormals included) is a BF16 value.
+__device__ inline uint32_t e4m3_to_bf16_bits(uint32_t b) {
+    const uint32_t mag = b & 0x7Fu;
+    // normal: exponent+mantissa field moves up 4 bits, exponent rebias 127-7
+    const uint32_t norm = (mag << 4) + (120u << 7);
+    // subnormal (exponent field 0): M * 2^-9, exact in FP32, upper half is BF16
+    const uint32_t sub = __builtin_bit_cast(uint32_t, (float)mag * 0.001953125f) >> 16;
+    uint32_t r = mag >= 8u ? norm : sub;
+    if (mag == 0x7Fu) r = 0x7FC0u;  // NaN
+    return r | ((b & 0x80u) << 8);
+}
+
+template <>
+struct LP<2> {
+    typedef uint8_t G;
+    typedef uint16_t L;
+    typedef u32x2 GF;
+    typedef u32x4 F;
+    __device__ static inline F widen(GF v) {
+        F r;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t w = v[h];
+            r[2 * h] = e4m3_to_bf16_bits(w & 0xFFu) | (e4m3_to_bf16_bits((w >> 8) & 0xFFu) << 16);
+            r[2 * h + 1] =
+                e4m3_to_bf16_bits((w >> 16) & 0xFFu) | (e4m3_to_bf16_bits(w >> 24) << 16);
+        }
+        return r;
+    }
+    __device__ static inline L widen1(G v) { return (L)e4m3_to_bf16_bits(v); }
+    __device__ static inline f32x4 mma(F a, F b, f32x4 c) { return LP<0>::mma(a, b, c); }
+};
+
+struct LpArgs {
+    const void* D;
+    const void* u;
+    float* out;
+    const float* inv_sD;
+    const float* inv_su;
+    int64_t nelem;
+    int64_t ntiles;
+    int nunit;
+    int mblk;
+    int panels_total;
+    int ppg;
+    int ngroups;
+    int nstreams;
+    int vec_in;
+    int vec_out;
+};
+
+template <int FMT, int KS>
+__device__ inline void lp_stage_panels(const typename LP<FMT>::G* __restrict__ D,
+                                       typename LP<FMT>::L* dl, int p0, int np, int nunit,
+                                       int mblk) {
+    typedef typename LP<FMT>::L E;
+    constexpr int KP = 32 * KS;
+    constexpr int LDE = KP + 16 / (int)sizeof(E);
+    const int total = np * 16 * KP;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int j = idx % KP;
+        const int rr = idx / KP;
+        const int panel = p0 + rr / 16;
+        const int m = panel / mblk;
+        const int i = (panel % mblk) * 16 + (rr % 16);
+        E v = 0;
+        if (i < nunit && j < nunit) v = LP<FMT>::widen1(D[((int64_t)m * nunit + i) * nunit + j]);
+        dl[rr * LDE + j] = v;
+    }
+}
+
+template <int FMT, int KS>
+__device__ inline void lp_load_b(const typename LP<FMT>::G* __restrict__ u, int64_t e, int g,
+                                 const LpArgs& a, typename LP<FMT>::F (&b)[KS]) {
+    typedef typename LP<FMT>::G E;
+    typedef typename LP<FMT>::GF F;
+    constexpr int KQ = 8 * KS;
+    const bool ev = e < a.nelem;
+    const E* row = u + (ev ? e : 0) * a.nunit + g * KQ;
+    if (a.vec_in) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            F v = F(0u);
+            if (ev && g * KQ + 8 * s < a.nunit) v = *reinterpret_cast<const F*>(row + 8 * s);
+            b[s] = LP<FMT>::widen(v);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            E tmp[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                tmp[t] = (ev && g * KQ + 8 * s + t < a.nunit) ? row[8 * s + t] : E(0);
+            b[s] = LP<FMT>::widen(__builtin_bit_cast(F, tmp));
+        }
+    }
+}
+
+template <int FMT, int KS, int CB>
+__global__ void __launch_bounds__(256) dg_lowp_kernel(LpArgs a) {
+    typedef typename LP<FMT>::L E;
+    typedef typename LP<FMT>::G GE;
+    typedef typename LP<FMT>::F F;
+    constexpr int KQ = 8 * KS;
+    constexpr int KP = 4 * KQ;
+    constexpr int LDE = KP + 16 / (int)sizeof(E);
+
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    E* dl = reinterpret_cast<E*>(smem);
+    const GE* __restrict__ D = static_cast<const GE*>(a.D);
+    const GE* __restrict__ u = static_cast<const GE*>(a.u);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const int c = lane & 15;
+    const int g = lane >> 4;
+    const int nunit = a.nunit;
+
+    const int xcd = blockIdx.x & 7;
+    const int k = blockIdx.x >> 3;
+    const int pg = k % a.ngroups;
+    const int64_t stream = (int64_t)(k / a.ngroups) * 8 + xcd;
+    const int p_lo = pg * a.ppg;
+    const int np = min(a.ppg, a.panels_total - p_lo);
+    lp_stage_panels<FMT, KS>(D, dl, p_lo, np, nunit, a.mblk);
+    __syncthreads();
+
+    const int64_t tile_elems = (int64_t)nw * 16 * CB;
+    for (int64_t tile = stream; tile < a.ntiles; tile += a.nstreams) {
+        const int64_t e0 = tile * tile_elems + (int64_t)wave * 16 * CB;
+        if (e0 >= a.nelem) continue;
+        F b[CB][KS];
+        float esc[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int64_t e = e0 + cb * 16 + c;
+            lp_load_b<FMT, KS>(u, e, g, a, b[cb]);
+            esc[cb] = (a.inv_su && e < a.nelem) ? a.inv_su[e] : 1.0f;
+        }
+        for (int pp = 0; pp < np; ++pp) {
+            const int panel = p_lo + pp;
+            const int m = panel / a.mblk;
+            const int i0 = (panel % a.mblk) * 16;
+            f32x4 acc[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const E* arow = dl + (pp * 16 + c) * LDE + g * KQ;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const F av = *reinterpret_cast<const F*>(arow + 8 * s);
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) acc[cb] = LP<FMT>::mma(av, b[cb][s], acc[cb]);
+            }
+            const float msc = a.inv_sD ? a.inv_sD[m] : 1.0f;
+            const int i = i0 + 4 * g;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int64_t e = e0 + cb * 16 + c;
+                if (e >= a.nelem) continue;
+                const float sc = msc * esc[cb];  // product of powers of two: exact
+                const f32x4 v = acc[cb] * sc;
+                float* dst = a.out + ((int64_t)m * a.nelem + e) * nunit + i;
+                if (a.vec_out) {
+                    if (i < nunit) *reinterpret_cast<f32x4*>(dst) = v;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (i + r < nunit) dst[r] = v[r];
+                }
+            }
+        }
+    }
+}
+
+typedef void (*lp_fn)(LpArgs);
+
+template <int FMT, int CB>
+lp_fn pick_lp(int ks) {
+    switch (ks) {
+#define X(K) \
+    case K: return dg_lowp_kernel<FMT, K, CB>;
+        X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#undef X
+    }
+    return nullptr;
+}
+
+constexpr size_t kLpBudget = 80 * 1024;
+constexpr size_t kLpMax = 160 * 1024;
+
+}  // namespace
+
+dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nunit, const void* D,
+                                 const void* u, void* out, const float* inv_sD,
+                                 const float* inv_su, const dg_tile* tile, hipStream_t s) {
+    DeviceInfo dev;
+    dg_status st = current_device(&dev);
+    if (st != DG_OK) return st;
+    const bool native = tile && (tile->flags & DG_TILE_FP8_NATIVE);
+    const int fmt = (in_t == DG_BF16) ? 0 : native ? 1 : 2;
+    const size_t esz = fmt == 1 ? 1 : 2;  // LDS bytes per operator entry
+    const int ks = (int)ceil_div(nunit, 32);
+    if (ks > 16) return fail(DG_EUNSUPPORTED, "nunit too large");
+    int waves = (tile && tile->waves) ? tile->waves : 4;
+    if (waves < 1 || waves > 4) return fail(DG_EINVAL, "tile.waves must be in 1..4");
+    const int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : 32;
+    int cb;
+    if (epw == 16) cb = 1;
+    else if (epw == 32) cb = 2;
+    else if (epw == 64 && ks <= 8) cb = 4;
+    else return fail(DG_EINVAL, "tile.elems_per_wave must be 16, 32 (or 64 for nunit <= 256)");
+
+    const int mblk = (int)ceil_div(nunit, 16);
+    const int panels_total = nmat * mblk;
+    const size_t panel_bytes = (size_t)16 * (32 * ks * esz + 16);
+    int ppg;
+    if (tile && tile->d_panels > 0) {
+        ppg = std::min(tile->d_panels, panels_total);
+    } else if ((size_t)panels_total * panel_bytes <= kLpBudget) {
+        ppg = panels_total;
+    } else {
+        const int fit = std::max<int>(1, (int)(kLpMax / panel_bytes));
+        const int groups = (int)ceil_div(panels_total, fit);
+        ppg = (int)ceil_div(panels_total, groups);
+    }
+    const int ngroups = (int)ceil_div(panels_total, ppg);
+    const size_t smem = (size_t)ppg * panel_bytes;
+    if (smem > kLpMax) return fail(DG_EINVAL, "tile.d_panels exceeds the 160 KB LDS");
+
+    lp_fn fn;
+    if (fmt == 0) fn = cb == 4 ? pick_lp<0, 4>(ks) : cb == 2 ? pick_lp<0, 2>(ks) : pick_lp<0, 1>(ks);
+    else if (fmt == 1) fn = cb == 4 ? pick_lp<1, 4>(ks) : cb == 2 ? pick_lp<1, 2>(ks) : pick_lp<1, 1>(ks);
+    else fn = cb == 4 ? pick_lp<2, 4>(ks) : cb == 2 ? pick_lp<2, 2>(ks) : pick_lp<2, 1>(ks);
+    if (!fn) return fail(DG_EUNSUPPORTED, "no low-precision DG kernel instance");
+    DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    const int block = 64 * waves;
+    const int64_t ntiles = ceil_div(nelem, (int64_t)16 * cb * waves);
+    int per_cu = (tile && tile->groups_per_cu > 0) ? tile->groups_per_cu : 0;
+    if (per_cu == 0) {
+        DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(fn), block, smem));
+        if (per_cu < 1) per_cu = 1;
+    }
+    const int64_t cap = std::max<int64_t>(1, (int64_t)per_cu * dev.num_cu / (8 * ngroups));
+    const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(ntiles, 8)));
+
+    LpArgs a;
+    a.D = D;
+    a.u = u;
+    a.out = static_cast<float*>(out);
+    a.inv_sD = inv_sD;
+    a.inv_su = inv_su;
+    a.nelem = nelem;
+    a.ntiles = ntiles;
+    a.nunit = nunit;
+    a.mblk = mblk;
+    a.panels_total = panels_total;
+    a.ppg = ppg;
+    a.ngroups = ngroups;
+    a.nstreams = (int)(8 * slots);
+    a.vec_in = (nunit % 8 == 0) && (reinterpret_cast<uintptr_t>(u) % 16 == 0);  // 8 values / load
+    a.vec_out = (nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    hipLaunchKernelGGL(fn, dim3((unsigned)(8 * ngroups * slots)), dim3(block), smem, s, a);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+}  // namespace dg

@@ -1,0 +1,131 @@
+// Quantisation of FP32 operands for the low-precision DG path.
+//
+//   BF16:      q = RNE(x) to bfloat16 (upper half of the FP32 encoding), NaN kept
+//              quiet, overflow to infinity; inverse scales (if requested) are 1.
+//   FP8 E4M3:  q = RNE(x * s) to OCP E4M3FN (bias 7, max 448, no infinities),
+//              magnitudes past 448 saturate, NaN stays NaN; s is the largest
+//              power of two with amax * s <= 448 (s = 1 when amax is 0 or not
+//              finite; at most 2^127; NaN entries are ignored), chosen per row
+//              (per_row = 1) or for the whole array; inv_scale = 1/s.  Scaling by a power of two is exact, so the
+//              de-scaling in the DG epilogue is exact too.
+//
+// One wave per row: a max-reduction over the row (order-independent, exact),
+// then the encode pass.  The whole-array scale runs one wave over everything;
+// it is meant for small operator stacks.
+#include "common.hpp"
+
+namespace dg {
+namespace {
+
+__device__ inline uint32_t f32_bits(float f) { return __builtin_bit_cast(uint32_t, f); }
+
+__device__ inline uint16_t bf16_rne(float f) {
+    uint32_t b = f32_bits(f);
+    if ((b & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((b >> 16) | 0x40u);  // quiet NaN
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+// E4M3FN encode of an FP32 value by its bit fields.
+__device__ inline uint8_t e4m3_rne(float f) {
+    const uint32_t b = f32_bits(f);
+    const uint8_t sign = (uint8_t)((b >> 24) & 0x80u);
+    const uint32_t a = b & 0x7FFFFFFFu;
+    if (a > 0x7F800000u) return sign | 0x7F;          // NaN
+    if (a >= 0x43E00000u) return sign | 0x7E;         // |f| >= 448 (incl. inf): saturate
+    const int e = (int)(a >> 23) - 127;               // unbiased exponent (normal FP32)
+    if (e < -6) {
+        // E4M3 subnormal range: integer multiple of 2^-9, RNE by the hardware
+        // round-to-nearest-even of an exactly scaled value
+        const float m = __builtin_rintf(__builtin_bit_cast(float, a) * 512.0f);
+        return sign | (uint8_t)m;                     // m in 0..8; 8 is the smallest normal
+    }
+    // keep 3 of the 23 mantissa bits, ties to even; a carry bumps the exponent
+    uint32_t t = a + 0x7FFFFu + ((a >> 20) & 1u);
+    const uint32_t E = (t >> 23) - 127 + 7;
+    const uint32_t M = (t >> 20) & 7u;
+    uint32_t code = (E << 3) | M;
+    if (code > 0x7E) code = 0x7E;
+    return sign | (uint8_t)code;
+}
+
+// Exponent k of the largest power of two s = 2^k with amax * s <= 448, from
+// the exponent and mantissa of amax (exact; no division).  k <= 127.
+__device__ inline int pow2_scale_exp_448(float amax) {
+    const uint32_t a = f32_bits(amax) & 0x7FFFFFFFu;
+    if (a == 0 || a >= 0x7F800000u) return 0;
+    int E;
+    uint32_t mant;
+    if ((a >> 23) == 0) {  // FP32 subnormal amax: normalise
+        const int lz = __builtin_clz(a) - 8;
+        E = -126 - lz;
+        mant = (a << lz) & 0x7FFFFFu;
+    } else {
+        E = (int)(a >> 23) - 127;
+        mant = a & 0x7FFFFFu;
+    }
+    // amax = 1.mant * 2^E and 448 = 1.75 * 2^8 (0x600000 is the mantissa of 1.75)
+    const int k = (mant <= 0x600000u) ? 8 - E : 7 - E;
+    return k > 127 ? 127 : k;
+}
+
+// 2^k as an FP32 bit pattern, k in [-149, 127] (subnormal results built
+// directly, so no flush-to-zero can touch them).
+__device__ inline float exp2_bits(int k) {
+    if (k >= -126) return __builtin_bit_cast(float, (uint32_t)(k + 127) << 23);
+    return __builtin_bit_cast(float, 1u << (k + 149));
+}
+
+__device__ inline float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__global__ void __launch_bounds__(256) quantize_rows_kernel(int to_fp8, int64_t rows, int64_t cols,
+                                                           const float* __restrict__ x,
+                                                           void* __restrict__ q,
+                                                           float* __restrict__ inv_scale) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave; r < rows; r += nwaves) {
+        const float* xr = x + r * cols;
+        if (!to_fp8) {
+            uint16_t* qr = static_cast<uint16_t*>(q) + r * cols;
+            for (int64_t c = lane; c < cols; c += 64) qr[c] = bf16_rne(xr[c]);
+            if (inv_scale && lane == 0) inv_scale[r] = 1.0f;
+            continue;
+        }
+        float amax = 0.0f;
+        for (int64_t c = lane; c < cols; c += 64) {
+            const float v = fabsf(xr[c]);
+            amax = v > amax ? v : amax;   // NaN entries do not take part in the scale
+        }
+        amax = wave_max(amax);
+        const int ks = pow2_scale_exp_448(amax);
+        const float s = exp2_bits(ks);
+        uint8_t* qr = static_cast<uint8_t*>(q) + r * cols;
+        for (int64_t c = lane; c < cols; c += 64) qr[c] = e4m3_rne(xr[c] * s);
+        if (lane == 0) inv_scale[r] = exp2_bits(-ks);
+    }
+}
+
+}  // namespace
+
+dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, const float* x,
+                          void* q, float* inv_scale, hipStream_t s) {
+    if (!per_row) {
+        // one "row" covering everything
+        cols = rows * cols;
+        rows = 1;
+    }
+    const int64_t waves = std::min<int64_t>(rows, 65536);
+    const int64_t blocks = ceil_div(waves, 4);
+    hipLaunchKernelGGL(quantize_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                       to == DG_FP8E4M3 ? 1 : 0, rows, cols, x, q, inv_scale);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+}  // namespace dg

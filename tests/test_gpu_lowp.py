@@ -1,0 +1,195 @@
+"""GPU parity of the quantiser (bit-exact against the oracle's independent
+encoders) and of the BF16 / FP8-E4M3 DG path.
+
+Two error measures for the low-precision forward:
+  (i)  normwise, against the FP64 oracle on the unquantised FP32 inputs: the
+       accuracy of the method, bounded by 2e-2 (BF16) and 8e-2 (FP8);
+  (ii) against the FP64 oracle on the oracle's own dequantised inputs: the
+       kernel alone.  Products of BF16/FP8 values are exact in FP32, so what
+       remains is the FP32 accumulation; it is bounded elementwise by the
+       classical dot-product bound |y - y_ref| <= n 2^-23 sum_j |D_ij| |u_j|
+       (n = nunit; 2^-23 rather than 2^-24 allows the matrix core's internal
+       sums to truncate instead of rounding to nearest).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.metrics import normwise_rel
+from paper_1904_09538_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL_METHOD = {"bf16": 2e-2, "e4m3": 8e-2}
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_1904_09538_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def _q_gpu(ops, x32, to, per_row):
+    q, inv = ops.dgdiff_quantize(torch.from_numpy(x32).cuda(), to, per_row=per_row)
+    torch.cuda.synchronize()
+    codes = q.view(torch.int16 if to == "bf16" else torch.uint8).cpu().numpy()
+    return codes.view(np.uint16) if to == "bf16" else codes, inv.cpu().numpy()
+
+
+def _special_rows():
+    vals = np.array([0.0, -0.0, 1.0, -1.0, 448.0, 449.0, 464.0, 480.0, 1e30, -1e30, np.inf, -np.inf,
+                     np.nan, 2.0 ** -6, 2.0 ** -7, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -10, 1.0625,
+                     1.1875, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 3.4e38, 1e-38, 1e-45, 255.99, 0.1],
+                    dtype=np.float32)
+    return vals
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+@pytest.mark.parametrize("per_row", [True, False])
+def test_quantize_bit_exact(orc, ops, to, per_row):
+    rng = np.random.default_rng(21)
+    x = rng.uniform(-1, 1, size=(300, 216)).astype(np.float32)
+    x[7] *= 1e-3
+    x[8] *= 37.0
+    x[9] = 0.0
+    x[10, :len(_special_rows())] = _special_rows() if to == "bf16" else np.nan_to_num(_special_rows())
+    q, inv = _q_gpu(ops, x, to, per_row)
+    qo, invo = orc.quantize(x, to, per_row)
+    np.testing.assert_array_equal(q, qo)
+    if to == "e4m3" or per_row:
+        np.testing.assert_array_equal(inv, invo)
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+def test_quantize_random_bit_patterns(orc, ops, to):
+    """2^20 random FP32 bit patterns (all exponents, NaN, inf, subnormals)
+    in rows of 64: codes and scales bit-equal to the oracle."""
+    rng = np.random.default_rng(22)
+    bits = rng.integers(0, 2 ** 32, size=(1 << 14, 64), dtype=np.uint64).astype(np.uint32)
+    x = bits.view(np.float32)
+    q, inv = _q_gpu(ops, x, to, True)
+    qo, invo = orc.quantize(x, to, True)
+    np.testing.assert_array_equal(q, qo)
+    np.testing.assert_array_equal(inv.view(np.uint32), invo.view(np.uint32))
+
+
+def _dot_scaled(orc, got, ref, Dd, ud):
+    den = orc.dg_forward(np.abs(Dd), np.abs(ud))
+    return float(np.max(np.abs(got - ref) / np.maximum(den, 1e-300)))
+
+
+def _lowp_case(orc, ops, D64, u64, to):
+    D32, u32 = D64.astype(np.float32), u64.astype(np.float32)
+    nmat, n, _ = D32.shape
+    per_matrix = D32.reshape(nmat, n * n)
+    # GPU path: quantise on the GPU, multiply on the GPU
+    qD, isD = ops.dgdiff_quantize(torch.from_numpy(per_matrix).cuda(), to, per_row=True)
+    qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), to, per_row=True)
+    out = ops.dgdiff_apply(qD.view(nmat, n, n), qu, inv_sD=isD if to == "e4m3" else None,
+                           inv_su=isu if to == "e4m3" else None)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    # oracle path: its own quantiser and decoder, FP64 contraction
+    qDo, isDo = orc.quantize(per_matrix, to, True)
+    quo, isuo = orc.quantize(u32, to, True)
+    if to == "bf16":
+        Dd = orc.bf16_decode_array(qDo).astype(np.float64).reshape(nmat, n, n)
+        ud = orc.bf16_decode_array(quo).astype(np.float64)
+    else:
+        Dd = (orc.e4m3_decode_array(qDo) * isDo[:, None]).reshape(nmat, n, n)
+        ud = orc.e4m3_decode_array(quo) * isuo[:, None]
+    ref_kernel = orc.dg_forward(Dd, ud)
+    ref_method = orc.dg_forward(D32.astype(np.float64), u32.astype(np.float64))
+    return _dot_scaled(orc, got, ref_kernel, Dd, ud) / (n * 2.0 ** -23), normwise_rel(got, ref_method)
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+@pytest.mark.parametrize("nunit", [8, 27, 64, 100, 125, 216, 343])
+def test_lowp_forward(orc, ops, to, nunit):
+    p = round(nunit ** (1 / 3)) - 1
+    D = I.gll_dmats(p) if (p + 1) ** 3 == nunit else I.random_dmats(nunit)
+    u = I.uniform_u(300, nunit)
+    k_err, m_err = _lowp_case(orc, ops, D, u, to)
+    assert k_err <= 1.0, k_err          # fraction of the FP32 accumulation bound
+    assert m_err <= TOL_METHOD[to], m_err
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+def test_lowp_random_operators(orc, ops, to):
+    D = I.random_dmats(216)
+    u = I.uniform_u(500, 216)
+    k_err, m_err = _lowp_case(orc, ops, D, u, to)
+    assert k_err <= 1.0 and m_err <= TOL_METHOD[to]
+
+
+@pytest.mark.parametrize("tile", [dict(elems_per_wave=16), dict(elems_per_wave=64),
+                                  dict(d_panels=5), dict(waves=2)])
+def test_lowp_tiles(orc, ops, tile):
+    D32 = I.gll_dmats(3).astype(np.float32)
+    u32 = I.uniform_u(333, 64).astype(np.float32)
+    qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), "e4m3")
+    qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), "e4m3")
+    ref = ops.dgdiff_apply(qD.view(3, 64, 64), qu, inv_sD=isD, inv_su=isu)
+    got = ops.dgdiff_apply(qD.view(3, 64, 64), qu, inv_sD=isD, inv_su=isu, tile=tile)
+    torch.cuda.synchronize()
+    assert normwise_rel(got.double().cpu().numpy(), ref.double().cpu().numpy()) <= 1e-6
+
+
+def test_fp8_requires_scales(ops):
+    q = torch.zeros(3, 64, 64, dtype=torch.float8_e4m3fn, device="cuda:0")
+    u = torch.zeros(10, 64, dtype=torch.float8_e4m3fn, device="cuda:0")
+    with pytest.raises(ops.DGError):
+        ops.dgdiff_apply(q, u)
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+def test_lowp_full_size_sampled(orc, ops, to):
+    """Hex p=5, 2^20 elements: the low-precision benchmark configuration."""
+    n, E = 216, 1 << 20
+    D32 = I.gll_dmats(5).astype(np.float32)
+    u32 = np.asarray(I.uniform_u(E, n), dtype=np.float32)
+    qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), to)
+    qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), to)
+    out = ops.dgdiff_apply(qD.view(3, n, n), qu, inv_sD=isD if to == "e4m3" else None,
+                           inv_su=isu if to == "e4m3" else None)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(31)
+    sel = np.unique(np.concatenate([np.arange(32), np.arange(E - 32, E), rng.integers(0, E, 512)]))
+    got = out[:, torch.from_numpy(sel).cuda(), :].permute(1, 0, 2).double().cpu().numpy()
+    us = u32[sel]
+    qDo, isDo = orc.quantize(D32.reshape(3, -1), to, True)
+    quo, isuo = orc.quantize(us, to, True)
+    if to == "bf16":
+        Dd = orc.bf16_decode_array(qDo).astype(np.float64).reshape(3, n, n)
+        ud = orc.bf16_decode_array(quo).astype(np.float64)
+    else:
+        Dd = (orc.e4m3_decode_array(qDo) * isDo[:, None]).reshape(3, n, n)
+        ud = orc.e4m3_decode_array(quo) * isuo[:, None]
+    ref_k = orc.dg_forward(Dd, ud).transpose(1, 0, 2)
+    den = orc.dg_forward(np.abs(Dd), np.abs(ud)).transpose(1, 0, 2)
+    ref_m = orc.dg_forward(D32.astype(np.float64), us.astype(np.float64)).transpose(1, 0, 2)
+    assert np.max(np.abs(got - ref_k) / den) <= n * 2.0 ** -23
+    assert normwise_rel(got, ref_m) <= TOL_METHOD[to]
+
+
+def test_fp8_native_instruction_flag(orc, ops):
+    """The opt-in native FP8 matrix instruction: same method accuracy bound;
+    its internal 32-product sums are coarser than FP32, bounded here by
+    2^-12 of sum_j |D_ij| |u_j| (measured worst about 2^-12.8)."""
+    n = 216
+    D32 = I.gll_dmats(5).astype(np.float32)
+    u32 = I.uniform_u(400, n).astype(np.float32)
+    qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), "e4m3")
+    qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), "e4m3")
+    got = ops.dgdiff_apply(qD.view(3, n, n), qu, inv_sD=isD, inv_su=isu,
+                           tile=dict(flags=ops.DG_TILE_FP8_NATIVE))
+    torch.cuda.synchronize()
+    got = got.double().cpu().numpy()
+    qDo, isDo = orc.quantize(D32.reshape(3, -1), "e4m3", True)
+    quo, isuo = orc.quantize(u32, "e4m3", True)
+    Dd = (orc.e4m3_decode_array(qDo) * isDo[:, None]).reshape(3, n, n)
+    ud = orc.e4m3_decode_array(quo) * isuo[:, None]
+    assert _dot_scaled(orc, got, orc.dg_forward(Dd, ud), Dd, ud) <= 2.0 ** -12
+    ref_m = orc.dg_forward(D32.astype(np.float64), u32.astype(np.float64))
+    assert normwise_rel(got, ref_m) <= TOL_METHOD["e4m3"]
