@@ -91,6 +91,20 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
                        const float* inv_sD, const float* inv_su,
                        const dg_tile* tile, dg_stream_t stream);
 
+/* Adjoint of dgdiff_apply (not part of the paper; the addition that makes
+   the operator differentiable).  With g = dL/dout [nmat][nelem][nunit]:
+       grad_u[e][j]    = sum_m sum_i D[m][i][j] g[m][e][i]     [nelem][nunit]
+       grad_D[m][i][j] = sum_e g[m][e][i] u[e][j]               [nmat][nunit][nunit]
+   t is DG_F32 or DG_F64 (all arrays of t).  Either output may be NULL (not
+   computed).  grad_D is reduced over element splits into the caller's
+   workspace ws (>= dgdiff_backward_workspace(...) bytes; unused when grad_D
+   is NULL) and then summed in a fixed order: results are deterministic.
+   nelem == 0 gives grad_D = 0 and touches no workspace.                     */
+size_t dgdiff_backward_workspace(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit);
+dg_status dgdiff_backward(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit, const void* D,
+                          const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
+                          size_t ws_bytes, dg_stream_t stream);
+
 /* Quantise an FP32 [rows][cols] array for the low-precision DG path.
      to = DG_BF16:     q (uint16 [rows][cols]) = round-to-nearest-even BF16 of x;
                        inv_scale, if not NULL, is filled with 1.

@@ -48,6 +48,7 @@ def _declare(L):
     L.orc_dg_forward_select.argtypes = [_i32, _i32, _dp, _dp, _i64, _i64p, _dp]
     L.orc_dg_batched.argtypes = [_i32, _i64, _i8p, _i64p, _dp, _i64p, _dp, _dp]
     L.orc_dg_adjoint.argtypes = [_i32, _i64, _i32, _dp, _dp, _dp, ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_dg_adjoint_D_select.argtypes = [_i32, _i64, _i32, _dp, _dp, _i64, _i64p, _i64p, _i64p, _dp]
     L.orc_stencil5.argtypes = [_i64, _dp, _i64, _dp, _i64]
     L.orc_stencil5_select.argtypes = [_i64, _dp, _i64, _i64, _i64p, _i64p, _dp]
     L.orc_matmul.argtypes = [_i64, _dp, _dp, _dp]
@@ -133,6 +134,17 @@ def dg_adjoint(D, u, g, want_u=True, want_D=True):
                          gu.ctypes.data if gu is not None else None,
                          gD.ctypes.data if gD is not None else None)
     return gu, gD
+
+
+def dg_adjoint_D_select(u, g, mm, ii, jj):
+    """Listed entries of grad_D = sum_e g[m][e][i] u[e][j]."""
+    u, g = _f64(u), _f64(g)
+    nmat, nelem, nunit = g.shape
+    mm, ii, jj = (np.ascontiguousarray(x, dtype=np.int64) for x in (mm, ii, jj))
+    out = np.empty(len(mm))
+    lib().orc_dg_adjoint_D_select(nmat, nelem, nunit, _ptr(u), _ptr(g), len(mm), _ptr(mm, _i64p),
+                                  _ptr(ii, _i64p), _ptr(jj, _i64p), _ptr(out))
+    return out
 
 
 # ------------------------------------------------------------------ companions

@@ -113,6 +113,19 @@ void orc_dg_adjoint(int nmat, int64_t nelem, int nunit,
     }
 }
 
+/* grad_D entries (m, i, j) listed in mm/ii/jj: sum_e g[m][e][i] u[e][j]. */
+void orc_dg_adjoint_D_select(int nmat, int64_t nelem, int nunit, const double* u, const double* g,
+                             int64_t cnt, const int64_t* mm, const int64_t* ii, const int64_t* jj,
+                             double* out) {
+    (void)nmat;
+    for (int64_t s = 0; s < cnt; ++s) {
+        double acc = 0.0;
+        for (int64_t e = 0; e < nelem; ++e)
+            acc += g[(mm[s] * nelem + e) * nunit + ii[s]] * u[e * nunit + jj[s]];
+        out[s] = acc;
+    }
+}
+
 /* ---------------------------------------------------------------- stencil */
 
 /* res[i][j] = u[i][j+1] + u[i+1][j] - 4 u[i+1][j+1] + u[i+1][j+2] + u[i+2][j+1],

@@ -62,6 +62,11 @@ def _declare(L):
     L.dgdiff_apply.restype = _i32
     L.dgdiff_apply.argtypes = [_i32, _i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp,
                                ctypes.POINTER(dg_tile), _vp]
+    L.dgdiff_backward_workspace.restype = ctypes.c_size_t
+    L.dgdiff_backward_workspace.argtypes = [_i32, _i32, _i64, _i32]
+    L.dgdiff_backward.restype = _i32
+    L.dgdiff_backward.argtypes = [_i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  ctypes.c_size_t, _vp]
     L.dgdiff_quantize.restype = _i32
     L.dgdiff_quantize.argtypes = [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp]
     L.stencil5_apply.restype = _i32
@@ -179,3 +184,21 @@ def dgdiff_quantize(x, to, per_row=True, stream=None):
     check(lib().dgdiff_quantize(code, rows, cols, int(per_row), _ptr(x), _ptr(q), _ptr(inv),
                                 _stream(stream)))
     return q, inv
+
+
+def dgdiff_backward(D, u, g, want_u=True, want_D=True, stream=None):
+    """(grad_u, grad_D) of L with dL/dout = g, on the GPU (FP32 or FP64)."""
+    nmat, nunit, _ = D.shape
+    nelem = u.shape[0]
+    if g.shape != (nmat, nelem, nunit):
+        raise ValueError("g must be [nmat][nelem][nunit]")
+    if not (D.dtype == u.dtype == g.dtype):
+        raise TypeError("D, u, g must share a dtype")
+    t = _dtype_code(u.dtype)
+    gu = torch.empty_like(u) if want_u else None
+    gD = torch.empty_like(D) if want_D else None
+    nbytes = lib().dgdiff_backward_workspace(t, nmat, nelem, nunit) if want_D else 0
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=u.device) if nbytes else None
+    check(lib().dgdiff_backward(t, nmat, nelem, nunit, _ptr(D), _ptr(u), _ptr(g), _ptr(gu), _ptr(gD),
+                                _ptr(ws), nbytes, _stream(stream)))
+    return gu, gD

@@ -103,6 +103,40 @@ dg_status dgdiff_quantize(dg_dtype to, int64_t rows, int64_t cols, int32_t per_r
                            reinterpret_cast<hipStream_t>(stream));
 }
 
+size_t dgdiff_backward_workspace(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit) {
+    if ((t != DG_F32 && t != DG_F64) || nmat < 1 || nmat > 8 || nunit < 1 || nunit > 512 ||
+        nelem <= 0)
+        return 0;
+    return backward_workspace_bytes(t, nmat, nelem, nunit);
+}
+
+dg_status dgdiff_backward(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit, const void* D,
+                          const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
+                          size_t ws_bytes, dg_stream_t stream) {
+    set_error("");
+    if (t != DG_F32 && t != DG_F64) return fail(DG_EUNSUPPORTED, "dgdiff_backward: FP32 or FP64 only");
+    if (nelem < 0 || nmat < 1 || nunit < 1) return fail(DG_EINVAL, "dgdiff_backward: sizes must be positive");
+    if (nmat > 8 || nunit > 512) return fail(DG_EUNSUPPORTED, "dgdiff_backward: nmat <= 8 and nunit <= 512");
+    if (!grad_u && !grad_D) return DG_OK;
+    if (nelem > 0 && (!g || (grad_u && !D) || (grad_D && !u)))
+        return fail(DG_EINVAL, "dgdiff_backward: NULL input");
+    const size_t es = dtype_size(t);
+    const size_t nD = (size_t)nmat * nunit * nunit * es, nu = (size_t)nelem * nunit * es;
+    const size_t ng = (size_t)nmat * nelem * nunit * es;
+    if (grad_u && (overlaps(grad_u, nu, D, nD) || overlaps(grad_u, nu, u, nu) ||
+                   overlaps(grad_u, nu, g, ng) || overlaps(grad_u, nu, grad_D, nD) ||
+                   overlaps(grad_u, nu, ws, ws_bytes)))
+        return fail(DG_EINVAL, "dgdiff_backward: grad_u overlaps another array");
+    if (grad_D && (overlaps(grad_D, nD, D, nD) || overlaps(grad_D, nD, u, nu) ||
+                   overlaps(grad_D, nD, g, ng) || overlaps(grad_D, nD, ws, ws_bytes)))
+        return fail(DG_EINVAL, "dgdiff_backward: grad_D overlaps another array");
+    if (ws && (overlaps(ws, ws_bytes, D, nD) || overlaps(ws, ws_bytes, u, nu) ||
+               overlaps(ws, ws_bytes, g, ng)))
+        return fail(DG_EINVAL, "dgdiff_backward: workspace overlaps an input");
+    return launch_dg_backward(t, nmat, nelem, nunit, D, u, g, grad_u, grad_D, ws, ws_bytes,
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
 dg_status stencil5_apply(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,
                          int64_t ld_res, dg_stream_t stream) {
     set_error("");

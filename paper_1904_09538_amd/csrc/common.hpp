@@ -68,6 +68,11 @@ dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nun
                                  const void* u, void* out, const float* inv_sD,
                                  const float* inv_su, const dg_tile* tile, hipStream_t s);
 
+size_t backward_workspace_bytes(dg_dtype t, int nmat, int64_t nelem, int nunit);
+dg_status launch_dg_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D,
+                             const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
+                             size_t ws_bytes, hipStream_t s);
+
 dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, const float* x,
                           void* q, float* inv_scale, hipStream_t s);
 

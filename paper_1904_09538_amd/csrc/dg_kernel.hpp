@@ -1,0 +1,428 @@
+// The DG contraction kernel shared by the forward operator and the adjoint's
+// grad_u (FP32 and FP64, gfx950 matrix cores).
+//
+// Forward (paper, Section "DG Differentiation"):
+//     out[m][e][i] = sum_j D[m][i][j] * u[e][j].
+// Stacking the operators' rows, this is one tall-skinny GEMM
+//     C^T[(m,i)][e] = sum_j D[(m,i)][j] * U^T[j][e]
+// whose long dimension is the element count.  Adjoint, element part:
+//     grad_u[e][j] = sum_m sum_i D[m][i][j] * g[m][e][i],
+// the same shape with the operator transposed and a contraction index
+// (m, i) that runs over nmat "segments" of the B operand (the slabs g[m]).
+// One kernel serves both: a panel row is an output node, the contraction runs
+// over NSEG segments of KP nodes each, and the B operand of segment s is read
+// from src + s * seg_stride.
+//
+// MFMA mapping.  v_mfma_{f32,f64}_16x16x4: A = a 16-row panel of the
+// (possibly transposed) operator stack, B = the data of 16 elements, so each
+// lane's accumulator holds four output nodes of one element.  Lane group
+// g = lane/16 supplies the k index: group g owns nodes [g*KQ, (g+1)*KQ) of a
+// segment and k-step s contracts node g*KQ + s, so a lane reads KQ contiguous
+// values of its element (16-byte vector loads straight from HBM) and KQ
+// contiguous operator entries (16-byte LDS reads).  KP = 4*KQ >= nunit; the
+// zero padding lives in registers and LDS only.
+//
+// Row order.  The f32 instruction returns rows 4g..4g+3 to lane group g; the
+// f64 one returns rows g, g+4, g+8, g+12.  Panels are staged in the matching
+// row order, so a lane's four results are always the consecutive nodes
+// i0+4g .. i0+4g+3 (one 16-byte FP32 store).
+//
+// Operator residency.  The panels are split into `ngroups` groups of at most
+// `ppg` panels; a work-group stages ONE group in LDS once and keeps it for its
+// whole life, computing only those output rows for every element tile it
+// visits.  Nothing is re-staged inside the tile loop.
+//
+// Grid (persistent, XCD-aware).  Work-groups are dispatched round-robin over
+// the 8 XCDs (block b lands on XCD b % 8).  Block b takes panel group
+// pg = (b/8) % ngroups and tile stream (b/8)/ngroups * 8 + b % 8, so the
+// ngroups blocks that need the same element tile sit on the same XCD and walk
+// the same tile sequence: the tile is fetched from HBM once and re-read from
+// that XCD's L2 by the other groups.
+//
+// Unaligned rows.  When nunit is not a multiple of the 16-byte vector (or the
+// source is not 16-byte aligned) a wave copies its contiguous slab of element
+// data into a wave-private LDS area with aligned 16-byte loads and reads its
+// fragments from there (or, if the slab would not fit, uses masked scalar
+// loads).
+#pragma once
+
+#include "common.hpp"
+
+namespace dg {
+namespace kern {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Mma;
+
+template <>
+struct Mma<float> {
+    typedef f32x4 acc_t;
+    typedef f32x4 vec_t;  // one 16-byte vector
+    static constexpr int V = 4;
+    // accumulator register r of lane group g holds C row 4g + r
+    __device__ static inline int acc_row(int g, int r) { return 4 * g + r; }
+    __device__ static inline acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Mma<double> {
+    typedef f64x4 acc_t;
+    typedef f64x2 vec_t;
+    static constexpr int V = 2;
+    // accumulator register r of lane group g holds C row g + 4r (interleaved)
+    __device__ static inline int acc_row(int g, int r) { return g + 4 * r; }
+    __device__ static inline acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+struct KArgs {
+    const void* D;      // operator stack [nmat][nunit][nunit]
+    const void* src;    // B operand: segment s, element e at src + s*seg_stride + e*nunit
+    void* out;          // [out_slabs][nelem][nunit]
+    int64_t nelem;
+    int64_t ntiles;
+    int64_t seg_stride; // elements between B segments (0 when NSEG == 1)
+    int nunit;
+    int transpose;      // 0: panel rows (m, i), k = j;  1: panel rows j, k = (m, i)
+    int mblk;           // 16-row panels per output slab: ceil(nunit/16)
+    int panels_total;   // out_slabs * mblk
+    int ppg;            // panels per resident group
+    int ngroups;        // ceil(panels_total / ppg)
+    int nstreams;       // tile streams: 8 * (blocks per XCD per group)
+    int vec_in;         // B rows may be read as 16-byte vectors
+    int src_aligned;    // src itself is 16-byte aligned
+    int use_slab;       // unaligned rows go through the wave-private LDS slab
+    int vec_out;        // out rows may be written as 16-byte vectors
+    int nt_store;       // streaming (non-temporal) output stores
+};
+
+__device__ inline int round_up_dev(int x, int v) { return (x + v - 1) / v * v; }
+
+// Stage np panels starting at panel p0.  LDS row = output node, row stride
+// NSEG*KP + V; entry (row, s*KP + k) is the operator value multiplying
+// segment s, node k of the B operand.
+template <typename T, int KQ, int NSEG>
+__device__ inline void stage_panels(const T* __restrict__ D, T* dl, int p0, int np,
+                                    const KArgs& a) {
+    constexpr int KP = 4 * KQ;
+    constexpr int LD = NSEG * KP + Mma<T>::V;
+    const int nunit = a.nunit;
+    const int total = np * 16 * NSEG * KP;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int kk = idx % (NSEG * KP);
+        const int rr = idx / (NSEG * KP);  // output row within the staged group
+        const int s = kk / KP;
+        const int k = kk % KP;
+        const int rn = rr % 16;            // node offset 4g + r within its panel
+        const int panel = p0 + rr / 16;
+        const int slab = panel / a.mblk;
+        const int o = (panel % a.mblk) * 16 + rn;  // output node
+        T v = T(0);
+        if (o < nunit && k < nunit) {
+            // forward: D[slab][o][k];  transposed: D[s][k][o]
+            const int64_t idx_d = a.transpose ? ((int64_t)s * nunit + k) * nunit + o
+                                              : ((int64_t)slab * nunit + o) * nunit + k;
+            v = D[idx_d];
+        }
+        // Place node 4g + r at the panel row whose accumulator lands in
+        // register r of lane group g.
+        const int rho = Mma<T>::acc_row(rn >> 2, rn & 3);
+        dl[(rr - rn + rho) * LD + kk] = v;
+    }
+}
+
+// B fragments of one 16-element column block straight from global memory:
+// KQ contiguous nodes of the lane's element from node g*KQ; zero beyond nunit
+// or nelem.  Requires 16-byte aligned rows (vec_in).
+template <typename T, int KQ>
+__device__ inline void load_b_global(const T* __restrict__ src, int64_t e, int g, const KArgs& a,
+                                     T (&b)[KQ]) {
+    typedef typename Mma<T>::vec_t vec_t;
+    constexpr int V = Mma<T>::V;
+    const bool ev = e < a.nelem;
+    const T* row = src + (ev ? e : 0) * a.nunit + g * KQ;
+#pragma unroll
+    for (int s = 0; s < KQ; s += V) {
+        vec_t v = vec_t(T(0));
+        if (ev && g * KQ + s < a.nunit) v = *reinterpret_cast<const vec_t*>(row + s);
+#pragma unroll
+        for (int t = 0; t < V; ++t) b[s + t] = v[t];
+    }
+}
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Copy the wave's contiguous slab of nel elements (nel*nunit values starting
+// at element ew0) into wave-private LDS.
+template <typename T>
+__device__ inline void stage_slab(const T* __restrict__ src, int64_t ew0, int nel, int nunit,
+                                  bool aligned, T* slab, int lane) {
+    typedef typename Mma<T>::vec_t vec_t;
+    constexpr int V = Mma<T>::V;
+    const int len = nel * nunit;
+    const T* base = src + ew0 * nunit;
+    // ew0 is a multiple of 16, so the slab starts 16-byte aligned iff src does
+    const int nvec = aligned ? len / V : 0;
+    for (int q = lane; q < nvec; q += 64)
+        reinterpret_cast<vec_t*>(slab)[q] = reinterpret_cast<const vec_t*>(base)[q];
+    for (int f = nvec * V + lane; f < len; f += 64) slab[f] = base[f];
+}
+
+// ACC: out += result instead of out = result (a compile-time switch: as a
+// runtime branch it costs the FP32 kernels ~150 registers).
+template <typename T, int KQ, int CB, int NSEG, bool ACC = false>
+__global__ void __launch_bounds__(256) dg_kernel(KArgs a) {
+    typedef typename Mma<T>::acc_t acc_t;
+    typedef typename Mma<T>::vec_t vec_t;
+    constexpr int V = Mma<T>::V;
+    constexpr int KP = 4 * KQ;
+    constexpr int LD = NSEG * KP + V;  // one vector of row padding against bank conflicts
+
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    T* dl = reinterpret_cast<T*>(smem);
+    const T* __restrict__ D = static_cast<const T*>(a.D);
+    const T* __restrict__ src = static_cast<const T*>(a.src);
+    T* __restrict__ out = static_cast<T*>(a.out);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const int c = lane & 15;  // MFMA column: the element within a 16-block
+    const int g = lane >> 4;  // MFMA k index: which quarter of the nodes
+    const int nunit = a.nunit;
+
+    // XCD-aware placement: see the file comment.
+    const int xcd = blockIdx.x & 7;
+    const int kb = blockIdx.x >> 3;
+    const int pg = kb % a.ngroups;
+    const int64_t stream = (int64_t)(kb / a.ngroups) * 8 + xcd;
+    const int p_lo = pg * a.ppg;
+    const int np = min(a.ppg, a.panels_total - p_lo);
+
+    stage_panels<T, KQ, NSEG>(D, dl, p_lo, np, a);
+    // wave-private slab (all segments) for unaligned element rows
+    const int slab_seg = round_up_dev(16 * CB * nunit, V);
+    T* slab = dl + (size_t)a.ppg * 16 * LD + (size_t)wave * NSEG * slab_seg;
+    __syncthreads();
+
+    const int64_t tile_elems = (int64_t)nw * 16 * CB;
+    for (int64_t tile = stream; tile < a.ntiles; tile += a.nstreams) {
+        const int64_t e0 = tile * tile_elems + (int64_t)wave * 16 * CB;
+        if (e0 >= a.nelem) continue;  // whole wave past the end (no block-level sync below)
+
+        T b[NSEG][CB][KQ];
+        if (a.vec_in) {
+#pragma unroll
+            for (int s = 0; s < NSEG; ++s)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    load_b_global<T, KQ>(src + s * a.seg_stride, e0 + cb * 16 + c, g, a, b[s][cb]);
+        } else if (!a.use_slab) {
+            // unaligned rows too long for a wave slab: masked scalar loads
+#pragma unroll
+            for (int s = 0; s < NSEG; ++s)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const int64_t e = e0 + cb * 16 + c;
+                    const T* row = src + s * a.seg_stride + (e < a.nelem ? e : 0) * nunit + g * KQ;
+#pragma unroll
+                    for (int t = 0; t < KQ; ++t)
+                        b[s][cb][t] = (e < a.nelem && g * KQ + t < nunit) ? row[t] : T(0);
+                }
+        } else {
+            const int nel = (int)min<int64_t>(16 * CB, a.nelem - e0);
+#pragma unroll
+            for (int s = 0; s < NSEG; ++s)
+                stage_slab<T>(src + s * a.seg_stride, e0, nel, nunit, a.src_aligned,
+                              slab + s * slab_seg, lane);
+            wave_lds_sync();
+#pragma unroll
+            for (int s = 0; s < NSEG; ++s)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const int el = cb * 16 + c;
+                    const T* row = slab + s * slab_seg + el * nunit + g * KQ;
+#pragma unroll
+                    for (int t = 0; t < KQ; ++t)
+                        b[s][cb][t] = (el < nel && g * KQ + t < nunit) ? row[t] : T(0);
+                }
+            wave_lds_sync();  // slab reads done before the next tile overwrites it
+        }
+
+        for (int pp = 0; pp < np; ++pp) {
+            const int panel = p_lo + pp;
+            const int slab_o = panel / a.mblk;
+            const int i0 = (panel % a.mblk) * 16;
+            acc_t acc[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[cb] = acc_t(T(0));
+#pragma unroll
+            for (int s = 0; s < NSEG; ++s) {
+                const T* arow = dl + (pp * 16 + c) * LD + s * KP + g * KQ;
+#pragma unroll
+                for (int t = 0; t < KQ; t += V) {
+                    const vec_t av = *reinterpret_cast<const vec_t*>(arow + t);
+#pragma unroll
+                    for (int q = 0; q < V; ++q)
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb)
+                            acc[cb] = Mma<T>::step(av[q], b[s][cb][t + q], acc[cb]);
+                }
+            }
+            // Lane holds the results for nodes i0+4g .. i0+4g+3 of element column c.
+            const int i = i0 + 4 * g;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int64_t e = e0 + cb * 16 + c;
+                if (e >= a.nelem) continue;
+                T* dst = out + ((int64_t)slab_o * a.nelem + e) * nunit + i;
+                if constexpr (ACC) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (i + r < nunit) acc[cb][r] += dst[r];
+                }
+                if (a.vec_out) {
+                    if (i < nunit) {
+                        if constexpr (V == 4) {
+                            if (a.nt_store)
+                                __builtin_nontemporal_store(acc[cb], reinterpret_cast<f32x4*>(dst));
+                            else
+                                *reinterpret_cast<f32x4*>(dst) = acc[cb];
+                        } else {
+                            f64x2 lo = {acc[cb][0], acc[cb][1]};
+                            f64x2 hi = {acc[cb][2], acc[cb][3]};
+                            reinterpret_cast<f64x2*>(dst)[0] = lo;
+                            reinterpret_cast<f64x2*>(dst)[1] = hi;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (i + r < nunit) dst[r] = acc[cb][r];
+                }
+            }
+        }
+    }
+}
+
+typedef void (*kern_fn)(KArgs);
+
+// KQ values instantiated: every node count up to 512 is covered by the next
+// listed value (KQ >= ceil(nunit/4) rounded up to 4).
+#define DG_KQ_LIST(X) X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(40) X(48) X(56) X(64) \
+    X(72) X(80) X(88) X(96) X(112) X(128)
+
+inline int kq_for(int nunit) {
+    static const int kKQ[] = {
+#define X(k) k,
+        DG_KQ_LIST(X)
+#undef X
+    };
+    const int need = (int)round_up(ceil_div(nunit, 4), 4);
+    for (int k : kKQ)
+        if (k >= need) return k;
+    return -1;
+}
+
+// Register budget of the B fragments: CB*NSEG*KQ values of T per lane.
+template <typename T, int CB, int NSEG, int KQ>
+constexpr bool fits_registers() {
+    return CB * NSEG * KQ * sizeof(T) <= (NSEG == 1 ? 1024u : 768u);
+}
+
+template <typename T, int CB, int NSEG>
+kern_fn pick_kernel(int kq) {
+#define X(k)                                                            \
+    if constexpr (fits_registers<T, CB, NSEG, k>()) {                   \
+        if (kq == k) return dg_kernel<T, k, CB, NSEG>;                  \
+    }
+    DG_KQ_LIST(X)
+#undef X
+    return nullptr;
+}
+
+constexpr size_t kLdsBudget = 64 * 1024;  // default: whole stack if it fits here
+constexpr size_t kLdsMax = 160 * 1024;    // gfx950 LDS per CU
+
+// Plan and launch one contraction.  fn chooser: pick(cb) -> kernel.
+template <typename T, int NSEG, typename Pick>
+dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, int waves, Pick pick,
+                 hipStream_t s) {
+    DeviceInfo dev;
+    dg_status st = current_device(&dev);
+    if (st != DG_OK) return st;
+    const int nunit = a.nunit;
+    const int mblk = (int)ceil_div(nunit, 16);
+    const int panels_total = out_slabs * mblk;
+    const size_t panel_bytes = (size_t)16 * (NSEG * 4 * kq + Mma<T>::V) * sizeof(T);
+    const bool vec_in = (nunit % Mma<T>::V == 0) && (reinterpret_cast<uintptr_t>(a.src) % 16 == 0) &&
+                        (a.seg_stride % Mma<T>::V == 0);
+    size_t slab_bytes =
+        vec_in ? 0 : (size_t)waves * NSEG * round_up(16 * cb * nunit, Mma<T>::V) * sizeof(T);
+    const bool use_slab = slab_bytes > 0 && slab_bytes + panel_bytes <= kLdsMax / 2;
+    if (!use_slab) slab_bytes = 0;
+    int ppg;
+    if (tile && tile->d_panels > 0) {
+        ppg = std::min(tile->d_panels, panels_total);
+    } else {
+        const size_t budget = kLdsBudget > slab_bytes ? kLdsBudget - slab_bytes : 0;
+        if ((size_t)panels_total * panel_bytes <= budget) {
+            ppg = panels_total;
+        } else {
+            const size_t room = kLdsMax - slab_bytes;
+            const int fit = std::max<int>(1, (int)(room / panel_bytes));
+            const int groups = (int)ceil_div(panels_total, fit);
+            ppg = (int)ceil_div(panels_total, groups);
+        }
+    }
+    const int ngroups = (int)ceil_div(panels_total, ppg);
+    const size_t smem = (size_t)ppg * panel_bytes + slab_bytes;
+    if (smem > kLdsMax) return fail(DG_EINVAL, "tile.d_panels exceeds the 160 KB LDS");
+
+    kern_fn fn = pick(cb);
+    if (!fn) return fail(DG_EUNSUPPORTED, "no DG kernel instance for this shape");
+    DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    const int block = 64 * waves;
+    const int64_t tile_elems = (int64_t)16 * cb * waves;
+    const int64_t ntiles = ceil_div(a.nelem, tile_elems);
+    int per_cu = (tile && tile->groups_per_cu > 0) ? tile->groups_per_cu : 0;
+    if (per_cu == 0) {
+        DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(fn), block, smem));
+        if (per_cu < 1) per_cu = 1;
+    }
+    // blocks per XCD per group: fill the resident capacity, no more streams than tiles
+    const int64_t cap = std::max<int64_t>(1, (int64_t)per_cu * dev.num_cu / (8 * ngroups));
+    const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(ntiles, 8)));
+    const int64_t grid = 8 * ngroups * slots;
+
+    a.ntiles = ntiles;
+    a.mblk = mblk;
+    a.panels_total = panels_total;
+    a.ppg = ppg;
+    a.ngroups = ngroups;
+    a.nstreams = (int)(8 * slots);
+    a.vec_in = vec_in;
+    a.src_aligned = reinterpret_cast<uintptr_t>(a.src) % 16 == 0;
+    a.use_slab = use_slab;
+    a.vec_out = (nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(a.out) % 16 == 0);
+    a.nt_store = (tile && (tile->flags & DG_TILE_NT_STORE)) ? 1 : 0;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), smem, s, a);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+}  // namespace kern
+}  // namespace dg

@@ -206,3 +206,12 @@ def test_adjoint_vs_einsum(orc):
     only_u, none_d = orc.dg_adjoint(D, u, g, want_D=False)
     assert none_d is None
     np.testing.assert_array_equal(only_u, gu)
+
+
+def test_adjoint_D_select_matches_full(orc):
+    rng = np.random.default_rng(6)
+    u = rng.normal(size=(40, 8))
+    g = rng.normal(size=(3, 40, 8))
+    _, gD = orc.dg_adjoint(rng.normal(size=(3, 8, 8)), u, g)
+    mm, ii, jj = np.array([0, 2, 1]), np.array([7, 0, 3]), np.array([1, 7, 3])
+    np.testing.assert_array_equal(orc.dg_adjoint_D_select(u, g, mm, ii, jj), gD[mm, ii, jj])
