@@ -139,6 +139,93 @@ dg_status stencil5_apply(dg_dtype t, int64_t n, const void* u, int64_t ld_u, voi
 dg_status matmul_apply(dg_dtype t, int64_t n, const void* a, const void* b, void* c,
                        dg_stream_t stream);
 
+/* ------------------------------------------------------------------------
+   Black-box performance model (Sections "Gathering Kernel Statistics",
+   "Modeling Kernel Execution Time", "Computing Model Parameters" and
+   "Predicting Cost").  Host only, FP64.
+   ------------------------------------------------------------------------ */
+
+/* An empty kernel (no instructions) with the given number of 256-lane
+   work-groups: isolates the launch and work-group costs of the model
+   (Section "Other Features").  workgroups >= 1.                            */
+dg_status dg_empty_launch(int64_t workgroups, dg_stream_t stream);
+
+typedef enum {
+    DG_K_DGDIFF = 0,   /* dgdiff_apply forward (dtype = in_t) */
+    DG_K_STENCIL5 = 1, /* stencil5_apply (fast path: FP32, n % 4 == 0, padded pitches) */
+    DG_K_MATMUL = 2,   /* matmul_apply */
+    DG_K_EMPTY = 3     /* dg_empty_launch */
+} dg_kernel;
+
+typedef struct {
+    dg_kernel kernel;
+    dg_dtype dtype;
+    int64_t n0;        /* DG: nelem; stencil and matmul: n; empty: work-groups */
+    int32_t nunit;     /* DG only */
+    int32_t nmat;      /* DG only */
+    dg_tile tile;      /* DG only: fully resolved launch shape (dgdiff_resolve_tile) */
+    int32_t num_cu;    /* DG only: compute units of the target device */
+} perf_kernel_desc;
+
+/* Feature indices of perf_features_count (counts are int64, exact):          */
+enum {
+    PF_LAUNCH = 0,       /* kernel launches */
+    PF_WORKGROUPS,       /* work-groups */
+    PF_BARRIER_X_WG,     /* barriers met by one work-item x work-groups */
+    PF_GLD_DG_U,         /* DG element-data loads, bytes (first operator group) */
+    PF_GLD_DG_U_L2,      /* DG element-data re-loads by further operator groups (L2) */
+    PF_GLD_DG_D,         /* DG operator loads while staging into LDS, bytes */
+    PF_GST_DG_OUT,       /* DG output stores, bytes */
+    PF_GLD_ST_U,         /* stencil grid loads, bytes */
+    PF_GST_ST_RES,       /* stencil result stores, bytes */
+    PF_GLD_MM_AB,        /* matmul operand loads, bytes */
+    PF_GST_MM_C,         /* matmul result stores, bytes */
+    PF_LDS_BYTES,        /* LDS bytes moved (incl. wave shuffles) */
+    PF_MFMA_F64,         /* matrix-core flops executed, per input type */
+    PF_MFMA_F32,
+    PF_MFMA_BF16,
+    PF_MFMA_FP8,
+    PF_VALU_F32,         /* vector-ALU flops */
+    PF_VALU_F64,
+    PF_COUNT
+};
+
+int32_t perf_feature_count(void);           /* PF_COUNT */
+const char* perf_feature_name(int32_t k);   /* "" when out of range */
+
+/* Exact operation counts of one launch described by d (int64 counts[PF_COUNT],
+   overwritten).  Global and LDS traffic are bytes of the lanes that execute
+   the access; matrix-core work is the flops of the executed instructions
+   (padding included); barriers are counted per work-item and multiplied by
+   the work-group count (the paper's granularity rules).  DG descriptors need
+   a resolved tile (all of elems_per_wave, waves, groups_per_cu, d_panels)
+   and num_cu: counts then follow the exact schedule dgdiff_apply launches
+   with that tile on a device with num_cu compute units.                     */
+dg_status perf_features_count(const perf_kernel_desc* d, int64_t* counts);
+
+/* Fill the 0 fields of *tile with the launch shape dgdiff_apply would use
+   for this problem on the current device (groups_per_cu from the occupancy
+   of the chosen kernel; needs a GPU).                                       */
+dg_status dgdiff_resolve_tile(dg_dtype in_t, int32_t nmat, int64_t nelem, int32_t nunit,
+                              dg_tile* tile);
+
+/* Fit a linear model t ~ F p (F [rows][cols] row-major FP64 features, t
+   [rows] seconds): the p [cols] minimising ||t - F p||_2, or with relative = 1
+   the relative error ||1 - diag(1/t) F p||_2 (the paper's
+   scale_features_by_output).  Columns are equilibrated, the system is solved
+   by an FP64 SVD (no normal equations), singular values below 1e-12 of the
+   largest are dropped and the minimum-norm solution is returned: a
+   rank-deficient F is not an error (*rank < cols).  *resid = residual norm
+   at the solution, *cond = condition number of the kept part.  Each output
+   pointer except p may be NULL.  DG_EINVAL: rows or cols <= 0, non-finite
+   input, or t <= 0 with relative = 1.                                       */
+dg_status perf_model_fit(int32_t rows, int32_t cols, const double* F, const double* t,
+                         int32_t relative, double* p, double* resid, int32_t* rank, double* cond);
+
+/* t_out[k] = sum_j F[k][j] p[j] (Section "Predicting Cost").               */
+dg_status perf_model_predict(int32_t rows, int32_t cols, const double* F, const double* p,
+                             double* t_out);
+
 #ifdef __cplusplus
 }
 #endif

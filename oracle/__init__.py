@@ -64,9 +64,10 @@ def _declare(L):
     L.orc_pow2_scale.argtypes = [ctypes.c_double, ctypes.c_double]
     L.orc_pow2_scale.restype = ctypes.c_double
     L.orc_quantize.argtypes = [_i32, _i64, _i64, _i32, _fp, ctypes.c_void_p, _fp]
-    if hasattr(L, "orc_features"):
-        L.orc_features.argtypes = [_i32, _i32, _i64, _i64, _i64, _i32, _i32, _i32, _i32, _i64p]
-        L.orc_features.restype = _i32
+    L.orc_features.argtypes = [_i32, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i64p]
+    L.orc_features.restype = _i32
+    L.orc_count_triangle.argtypes = [_i64, _i64]
+    L.orc_count_triangle.restype = _i64
 
 
 def _f64(x):
@@ -187,6 +188,31 @@ def matmul_select(a, b, ii, jj):
     out = np.empty(len(ii))
     lib().orc_matmul_select(n, _ptr(a), _ptr(b), len(ii), _ptr(ii, _i64p), _ptr(jj, _i64p), _ptr(out))
     return out
+
+
+# ------------------------------------------------------------------ feature counts
+
+FEATURES = ["launch", "workgroups", "barrier_x_wg", "gld_dg_u", "gld_dg_u_l2", "gld_dg_d",
+            "gst_dg_out", "gld_st_u", "gst_st_res", "gld_mm_ab", "gst_mm_c", "lds_bytes",
+            "mfma_f64", "mfma_f32", "mfma_bf16", "mfma_fp8", "valu_f32", "valu_f64"]
+KERNELS = {"dg": 0, "stencil": 1, "matmul": 2, "empty": 3}
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
+
+
+def features(kernel, dtype, n0, nunit=0, nmat=0, elems_per_wave=0, waves=0, groups_per_cu=0,
+             d_panels=0, flags=0, num_cu=0):
+    """Brute-force enumeration of one launch's operation counts (int64 array)."""
+    out = np.zeros(len(FEATURES), dtype=np.int64)
+    rc = lib().orc_features(KERNELS[kernel], DTYPES[dtype], int(n0), nunit, nmat, elems_per_wave,
+                            waves, groups_per_cu, d_panels, flags, num_cu, _ptr(out, _i64p))
+    if rc != 0:
+        raise ValueError("unsupported descriptor")
+    return out
+
+
+def count_triangle(p, n):
+    """#{(i, j): p <= i < n, p <= j < i + 1} by enumeration."""
+    return int(lib().orc_count_triangle(p, n))
 
 
 # ------------------------------------------------------------------ encodings

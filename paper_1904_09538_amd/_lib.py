@@ -35,6 +35,14 @@ class dg_tile(ctypes.Structure):
 DG_TILE_NT_STORE = 1
 DG_TILE_FP8_NATIVE = 2
 
+DG_K_DGDIFF, DG_K_STENCIL5, DG_K_MATMUL, DG_K_EMPTY = range(4)
+
+
+class perf_kernel_desc(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n0", ctypes.c_int64),
+                ("nunit", ctypes.c_int32), ("nmat", ctypes.c_int32), ("tile", dg_tile),
+                ("num_cu", ctypes.c_int32)]
+
 
 _lib = None
 
@@ -69,6 +77,20 @@ def _declare(L):
                                   ctypes.c_size_t, _vp]
     L.dgdiff_quantize.restype = _i32
     L.dgdiff_quantize.argtypes = [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp]
+    L.dg_empty_launch.restype = _i32
+    L.dg_empty_launch.argtypes = [_i64, _vp]
+    L.perf_feature_count.restype = _i32
+    L.perf_feature_name.restype = ctypes.c_char_p
+    L.perf_feature_name.argtypes = [_i32]
+    L.perf_features_count.restype = _i32
+    L.perf_features_count.argtypes = [ctypes.POINTER(perf_kernel_desc), ctypes.POINTER(ctypes.c_int64)]
+    L.dgdiff_resolve_tile.restype = _i32
+    L.dgdiff_resolve_tile.argtypes = [_i32, _i32, _i64, _i32, ctypes.POINTER(dg_tile)]
+    _dp = ctypes.POINTER(ctypes.c_double)
+    L.perf_model_fit.restype = _i32
+    L.perf_model_fit.argtypes = [_i32, _i32, _dp, _dp, _i32, _dp, _dp, ctypes.POINTER(_i32), _dp]
+    L.perf_model_predict.restype = _i32
+    L.perf_model_predict.argtypes = [_i32, _i32, _dp, _dp, _dp]
     L.stencil5_apply.restype = _i32
     L.stencil5_apply.argtypes = [_i32, _i64, _vp, _i64, _vp, _i64, _vp]
     L.matmul_apply.restype = _i32
@@ -202,3 +224,75 @@ def dgdiff_backward(D, u, g, want_u=True, want_D=True, stream=None):
     check(lib().dgdiff_backward(t, nmat, nelem, nunit, _ptr(D), _ptr(u), _ptr(g), _ptr(gu), _ptr(gD),
                                 _ptr(ws), nbytes, _stream(stream)))
     return gu, gD
+
+
+# ------------------------------------------------------------------ performance model
+
+_DT = {"f64": DG_F64, "f32": DG_F32, "bf16": DG_BF16, "fp8": DG_FP8E4M3}
+
+
+def feature_names():
+    L = lib()
+    return [L.perf_feature_name(k).decode() for k in range(L.perf_feature_count())]
+
+
+def perf_features_count(kernel, dtype, n0, nunit=0, nmat=0, tile=None, num_cu=0):
+    """Exact operation counts of one launch (numpy int64 array, feature_names() order)."""
+    import numpy as np
+    L = lib()
+    d = perf_kernel_desc()
+    d.kernel = {"dg": DG_K_DGDIFF, "stencil": DG_K_STENCIL5, "matmul": DG_K_MATMUL,
+                "empty": DG_K_EMPTY}[kernel]
+    d.dtype = _DT[dtype]
+    d.n0 = int(n0)
+    d.nunit = int(nunit)
+    d.nmat = int(nmat)
+    if tile is not None:
+        t = tile if isinstance(tile, dg_tile) else dg_tile(
+            *[int(tile.get(k, 0)) for k in ("elems_per_wave", "waves", "groups_per_cu", "d_panels", "flags")])
+        d.tile = t
+    d.num_cu = int(num_cu)
+    out = np.zeros(L.perf_feature_count(), dtype=np.int64)
+    check(L.perf_features_count(ctypes.byref(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return out
+
+
+def resolve_tile(dtype, nmat, nelem, nunit, tile=None):
+    """Fill the open fields of a DG launch shape as dgdiff_apply would (GPU)."""
+    t = dg_tile(*[int((tile or {}).get(k, 0)) for k in
+                  ("elems_per_wave", "waves", "groups_per_cu", "d_panels", "flags")])
+    check(lib().dgdiff_resolve_tile(_DT[dtype], nmat, nelem, nunit, ctypes.byref(t)))
+    return {k: getattr(t, k) for k in ("elems_per_wave", "waves", "groups_per_cu", "d_panels", "flags")}
+
+
+def perf_model_fit(F, t, relative=True):
+    """FP64 least-squares fit; returns dict(p, resid, rank, cond)."""
+    import numpy as np
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    rows, cols = F.shape
+    p = np.zeros(cols)
+    resid = ctypes.c_double()
+    rank = ctypes.c_int32()
+    cond = ctypes.c_double()
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().perf_model_fit(rows, cols, F.ctypes.data_as(dp), t.ctypes.data_as(dp), int(relative),
+                               p.ctypes.data_as(dp), ctypes.byref(resid), ctypes.byref(rank),
+                               ctypes.byref(cond)))
+    return {"p": p, "resid": resid.value, "rank": rank.value, "cond": cond.value,
+            "negative": [int(k) for k in np.nonzero(p < 0)[0]]}
+
+
+def perf_model_predict(F, p):
+    import numpy as np
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros(F.shape[0])
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().perf_model_predict(F.shape[0], F.shape[1], F.ctypes.data_as(dp), p.ctypes.data_as(dp),
+                                   out.ctypes.data_as(dp)))
+    return out
+
+
+def dg_empty_launch(workgroups, stream=None):
+    check(lib().dg_empty_launch(int(workgroups), _stream(stream)))

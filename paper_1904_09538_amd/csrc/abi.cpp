@@ -151,6 +151,13 @@ dg_status stencil5_apply(dg_dtype t, int64_t n, const void* u, int64_t ld_u, voi
     return launch_stencil5(t, n, u, ld_u, res, ld_res, reinterpret_cast<hipStream_t>(stream));
 }
 
+dg_status dg_empty_launch(int64_t workgroups, dg_stream_t stream) {
+    set_error("");
+    if (workgroups < 1 || workgroups > ((int64_t)1 << 31) - 1)
+        return fail(DG_EINVAL, "dg_empty_launch: workgroups out of range");
+    return launch_empty(workgroups, reinterpret_cast<hipStream_t>(stream));
+}
+
 dg_status matmul_apply(dg_dtype t, int64_t n, const void* a, const void* b, void* c,
                        dg_stream_t stream) {
     set_error("");

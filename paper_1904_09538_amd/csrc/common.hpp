@@ -64,6 +64,20 @@ dg_status launch_dg_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit,
                                const void* D, const void* u, void* out,
                                const dg_tile* tile, hipStream_t s);
 
+// Launch plan of the low-precision forward (shared with the feature counter).
+struct LpPlan {
+    int fmt;       // 0 BF16, 1 FP8 native, 2 FP8 widened to BF16
+    int ks, cb, waves, lds_esz;
+    int mblk, panels_total, ppg, ngroups;
+    int64_t ntiles, slots, grid;
+    size_t panel_bytes, smem;
+};
+int lp_format(dg_dtype in_t, const dg_tile* tile);
+dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_tile* tile, int per_cu,
+                       int num_cu, LpPlan* P);
+dg_status resolve_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nunit, dg_tile* tile);
+dg_status resolve_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_tile* tile);
+
 dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nunit, const void* D,
                                  const void* u, void* out, const float* inv_sD,
                                  const float* inv_su, const dg_tile* tile, hipStream_t s);
@@ -81,6 +95,8 @@ dg_status launch_stencil5(dg_dtype t, int64_t n, const void* u, int64_t ld_u, vo
 bool stencil5_vector_ok(dg_dtype t, int64_t n, const void* u, int64_t ld_u, const void* res,
                         int64_t ld_res);
 int stencil5_rows_per_strip(int64_t n);
+
+dg_status launch_empty(int64_t workgroups, hipStream_t s);
 
 dg_status launch_matmul(int64_t n, const void* a, const void* b, void* c, hipStream_t s);
 bool matmul_vector_ok(int64_t n, const void* a, const void* b, const void* c);

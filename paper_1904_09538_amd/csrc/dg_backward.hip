@@ -219,10 +219,9 @@ dg_status launch_grad_u(int nmat, int64_t nelem, int nunit, const void* D, const
                 : nmat == 2 ? pick_kernel<T, 1, 2>(kq)
                 : nmat == 3 ? pick_kernel<T, 1, 3>(kq) : nullptr;
     if (one) {
-        auto pick = [one](int) { return one; };
-        if (nmat == 1) return launch<T, 1>(a, 1, kq, 1, tile, waves, pick, s);
-        if (nmat == 2) return launch<T, 2>(a, 1, kq, 1, tile, waves, pick, s);
-        return launch<T, 3>(a, 1, kq, 1, tile, waves, pick, s);
+        if (nmat == 1) return launch<T, 1>(a, 1, kq, 1, tile, waves, one, s);
+        if (nmat == 2) return launch<T, 2>(a, 1, kq, 1, tile, waves, one, s);
+        return launch<T, 3>(a, 1, kq, 1, tile, waves, one, s);
     }
     // one operator per launch; launches after the first accumulate
     for (int m = 0; m < nmat; ++m) {
@@ -236,8 +235,7 @@ dg_status launch_grad_u(int nmat, int64_t nelem, int nunit, const void* D, const
         DG_KQ_LIST(X)
 #undef X
         if (!fn) return fail(DG_EUNSUPPORTED, "no grad_u kernel instance");
-        auto pick = [fn](int) { return fn; };
-        dg_status st = launch<T, 1>(am, 1, kq, 1, tile, waves, pick, s);
+        dg_status st = launch<T, 1>(am, 1, kq, 1, tile, waves, fn, s);
         if (st != DG_OK) return st;
     }
     return DG_OK;

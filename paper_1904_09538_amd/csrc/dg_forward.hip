@@ -8,35 +8,23 @@ namespace {
 using namespace kern;
 
 template <typename T>
+kern_fn forward_kernel(int kq, int cb) {
+    return cb == 4 ? pick_kernel<T, 4, 1>(kq) : cb == 2 ? pick_kernel<T, 2, 1>(kq)
+                                                       : pick_kernel<T, 1, 1>(kq);
+}
+
+template <typename T>
 dg_status launch_fwd(int nmat, int64_t nelem, int nunit, const void* D, const void* u, void* out,
                      const dg_tile* tile, hipStream_t s) {
     const int kq = kq_for(nunit);
     if (kq < 0) return fail(DG_EUNSUPPORTED, "nunit too large for the DG kernel");
     const int waves = (tile && tile->waves) ? tile->waves : 4;
-    const int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : 0;
     if (waves < 1 || waves > 4) return fail(DG_EINVAL, "tile.waves must be in 1..4");
     const bool rows_aligned =
         (nunit % Mma<T>::V == 0) && (reinterpret_cast<uintptr_t>(u) % 16 == 0);
     int cb;
-    if (epw == 0) {
-        // measured defaults (FP32, 2^21 elements): aligned short rows favour one
-        // column block per wave (more waves in flight); otherwise more column
-        // blocks per wave, as registers allow
-        const int w = kq * (int)sizeof(T) / 4;  // KQ in 32-bit registers
-        if (rows_aligned && w <= 16) cb = 1;
-        else if (w <= 32) cb = 4;
-        else if (w <= 64) cb = 2;
-        else cb = 1;
-    } else if (epw == 16) {
-        cb = 1;
-    } else if (epw == 32) {
-        cb = 2;
-    } else if (epw == 64 && kq * (int)sizeof(T) <= 32 * 4) {
-        cb = 4;
-    } else {
-        return fail(DG_EINVAL,
-                    "tile.elems_per_wave must be 16 or 32 (or 64 for nunit <= 128 in FP32)");
-    }
+    dg_status st = forward_cb(sizeof(T), kq, rows_aligned, tile ? tile->elems_per_wave : 0, &cb);
+    if (st != DG_OK) return st;
     KArgs a = {};
     a.D = D;
     a.src = u;
@@ -45,11 +33,7 @@ dg_status launch_fwd(int nmat, int64_t nelem, int nunit, const void* D, const vo
     a.seg_stride = 0;
     a.nunit = nunit;
     a.transpose = 0;
-    auto pick = [kq](int c) -> kern_fn {
-        return c == 4 ? pick_kernel<T, 4, 1>(kq) : c == 2 ? pick_kernel<T, 2, 1>(kq)
-                                                         : pick_kernel<T, 1, 1>(kq);
-    };
-    return launch<T, 1>(a, nmat, kq, cb, tile, waves, pick, s);
+    return launch<T, 1>(a, nmat, kq, cb, tile, waves, forward_kernel<T>(kq, cb), s);
 }
 
 }  // namespace
@@ -59,6 +43,38 @@ dg_status launch_dg_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit, c
     if (t == DG_F32) return launch_fwd<float>(nmat, nelem, nunit, D, u, out, tile, s);
     if (t == DG_F64) return launch_fwd<double>(nmat, nelem, nunit, D, u, out, tile, s);
     return fail(DG_EUNSUPPORTED, "launch_dg_forward_fp: dtype");
+}
+
+// Resolve a forward launch shape (0 fields -> defaults, occupancy queried on
+// the current device) for the feature counter and the autotuner.
+dg_status resolve_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_tile* tile) {
+    const size_t ts = t == DG_F64 ? 8 : 4;
+    const int kq = kq_for(nunit);
+    if (kq < 0) return fail(DG_EUNSUPPORTED, "nunit too large for the DG kernel");
+    if (tile->waves == 0) tile->waves = 4;
+    int cb;
+    dg_status st = forward_cb(ts, kq, nunit % (int)(16 / ts) == 0, tile->elems_per_wave, &cb);
+    if (st != DG_OK) return st;
+    tile->elems_per_wave = 16 * cb;
+    DeviceInfo dev;
+    st = current_device(&dev);
+    if (st != DG_OK) return st;
+    Plan P;
+    st = make_plan(ts, 1, nmat, nelem, nunit, kq, cb, tile->waves, tile->d_panels, 1, dev.num_cu,
+                   nunit % (int)(16 / ts) == 0, &P);
+    if (st != DG_OK) return st;
+    tile->d_panels = P.ppg;
+    if (tile->groups_per_cu == 0) {
+        kern_fn fn = t == DG_F64 ? forward_kernel<double>(kq, cb) : forward_kernel<float>(kq, cb);
+        if (!fn) return fail(DG_EUNSUPPORTED, "no DG kernel instance");
+        DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
+        int per_cu = 0;
+        DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(fn), 64 * tile->waves, P.smem));
+        tile->groups_per_cu = std::max(1, per_cu);
+    }
+    return DG_OK;
 }
 
 }  // namespace dg

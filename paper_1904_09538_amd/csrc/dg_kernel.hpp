@@ -355,72 +355,125 @@ kern_fn pick_kernel(int kq) {
 constexpr size_t kLdsBudget = 64 * 1024;  // default: whole stack if it fits here
 constexpr size_t kLdsMax = 160 * 1024;    // gfx950 LDS per CU
 
-// Plan and launch one contraction.  fn chooser: pick(cb) -> kernel.
-template <typename T, int NSEG, typename Pick>
-dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, int waves, Pick pick,
+// The launch plan of one contraction: a pure function of the problem, the
+// explicit launch shape and the device's CU count (shared with the feature
+// counter, so counts follow the launched schedule exactly).
+struct Plan {
+    int kq, cb, waves, nseg;
+    int mblk, panels_total, ppg, ngroups;
+    int64_t ntiles, slots, grid;
+    int vec_in, use_slab;
+    size_t smem, panel_bytes, slab_bytes;
+};
+
+// per_cu: resident work-groups per CU (explicit, > 0).
+inline dg_status make_plan(size_t tsize, int nseg, int out_slabs, int64_t nelem, int nunit, int kq,
+                           int cb, int waves, int d_panels, int per_cu, int num_cu, bool src_vec_ok,
+                           Plan* P) {
+    const int V = (int)(16 / tsize);
+    P->kq = kq;
+    P->cb = cb;
+    P->waves = waves;
+    P->nseg = nseg;
+    P->mblk = (int)ceil_div(nunit, 16);
+    P->panels_total = out_slabs * P->mblk;
+    P->panel_bytes = (size_t)16 * (nseg * 4 * kq + V) * tsize;
+    P->vec_in = src_vec_ok ? 1 : 0;
+    size_t slab = P->vec_in ? 0 : (size_t)waves * nseg * round_up(16 * cb * nunit, V) * tsize;
+    P->use_slab = slab > 0 && slab + P->panel_bytes <= kLdsMax / 2;
+    if (!P->use_slab) slab = 0;
+    P->slab_bytes = slab;
+    int ppg;
+    if (d_panels > 0) {
+        ppg = std::min(d_panels, P->panels_total);
+    } else {
+        const size_t budget = kLdsBudget > slab ? kLdsBudget - slab : 0;
+        if ((size_t)P->panels_total * P->panel_bytes <= budget) {
+            ppg = P->panels_total;
+        } else {
+            const size_t room = kLdsMax - slab;
+            const int fit = std::max<int>(1, (int)(room / P->panel_bytes));
+            const int groups = (int)ceil_div(P->panels_total, fit);
+            ppg = (int)ceil_div(P->panels_total, groups);
+        }
+    }
+    P->ppg = ppg;
+    P->ngroups = (int)ceil_div(P->panels_total, ppg);
+    P->smem = (size_t)ppg * P->panel_bytes + slab;
+    if (P->smem > kLdsMax) return fail(DG_EINVAL, "tile.d_panels exceeds the 160 KB LDS");
+    P->ntiles = ceil_div(nelem, (int64_t)16 * cb * waves);
+    // blocks per XCD per group: fill the resident capacity, no more streams than tiles
+    const int64_t cap = std::max<int64_t>(1, (int64_t)per_cu * num_cu / (8 * P->ngroups));
+    P->slots = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(P->ntiles, 8)));
+    P->grid = 8 * P->ngroups * P->slots;
+    return DG_OK;
+}
+
+// Launch one contraction with the kernel fn; tile->groups_per_cu == 0 means
+// "occupancy maximum" (queried for fn).
+template <typename T, int NSEG>
+dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, int waves, kern_fn fn,
                  hipStream_t s) {
+    if (!fn) return fail(DG_EUNSUPPORTED, "no DG kernel instance for this shape");
     DeviceInfo dev;
     dg_status st = current_device(&dev);
     if (st != DG_OK) return st;
-    const int nunit = a.nunit;
-    const int mblk = (int)ceil_div(nunit, 16);
-    const int panels_total = out_slabs * mblk;
-    const size_t panel_bytes = (size_t)16 * (NSEG * 4 * kq + Mma<T>::V) * sizeof(T);
-    const bool vec_in = (nunit % Mma<T>::V == 0) && (reinterpret_cast<uintptr_t>(a.src) % 16 == 0) &&
-                        (a.seg_stride % Mma<T>::V == 0);
-    size_t slab_bytes =
-        vec_in ? 0 : (size_t)waves * NSEG * round_up(16 * cb * nunit, Mma<T>::V) * sizeof(T);
-    const bool use_slab = slab_bytes > 0 && slab_bytes + panel_bytes <= kLdsMax / 2;
-    if (!use_slab) slab_bytes = 0;
-    int ppg;
-    if (tile && tile->d_panels > 0) {
-        ppg = std::min(tile->d_panels, panels_total);
-    } else {
-        const size_t budget = kLdsBudget > slab_bytes ? kLdsBudget - slab_bytes : 0;
-        if ((size_t)panels_total * panel_bytes <= budget) {
-            ppg = panels_total;
-        } else {
-            const size_t room = kLdsMax - slab_bytes;
-            const int fit = std::max<int>(1, (int)(room / panel_bytes));
-            const int groups = (int)ceil_div(panels_total, fit);
-            ppg = (int)ceil_div(panels_total, groups);
-        }
-    }
-    const int ngroups = (int)ceil_div(panels_total, ppg);
-    const size_t smem = (size_t)ppg * panel_bytes + slab_bytes;
-    if (smem > kLdsMax) return fail(DG_EINVAL, "tile.d_panels exceeds the 160 KB LDS");
-
-    kern_fn fn = pick(cb);
-    if (!fn) return fail(DG_EUNSUPPORTED, "no DG kernel instance for this shape");
+    const bool src_vec_ok = (a.nunit % Mma<T>::V == 0) &&
+                            (reinterpret_cast<uintptr_t>(a.src) % 16 == 0) &&
+                            (a.seg_stride % Mma<T>::V == 0);
+    Plan P;
+    // first pass with a provisional occupancy to size the LDS request
+    st = make_plan(sizeof(T), NSEG, out_slabs, a.nelem, a.nunit, kq, cb, waves,
+                   tile ? tile->d_panels : 0, 1, dev.num_cu, src_vec_ok, &P);
+    if (st != DG_OK) return st;
     DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    const int block = 64 * waves;
-    const int64_t tile_elems = (int64_t)16 * cb * waves;
-    const int64_t ntiles = ceil_div(a.nelem, tile_elems);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
     int per_cu = (tile && tile->groups_per_cu > 0) ? tile->groups_per_cu : 0;
     if (per_cu == 0) {
         DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(fn), block, smem));
+            &per_cu, reinterpret_cast<const void*>(fn), 64 * waves, P.smem));
         if (per_cu < 1) per_cu = 1;
     }
-    // blocks per XCD per group: fill the resident capacity, no more streams than tiles
-    const int64_t cap = std::max<int64_t>(1, (int64_t)per_cu * dev.num_cu / (8 * ngroups));
-    const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(ntiles, 8)));
-    const int64_t grid = 8 * ngroups * slots;
-
-    a.ntiles = ntiles;
-    a.mblk = mblk;
-    a.panels_total = panels_total;
-    a.ppg = ppg;
-    a.ngroups = ngroups;
-    a.nstreams = (int)(8 * slots);
-    a.vec_in = vec_in;
+    st = make_plan(sizeof(T), NSEG, out_slabs, a.nelem, a.nunit, kq, cb, waves,
+                   tile ? tile->d_panels : 0, per_cu, dev.num_cu, src_vec_ok, &P);
+    if (st != DG_OK) return st;
+    a.ntiles = P.ntiles;
+    a.mblk = P.mblk;
+    a.panels_total = P.panels_total;
+    a.ppg = P.ppg;
+    a.ngroups = P.ngroups;
+    a.nstreams = (int)(8 * P.slots);
+    a.vec_in = P.vec_in;
     a.src_aligned = reinterpret_cast<uintptr_t>(a.src) % 16 == 0;
-    a.use_slab = use_slab;
-    a.vec_out = (nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(a.out) % 16 == 0);
+    a.use_slab = P.use_slab;
+    a.vec_out = (a.nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(a.out) % 16 == 0);
     a.nt_store = (tile && (tile->flags & DG_TILE_NT_STORE)) ? 1 : 0;
-    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(block), smem, s, a);
+    hipLaunchKernelGGL(fn, dim3((unsigned)P.grid), dim3(64 * waves), P.smem, s, a);
     DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
+// Column blocks per wave of the forward kernel: the measured default when the
+// tile leaves it open (FP32, 2^21 elements: aligned short rows favour one
+// column block per wave, i.e. more waves in flight; otherwise more column
+// blocks, as registers allow), else the requested one.
+inline dg_status forward_cb(size_t tsize, int kq, bool rows_aligned, int epw, int* cb) {
+    if (epw == 0) {
+        const int w = kq * (int)tsize / 4;  // KQ in 32-bit registers
+        if (rows_aligned && w <= 16) *cb = 1;
+        else if (w <= 32) *cb = 4;
+        else if (w <= 64) *cb = 2;
+        else *cb = 1;
+    } else if (epw == 16) {
+        *cb = 1;
+    } else if (epw == 32) {
+        *cb = 2;
+    } else if (epw == 64 && kq * (int)tsize <= 32 * 4) {
+        *cb = 4;
+    } else {
+        return fail(DG_EINVAL,
+                    "tile.elems_per_wave must be 16 or 32 (or 64 for nunit <= 128 in FP32)");
+    }
     return DG_OK;
 }
 

@@ -253,7 +253,85 @@ lp_fn pick_lp(int ks) {
 constexpr size_t kLpBudget = 80 * 1024;
 constexpr size_t kLpMax = 160 * 1024;
 
+lp_fn lp_kernel(int fmt, int ks, int cb) {
+    if (fmt == 0) return cb == 4 ? pick_lp<0, 4>(ks) : cb == 2 ? pick_lp<0, 2>(ks) : pick_lp<0, 1>(ks);
+    if (fmt == 1) return cb == 4 ? pick_lp<1, 4>(ks) : cb == 2 ? pick_lp<1, 2>(ks) : pick_lp<1, 1>(ks);
+    return cb == 4 ? pick_lp<2, 4>(ks) : cb == 2 ? pick_lp<2, 2>(ks) : pick_lp<2, 1>(ks);
+}
+
 }  // namespace
+
+int lp_format(dg_dtype in_t, const dg_tile* tile) {
+    const bool native = tile && (tile->flags & DG_TILE_FP8_NATIVE);
+    return (in_t == DG_BF16) ? 0 : native ? 1 : 2;
+}
+
+dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_tile* tile, int per_cu,
+                       int num_cu, LpPlan* P) {
+    P->fmt = fmt;
+    P->ks = (int)ceil_div(nunit, 32);
+    if (P->ks > 16) return fail(DG_EUNSUPPORTED, "nunit too large");
+    P->waves = (tile && tile->waves) ? tile->waves : 4;
+    if (P->waves < 1 || P->waves > 4) return fail(DG_EINVAL, "tile.waves must be in 1..4");
+    const int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : 32;
+    if (epw == 16) P->cb = 1;
+    else if (epw == 32) P->cb = 2;
+    else if (epw == 64 && P->ks <= 8) P->cb = 4;
+    else return fail(DG_EINVAL, "tile.elems_per_wave must be 16, 32 (or 64 for nunit <= 256)");
+    P->lds_esz = fmt == 1 ? 1 : 2;
+    P->mblk = (int)ceil_div(nunit, 16);
+    P->panels_total = nmat * P->mblk;
+    P->panel_bytes = (size_t)16 * (32 * P->ks * P->lds_esz + 16);
+    int ppg;
+    if (tile && tile->d_panels > 0) {
+        ppg = std::min(tile->d_panels, P->panels_total);
+    } else if ((size_t)P->panels_total * P->panel_bytes <= kLpBudget) {
+        ppg = P->panels_total;
+    } else {
+        const int fit = std::max<int>(1, (int)(kLpMax / P->panel_bytes));
+        const int groups = (int)ceil_div(P->panels_total, fit);
+        ppg = (int)ceil_div(P->panels_total, groups);
+    }
+    P->ppg = ppg;
+    P->ngroups = (int)ceil_div(P->panels_total, ppg);
+    P->smem = (size_t)ppg * P->panel_bytes;
+    if (P->smem > kLpMax) return fail(DG_EINVAL, "tile.d_panels exceeds the 160 KB LDS");
+    P->ntiles = ceil_div(nelem, (int64_t)16 * P->cb * P->waves);
+    const int64_t cap = std::max<int64_t>(1, (int64_t)per_cu * num_cu / (8 * P->ngroups));
+    P->slots = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(P->ntiles, 8)));
+    P->grid = 8 * P->ngroups * P->slots;
+    return DG_OK;
+}
+
+static dg_status lp_occupancy(const LpPlan& P, int* per_cu) {
+    lp_fn fn = lp_kernel(P.fmt, P.ks, P.cb);
+    if (!fn) return fail(DG_EUNSUPPORTED, "no low-precision DG kernel instance");
+    DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
+    DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, reinterpret_cast<const void*>(fn),
+                                                              64 * P.waves, P.smem));
+    if (*per_cu < 1) *per_cu = 1;
+    return DG_OK;
+}
+
+dg_status resolve_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nunit, dg_tile* tile) {
+    DeviceInfo dev;
+    dg_status st = current_device(&dev);
+    if (st != DG_OK) return st;
+    LpPlan P;
+    st = make_lp_plan(lp_format(in_t, tile), nmat, nelem, nunit, tile, 1, dev.num_cu, &P);
+    if (st != DG_OK) return st;
+    tile->waves = P.waves;
+    tile->elems_per_wave = 16 * P.cb;
+    tile->d_panels = P.ppg;
+    if (tile->groups_per_cu == 0) {
+        int per_cu = 0;
+        st = lp_occupancy(P, &per_cu);
+        if (st != DG_OK) return st;
+        tile->groups_per_cu = per_cu;
+    }
+    return DG_OK;
+}
 
 dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nunit, const void* D,
                                  const void* u, void* out, const float* inv_sD,
@@ -261,55 +339,20 @@ dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nun
     DeviceInfo dev;
     dg_status st = current_device(&dev);
     if (st != DG_OK) return st;
-    const bool native = tile && (tile->flags & DG_TILE_FP8_NATIVE);
-    const int fmt = (in_t == DG_BF16) ? 0 : native ? 1 : 2;
-    const size_t esz = fmt == 1 ? 1 : 2;  // LDS bytes per operator entry
-    const int ks = (int)ceil_div(nunit, 32);
-    if (ks > 16) return fail(DG_EUNSUPPORTED, "nunit too large");
-    int waves = (tile && tile->waves) ? tile->waves : 4;
-    if (waves < 1 || waves > 4) return fail(DG_EINVAL, "tile.waves must be in 1..4");
-    const int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : 32;
-    int cb;
-    if (epw == 16) cb = 1;
-    else if (epw == 32) cb = 2;
-    else if (epw == 64 && ks <= 8) cb = 4;
-    else return fail(DG_EINVAL, "tile.elems_per_wave must be 16, 32 (or 64 for nunit <= 256)");
-
-    const int mblk = (int)ceil_div(nunit, 16);
-    const int panels_total = nmat * mblk;
-    const size_t panel_bytes = (size_t)16 * (32 * ks * esz + 16);
-    int ppg;
-    if (tile && tile->d_panels > 0) {
-        ppg = std::min(tile->d_panels, panels_total);
-    } else if ((size_t)panels_total * panel_bytes <= kLpBudget) {
-        ppg = panels_total;
-    } else {
-        const int fit = std::max<int>(1, (int)(kLpMax / panel_bytes));
-        const int groups = (int)ceil_div(panels_total, fit);
-        ppg = (int)ceil_div(panels_total, groups);
-    }
-    const int ngroups = (int)ceil_div(panels_total, ppg);
-    const size_t smem = (size_t)ppg * panel_bytes;
-    if (smem > kLpMax) return fail(DG_EINVAL, "tile.d_panels exceeds the 160 KB LDS");
-
-    lp_fn fn;
-    if (fmt == 0) fn = cb == 4 ? pick_lp<0, 4>(ks) : cb == 2 ? pick_lp<0, 2>(ks) : pick_lp<0, 1>(ks);
-    else if (fmt == 1) fn = cb == 4 ? pick_lp<1, 4>(ks) : cb == 2 ? pick_lp<1, 2>(ks) : pick_lp<1, 1>(ks);
-    else fn = cb == 4 ? pick_lp<2, 4>(ks) : cb == 2 ? pick_lp<2, 2>(ks) : pick_lp<2, 1>(ks);
-    if (!fn) return fail(DG_EUNSUPPORTED, "no low-precision DG kernel instance");
-    DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    const int block = 64 * waves;
-    const int64_t ntiles = ceil_div(nelem, (int64_t)16 * cb * waves);
+    LpPlan P;
+    st = make_lp_plan(lp_format(in_t, tile), nmat, nelem, nunit, tile, 1, dev.num_cu, &P);
+    if (st != DG_OK) return st;
     int per_cu = (tile && tile->groups_per_cu > 0) ? tile->groups_per_cu : 0;
     if (per_cu == 0) {
-        DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(fn), block, smem));
-        if (per_cu < 1) per_cu = 1;
+        st = lp_occupancy(P, &per_cu);
+        if (st != DG_OK) return st;
     }
-    const int64_t cap = std::max<int64_t>(1, (int64_t)per_cu * dev.num_cu / (8 * ngroups));
-    const int64_t slots = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(ntiles, 8)));
-
+    st = make_lp_plan(P.fmt, nmat, nelem, nunit, tile, per_cu, dev.num_cu, &P);
+    if (st != DG_OK) return st;
+    lp_fn fn = lp_kernel(P.fmt, P.ks, P.cb);
+    if (!fn) return fail(DG_EUNSUPPORTED, "no low-precision DG kernel instance");
+    DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
     LpArgs a;
     a.D = D;
     a.u = u;
@@ -317,16 +360,16 @@ dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nun
     a.inv_sD = inv_sD;
     a.inv_su = inv_su;
     a.nelem = nelem;
-    a.ntiles = ntiles;
+    a.ntiles = P.ntiles;
     a.nunit = nunit;
-    a.mblk = mblk;
-    a.panels_total = panels_total;
-    a.ppg = ppg;
-    a.ngroups = ngroups;
-    a.nstreams = (int)(8 * slots);
+    a.mblk = P.mblk;
+    a.panels_total = P.panels_total;
+    a.ppg = P.ppg;
+    a.ngroups = P.ngroups;
+    a.nstreams = (int)(8 * P.slots);
     a.vec_in = (nunit % 8 == 0) && (reinterpret_cast<uintptr_t>(u) % 16 == 0);  // 8 values / load
     a.vec_out = (nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
-    hipLaunchKernelGGL(fn, dim3((unsigned)(8 * ngroups * slots)), dim3(block), smem, s, a);
+    hipLaunchKernelGGL(fn, dim3((unsigned)P.grid), dim3(64 * P.waves), P.smem, s, a);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
 }

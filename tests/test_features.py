@@ -1,0 +1,122 @@
+"""The library's closed-form operation counts against the oracle's brute-force
+enumeration of the same documented schedules (bit-exact int64), the paper's
+worked point-count example, and the library's FP64 model fit against the
+oracle fit (CPU only)."""
+import itertools
+
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1904_09538_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def test_feature_names_agree(orc, L):
+    assert L.feature_names() == orc.FEATURES
+
+
+@pytest.mark.parametrize("p,n", [(0, 0), (0, 1), (2, 7), (3, 3), (1, 11), (5, 40)])
+def test_paper_point_count_example(orc, p, n):
+    """#{p <= i < n, p <= j < i+1} = (n^2 + p^2 - 2np + n - p) / 2."""
+    assert orc.count_triangle(p, n) == (n * n + p * p - 2 * n * p + n - p) // 2
+    assert (n * n + p * p - 2 * n * p + n - p) % 2 == 0
+
+
+def _dg_cases():
+    rng = np.random.default_rng(123)
+    cases = []
+    for dtype in ("f32", "f64", "bf16", "fp8"):
+        for nunit in (1, 5, 8, 27, 64, 100, 125, 216, 343, 512):
+            for _ in range(3):
+                nmat = int(rng.choice([1, 2, 3]))
+                E = int(rng.choice([1, 15, 17, 129, 300, 1000, 4097]))
+                waves = int(rng.choice([1, 2, 3, 4]))
+                epw = int(rng.choice([16, 32, 64]))
+                per_cu = int(rng.choice([1, 2, 3]))
+                P = nmat * ((nunit + 15) // 16)
+                ppg = int(rng.choice([1, 2, max(1, P // 3), P]))
+                flags = int(rng.choice([0, 2])) if dtype == "fp8" else 0
+                cases.append((dtype, nunit, nmat, E, waves, epw, per_cu, ppg, flags))
+    # full-size points of the calibration grid
+    cases += [("f32", 64, 3, 1 << 21, 4, 16, 3, 12, 0), ("f32", 27, 3, 1 << 20, 4, 64, 2, 6, 0),
+              ("f32", 125, 3, 1 << 18, 4, 64, 1, 12, 0), ("bf16", 216, 3, 1 << 16, 4, 32, 1, 21, 0)]
+    return cases
+
+
+@pytest.mark.parametrize("case", _dg_cases())
+def test_dg_counts_match_brute_force(orc, L, case):
+    dtype, nunit, nmat, E, waves, epw, per_cu, ppg, flags = case
+    tile = dict(elems_per_wave=epw, waves=waves, groups_per_cu=per_cu, d_panels=ppg, flags=flags)
+    try:
+        got = L.perf_features_count("dg", dtype, E, nunit, nmat, tile, num_cu=256)
+    except L.DGError:
+        pytest.skip("launch shape not available for this problem (rejected by the library)")
+    ref = orc.features("dg", dtype, E, nunit, nmat, epw, waves, per_cu, ppg, flags, 256)
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype,n", list(itertools.product(["f32"], [4, 8, 100, 1000, 1024, 2048, 4096,
+                                                                       16384])) +
+                         [("f32", 5), ("f32", 1030), ("f64", 64), ("f64", 257)])
+def test_stencil_counts_match_brute_force(orc, L, dtype, n):
+    np.testing.assert_array_equal(L.perf_features_count("stencil", dtype, n),
+                                  orc.features("stencil", dtype, n))
+
+
+@pytest.mark.parametrize("n", [1, 7, 16, 100, 128, 130, 512, 1000, 2048])
+def test_matmul_counts_match_brute_force(orc, L, n):
+    np.testing.assert_array_equal(L.perf_features_count("matmul", "f32", n),
+                                  orc.features("matmul", "f32", n))
+
+
+def test_empty_counts(orc, L):
+    for wgs in (1, 16, 4096):
+        np.testing.assert_array_equal(L.perf_features_count("empty", "f32", wgs),
+                                      orc.features("empty", "f32", wgs))
+
+
+def test_dg_counts_invariants(L):
+    """Counts that the method fixes regardless of the launch shape."""
+    for tile in (dict(elems_per_wave=16, waves=4, groups_per_cu=3, d_panels=12),
+                 dict(elems_per_wave=32, waves=2, groups_per_cu=1, d_panels=5)):
+        c = dict(zip(L.feature_names(), L.perf_features_count("dg", "f32", 5000, 64, 3, tile, 256)))
+        assert c["gst_dg_out"] == 5000 * 3 * 64 * 4      # every output written once
+        assert c["gld_dg_u"] == 5000 * 64 * 4            # every input read once (first group)
+        assert c["mfma_f32"] >= 2 * 3 * 64 * 64 * 5000   # at least the algorithmic flops
+
+
+# ------------------------------------------------------------------ model fit
+
+
+def test_fit_matches_oracle(L):
+    from oracle import model as M
+    rng = np.random.default_rng(7)
+    F = rng.uniform(1, 10, size=(60, 8)) * np.logspace(-3, 9, 8)
+    t = F @ rng.uniform(0.5, 2, 8) * np.logspace(-12, -6, 8)[None, :].sum() * rng.uniform(0.95, 1.05, 60)
+    for rel in (True, False):
+        a = L.perf_model_fit(F, t, relative=rel)
+        b = M.fit(F, t, relative=rel)
+        np.testing.assert_allclose(a["p"], b["p"], rtol=1e-9)
+        assert a["rank"] == b["rank"] == 8
+        assert abs(a["resid"] - b["resid"]) <= 1e-9 * max(1.0, b["resid"])
+        np.testing.assert_allclose(L.perf_model_predict(F, a["p"]), M.predict(F, b["p"]), rtol=1e-12)
+
+
+def test_fit_rank_deficient_and_errors(L):
+    from oracle import model as M
+    rng = np.random.default_rng(8)
+    a = rng.uniform(1, 2, 30)
+    F = np.stack([a, a, rng.uniform(1, 2, 30), np.zeros(30)], axis=1)
+    t = F @ np.array([1.0, 3.0, 2.0, 0.0]) + 0.0
+    got = L.perf_model_fit(F, t, relative=False)
+    ref = M.fit(F, t, relative=False)
+    assert got["rank"] == ref["rank"] == 2
+    np.testing.assert_allclose(got["p"], ref["p"], rtol=1e-9, atol=1e-12)
+    with pytest.raises(L.DGError):
+        L.perf_model_fit(F, -t, relative=True)
+    with pytest.raises(L.DGError):
+        L.perf_model_fit(np.full((2, 2), np.nan), np.ones(2))
