@@ -222,6 +222,22 @@ dg_status dgdiff_resolve_tile(dg_dtype in_t, int32_t nmat, int64_t nelem, int32_
 dg_status perf_model_fit(int32_t rows, int32_t cols, const double* F, const double* t,
                          int32_t relative, double* p, double* resid, int32_t* rank, double* cond);
 
+/* The paper's nonlinear overlap model (Sections "Modeling Operation Overlap"
+   and "Models Demonstrated").  group[j] puts feature j into the overhead (0),
+   global-memory (1) or on-chip (2) cost; with c_x = sum over group x of
+   p_j F[k][j]:
+       t_k ~ c_0 + c_1 s(c_1 - c_2) + c_2 s(c_2 - c_1),  s(x) = (tanh(edge x) + 1) / 2.
+   Fitted by Levenberg-Marquardt in FP64 on the relative (or absolute)
+   residual; every step is an augmented least-squares solve by SVD (no normal
+   equations).  On entry a non-zero p (e.g. a linear fit) and edge > 0 seed
+   the iteration; on exit they hold the fit.  *iters = iterations taken.     */
+dg_status perf_model_fit_overlap(int32_t rows, int32_t cols, const double* F, const int32_t* group,
+                                 const double* t, int32_t relative, double* p, double* edge,
+                                 double* resid, int32_t* iters);
+dg_status perf_model_predict_overlap(int32_t rows, int32_t cols, const double* F,
+                                     const int32_t* group, const double* p, double edge,
+                                     double* t_out);
+
 /* t_out[k] = sum_j F[k][j] p[j] (Section "Predicting Cost").               */
 dg_status perf_model_predict(int32_t rows, int32_t cols, const double* F, const double* p,
                              double* t_out);

@@ -65,3 +65,37 @@ def geomean_rel_err(pred, meas, floor: float = 1e-6):
     pred, meas = np.asarray(pred, np.float64), np.asarray(meas, np.float64)
     r = np.maximum(np.abs(pred - meas) / meas, floor)
     return float(np.exp(np.mean(np.log(r))))
+
+
+# ---------------------------------------------------------------- overlap model
+
+def overlap_predict(F, group, p, edge):
+    """Section "Modeling Operation Overlap": with c_x the cost of group x
+    (0 overhead, 1 global memory, 2 on-chip),
+    t = c_0 + c_1 s(c_1 - c_2) + c_2 s(c_2 - c_1),  s(x) = (tanh(edge x) + 1)/2."""
+    F = np.asarray(F, dtype=np.float64)
+    group = np.asarray(group)
+    p = np.asarray(p, dtype=np.float64)
+    c = [F[:, group == k] @ p[group == k] for k in (0, 1, 2)]
+
+    def s(x):
+        return (np.tanh(edge * x) + 1.0) / 2.0
+    return c[0] + c[1] * s(c[1] - c[2]) + c[2] * s(c[2] - c[1])
+
+
+def overlap_fit(F, t, group, p0, edge0):
+    """Relative least squares of the overlap model with a library nonlinear
+    least-squares routine (scipy.optimize.least_squares, trust region),
+    unknowns scaled by their starting magnitudes."""
+    from scipy.optimize import least_squares
+    F = np.asarray(F, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    x0 = np.concatenate([np.asarray(p0, dtype=np.float64), [edge0]])
+    scale = np.where(np.abs(x0) > 0, np.abs(x0), 1.0)
+
+    def res(z):
+        x = z * scale
+        return 1.0 - overlap_predict(F, group, x[:-1], x[-1]) / t
+    sol = least_squares(res, np.ones_like(x0), xtol=1e-15, ftol=1e-15, gtol=1e-15, max_nfev=20000)
+    x = sol.x * scale
+    return {"p": x[:-1], "edge": float(x[-1]), "resid": float(np.linalg.norm(sol.fun))}

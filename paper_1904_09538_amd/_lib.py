@@ -89,6 +89,12 @@ def _declare(L):
     _dp = ctypes.POINTER(ctypes.c_double)
     L.perf_model_fit.restype = _i32
     L.perf_model_fit.argtypes = [_i32, _i32, _dp, _dp, _i32, _dp, _dp, ctypes.POINTER(_i32), _dp]
+    L.perf_model_fit_overlap.restype = _i32
+    L.perf_model_fit_overlap.argtypes = [_i32, _i32, _dp, ctypes.POINTER(_i32), _dp, _i32, _dp, _dp,
+                                         _dp, ctypes.POINTER(_i32)]
+    L.perf_model_predict_overlap.restype = _i32
+    L.perf_model_predict_overlap.argtypes = [_i32, _i32, _dp, ctypes.POINTER(_i32), _dp,
+                                             ctypes.c_double, _dp]
     L.perf_model_predict.restype = _i32
     L.perf_model_predict.argtypes = [_i32, _i32, _dp, _dp, _dp]
     L.stencil5_apply.restype = _i32
@@ -291,6 +297,38 @@ def perf_model_predict(F, p):
     dp = ctypes.POINTER(ctypes.c_double)
     check(lib().perf_model_predict(F.shape[0], F.shape[1], F.ctypes.data_as(dp), p.ctypes.data_as(dp),
                                    out.ctypes.data_as(dp)))
+    return out
+
+
+def perf_model_fit_overlap(F, t, group, relative=True, p0=None, edge0=0.0):
+    """Nonlinear overlap model fit (LM, FP64); returns dict(p, edge, resid, iters)."""
+    import numpy as np
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    g = np.ascontiguousarray(group, dtype=np.int32)
+    rows, cols = F.shape
+    p = np.zeros(cols) if p0 is None else np.array(p0, dtype=np.float64)
+    edge = ctypes.c_double(edge0)
+    resid = ctypes.c_double()
+    iters = ctypes.c_int32()
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().perf_model_fit_overlap(rows, cols, F.ctypes.data_as(dp),
+                                       g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       t.ctypes.data_as(dp), int(relative), p.ctypes.data_as(dp),
+                                       ctypes.byref(edge), ctypes.byref(resid), ctypes.byref(iters)))
+    return {"p": p, "edge": edge.value, "resid": resid.value, "iters": iters.value}
+
+
+def perf_model_predict_overlap(F, group, p, edge):
+    import numpy as np
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    g = np.ascontiguousarray(group, dtype=np.int32)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros(F.shape[0])
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().perf_model_predict_overlap(F.shape[0], F.shape[1], F.ctypes.data_as(dp),
+                                           g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           p.ctypes.data_as(dp), float(edge), out.ctypes.data_as(dp)))
     return out
 
 

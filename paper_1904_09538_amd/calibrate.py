@@ -1,0 +1,309 @@
+"""Calibration of the black-box performance model on this GPU.
+
+Follows the paper's procedure (Sections "Other Features", "Computing Model
+Parameters", "Predicting Cost", "Results"): run a set of measurement kernels,
+record each one's wall time as the output feature and its counted operation
+features as inputs, fit the linear model t ~ sum_k p_k f_k with relative
+scaling, and predict held-out kernels.
+
+Timing protocol (the paper's wall-time feature): warm-up launches, then 60
+timed trials, each bracketed by HIP events on the launch stream (host-device
+transfer excluded).  Between trials a 512 MB scratch buffer is rewritten so
+that inputs do not stay resident in the 256 MB last-level cache ("cold"
+protocol).  Samples above 10x the median are dropped (the paper drops
+occasional ~10x anomalies seen on AMD hardware); the model input is the mean
+of the kept samples.
+
+Measurement set: the DG forward in FP32 for hexahedral orders p = 2..5
+(nunit 27, 64, 125, 216) at 2^16..2^21 elements with several launch shapes,
+the five-point stencil at n = 1024..16384, square matmul at n = 512..8192, and
+empty kernels with 16..65536 work-groups (launch and work-group costs).
+20% of each family's variants are held out (seeded) and scored by MAPE and
+by the geometric mean of relative error.
+
+Usage:
+  python -m paper_1904_09538_amd.calibrate --measure out.jsonl [--quick]
+  python -m paper_1904_09538_amd.calibrate --fit out.jsonl [--json summary.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+SEED_SPLIT = 4
+
+# model expressions: the features each family's model uses (the paper builds one
+# model per application, with global-memory, on-chip and overhead terms)
+# and the cost group of each feature (0 overhead, 1 global memory, 2 on-chip)
+GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0,
+         "gld_dg_u": 1, "gld_dg_u_l2": 1, "gld_dg_d": 1, "gst_dg_out": 1,
+         "gld_st_u": 1, "gst_st_res": 1, "gld_mm_ab": 1, "gst_mm_c": 1,
+         "lds_bytes": 2, "mfma_f64": 2, "mfma_f32": 2, "mfma_bf16": 2, "mfma_fp8": 2,
+         "valu_f32": 2, "valu_f64": 2}
+# the paper's choice: the overlap model for DG and matmul, the linear model for
+# the stencil (little overlap observed there)
+KIND = {"dg": "overlap", "stencil": "linear", "matmul": "overlap"}
+MODELS = {
+    "dg": ["launch", "workgroups", "gld_dg_u", "gld_dg_u_l2", "gld_dg_d", "gst_dg_out",
+           "lds_bytes", "mfma_f32"],
+    "stencil": ["launch", "workgroups", "gld_st_u", "gst_st_res", "lds_bytes", "valu_f32"],
+    "matmul": ["launch", "workgroups", "barrier_x_wg", "gld_mm_ab", "gst_mm_c", "lds_bytes",
+               "mfma_f32"],
+}
+
+
+# ------------------------------------------------------------------ variants
+
+def dg_variants(quick=False):
+    out = []
+    sizes = [16, 17, 18, 19, 20, 21] if not quick else [16, 18, 20]
+    for p in (2, 3, 4, 5):
+        n = (p + 1) ** 3
+        kq = -(-n // 4)
+        shapes = [dict(), dict(elems_per_wave=16), dict(elems_per_wave=32)]
+        if kq <= 32:
+            shapes.append(dict(elems_per_wave=64))
+        if p >= 4:
+            shapes.append(dict(elems_per_wave=16, d_panels=6))
+        else:
+            shapes.append(dict(elems_per_wave=32, waves=2))
+        for s in sizes:
+            for t in shapes:
+                out.append({"family": "dg", "p": p, "nunit": n, "nelem": 1 << s, "tile": t})
+    return out
+
+
+def stencil_variants(quick=False):
+    ns = [1024, 2048, 4096, 8192, 16384] if not quick else [1024, 4096, 16384]
+    return [{"family": "stencil", "n": n} for n in ns]
+
+
+def matmul_variants(quick=False):
+    ns = [512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192] if not quick else [512, 2048, 8192]
+    return [{"family": "matmul", "n": n} for n in ns]
+
+
+def empty_variants(quick=False):
+    return [{"family": "empty", "wgs": w} for w in (16, 64, 256, 1024, 4096, 16384, 65536)]
+
+
+# ------------------------------------------------------------------ timing
+
+def time_launch(fn, trials=60, warmup=5, flush=None):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    samples = []
+    for _ in range(trials):
+        if flush is not None:
+            flush.zero_()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        samples.append(e0.elapsed_time(e1) * 1e-3)
+    s = np.array(samples)
+    med = float(np.median(s))
+    kept = s[s <= 10 * med]
+    return {"mean": float(kept.mean()), "median": med, "min": float(s.min()),
+            "kept": int(kept.size), "dropped": int(s.size - kept.size)}
+
+
+def measure(path, quick=False, trials=60, families=("dg", "stencil", "matmul", "empty")):
+    import torch
+
+    from . import _lib, inputs
+
+    dev = torch.device("cuda:0")
+    flush = torch.empty(128 << 20, dtype=torch.float32, device=dev)  # 512 MB
+    rows = []
+    num_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    t_start = time.time()
+
+    def emit(row):
+        rows.append(row)
+        print(json.dumps({k: row[k] for k in row if k not in ("features",)}), flush=True)
+
+    if "dg" in families:
+        cache = {}
+        for v in dg_variants(quick):
+            n, E = v["nunit"], v["nelem"]
+            if n not in cache:
+                emax = max(w["nelem"] for w in dg_variants(quick) if w["nunit"] == n)
+                D = torch.from_numpy(inputs.gll_dmats(v["p"])).float().to(dev)
+                u = torch.from_numpy(inputs.uniform_u(emax, n).astype(np.float32)).to(dev)
+                out = torch.empty(3 * emax * n, device=dev)
+                cache.clear()
+                torch.cuda.empty_cache()
+                cache[n] = (D, u, out)
+            D, u, out = cache[n]
+            uv = u[:E]
+            ov = out[:3 * E * n].view(3, E, n)
+            tile = _lib.resolve_tile("f32", 3, E, n, v["tile"])
+            tm = time_launch(lambda: _lib.dgdiff_apply(D, uv, out=ov, tile=tile), trials, flush=flush)
+            feats = _lib.perf_features_count("dg", "f32", E, n, 3, tile, num_cu)
+            emit({**v, "tile": tile, "t": tm, "features": feats.tolist()})
+        cache.clear()
+    if "stencil" in families:
+        for v in stencil_variants(quick):
+            n = v["n"]
+            ld = ((n + 2 + 63) // 64) * 64
+            ug = torch.zeros((n + 2, ld), device=dev)
+            ug[:, :n + 2] = torch.from_numpy(inputs.stencil_grid(n).astype(np.float32)).to(dev)
+            res = torch.empty((n, n), device=dev)
+            tm = time_launch(lambda: _lib.stencil5_apply(ug, res=res, n=n), trials, flush=flush)
+            emit({**v, "t": tm, "features": _lib.perf_features_count("stencil", "f32", n).tolist()})
+            del ug, res
+    if "matmul" in families:
+        for v in matmul_variants(quick):
+            n = v["n"]
+            a, b = inputs.matmul_operands(n)
+            a = torch.from_numpy(a.astype(np.float32)).to(dev)
+            b = torch.from_numpy(b.astype(np.float32)).to(dev)
+            c = torch.empty((n, n), device=dev)
+            tm = time_launch(lambda: _lib.matmul_apply(a, b, c), trials if n < 8192 else 20,
+                             flush=flush)
+            emit({**v, "t": tm, "features": _lib.perf_features_count("matmul", "f32", n).tolist()})
+            del a, b, c
+    if "empty" in families:
+        for v in empty_variants(quick):
+            tm = time_launch(lambda: _lib.dg_empty_launch(v["wgs"]), trials, flush=None)
+            emit({**v, "t": tm, "features": _lib.perf_features_count("empty", "f32", v["wgs"]).tolist()})
+    meta = {"meta": True, "device": torch.cuda.get_device_name(0), "num_cu": num_cu,
+            "feature_names": _lib.feature_names(), "trials": trials, "protocol": "cold",
+            "seconds": time.time() - t_start}
+    with open(path, "w") as fh:
+        fh.write(json.dumps(meta) + "\n")
+        for r in rows:
+            fh.write(json.dumps(r) + "\n")
+    return meta, rows
+
+
+# ------------------------------------------------------------------ fit
+
+def load(path):
+    meta, rows = None, []
+    with open(path) as fh:
+        for line in fh:
+            r = json.loads(line)
+            if r.get("meta"):
+                meta = r
+            else:
+                rows.append(r)
+    return meta, rows
+
+
+def split_heldout(n, frac=0.2, seed=SEED_SPLIT):
+    rng = np.random.default_rng(seed)
+    k = int(math.ceil(frac * n))
+    perm = rng.permutation(n)
+    return np.sort(perm[k:]), np.sort(perm[:k])
+
+
+def mape(pred, meas):
+    pred, meas = np.asarray(pred), np.asarray(meas)
+    return float(np.mean(np.abs(pred - meas) / meas))
+
+
+def geomean(pred, meas):
+    r = np.maximum(np.abs(np.asarray(pred) - np.asarray(meas)) / np.asarray(meas), 1e-6)
+    return float(np.exp(np.mean(np.log(r))))
+
+
+def fit_family(meta, rows, family, L, kind=None, with_overhead_rows=True):
+    """Fit one family's model on its training rows (plus the empty-kernel rows,
+    which pin the launch and work-group costs) and score the held-out rows."""
+    kind = kind or KIND[family]
+    names = meta["feature_names"]
+    cols = [names.index(f) for f in MODELS[family]]
+    group = [GROUP[f] for f in MODELS[family]]
+    fam = [r for r in rows if r["family"] == family]
+    F = np.array([[r["features"][c] for c in cols] for r in fam], dtype=np.float64)
+    t = np.array([r["t"]["mean"] for r in fam])
+    train, held = split_heldout(len(fam))
+    Ftr, ttr = F[train], t[train]
+    if with_overhead_rows:
+        emp = [r for r in rows if r["family"] == "empty"]
+        if emp:
+            Fe = np.array([[r["features"][c] for c in cols] for r in emp], dtype=np.float64)
+            te = np.array([r["t"]["mean"] for r in emp])
+            Ftr = np.vstack([Ftr, Fe])
+            ttr = np.concatenate([ttr, te])
+    lin = L.perf_model_fit(Ftr, ttr, relative=True)
+    out = {"family": family, "kind": kind, "features": MODELS[family], "groups": group,
+           "n_train": int(len(train)), "n_heldout": int(len(held)),
+           "rank": lin["rank"], "cond": lin["cond"]}
+    if kind == "linear":
+        p, edge, resid = lin["p"], None, lin["resid"]
+        pred = L.perf_model_predict(F, p)
+    else:
+        fit = L.perf_model_fit_overlap(Ftr, ttr, group, relative=True, p0=lin["p"])
+        p, edge, resid = fit["p"], fit["edge"], fit["resid"]
+        out["iters"] = fit["iters"]
+        pred = L.perf_model_predict_overlap(F, group, p, edge)
+        lin_pred = L.perf_model_predict(F, lin["p"])
+        out["linear_mape_heldout"] = mape(lin_pred[held], t[held])
+    out.update({
+        "params": [float(x) for x in p], "edge": edge, "resid": resid,
+        "negative_params": [MODELS[family][k] for k in np.nonzero(np.asarray(p) < 0)[0]],
+        "mape_train": mape(pred[train], t[train]), "mape_heldout": mape(pred[held], t[held]),
+        "geomean_heldout": geomean(pred[held], t[held]),
+        "heldout": [{"variant": {k: fam[i][k] for k in fam[i] if k not in ("features", "t")},
+                     "measured_s": float(t[i]), "predicted_s": float(pred[i])} for i in held],
+    })
+    return out
+
+
+def fit_all(path, kinds=None):
+    from . import _lib
+    meta, rows = load(path)
+    out = {"device": meta["device"], "protocol": meta["protocol"], "families": {}}
+    for fam in MODELS:
+        if any(r["family"] == fam for r in rows):
+            out["families"][fam] = fit_family(meta, rows, fam, _lib, (kinds or {}).get(fam))
+    allp, allm = [], []
+    for f in out["families"].values():
+        allp += [h["predicted_s"] for h in f["heldout"]]
+        allm += [h["measured_s"] for h in f["heldout"]]
+    out["mape_heldout_all"] = mape(allp, allm) if allm else None
+    out["geomean_heldout_all"] = geomean(allp, allm) if allm else None
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--measure")
+    ap.add_argument("--fit")
+    ap.add_argument("--json")
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--trials", type=int, default=60)
+    ap.add_argument("--families", default="dg,stencil,matmul,empty")
+    a = ap.parse_args(argv)
+    if a.measure:
+        measure(a.measure, quick=a.quick, trials=a.trials, families=tuple(a.families.split(",")))
+    if a.fit:
+        s = fit_all(a.fit)
+        for fam, f in s["families"].items():
+            extra = (f"  (linear model: {100 * f['linear_mape_heldout']:.1f}%)"
+                     if "linear_mape_heldout" in f else "")
+            print(f"{fam} [{f['kind']}]: held-out MAPE {100 * f['mape_heldout']:.1f}%  geomean "
+                  f"{100 * f['geomean_heldout']:.1f}%  train MAPE {100 * f['mape_train']:.1f}%  "
+                  f"rank {f['rank']}/{len(f['features'])}  negative {f['negative_params']}{extra}")
+        print(f"all families: held-out MAPE {100 * s['mape_heldout_all']:.1f}%")
+        if a.json:
+            with open(a.json, "w") as fh:
+                json.dump(s, fh, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

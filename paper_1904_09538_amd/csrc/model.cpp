@@ -15,6 +15,7 @@
 //   4. undo the column scaling.
 // Reported: the residual norm at the solution (logged by the paper as a model
 // adequacy signal), numerical rank and condition number of the kept part.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -71,6 +72,63 @@ void jacobi_svd(std::vector<double>& A, int m, int n, std::vector<double>& V,
         sv[j] = std::sqrt(s);
     }
 }
+
+// Minimum-norm least-squares solve of A x = b (A m x n) by the Jacobi SVD
+// above, with column equilibration; returns the numerical rank.
+int lstsq(std::vector<double> A, int m, int n, const std::vector<double>& b, std::vector<double>& x) {
+    std::vector<double> cs(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double s = 0;
+        for (int k = 0; k < m; ++k) s += A[(size_t)k * n + j] * A[(size_t)k * n + j];
+        cs[j] = s > 0 ? 1.0 / std::sqrt(s) : 0.0;
+        for (int k = 0; k < m; ++k) A[(size_t)k * n + j] *= cs[j];
+    }
+    std::vector<double> V, sv;
+    jacobi_svd(A, m, n, V, sv);
+    double smax = 0;
+    for (double v : sv) smax = std::max(smax, v);
+    x.assign(n, 0.0);
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+        if (!(sv[j] > kRcond * smax) || smax == 0) continue;
+        ++r;
+        double utb = 0;
+        for (int k = 0; k < m; ++k) utb += A[(size_t)k * n + j] * b[k];
+        const double coef = utb / (sv[j] * sv[j]);
+        for (int i = 0; i < n; ++i) x[i] += V[(size_t)i * n + j] * coef;
+    }
+    for (int j = 0; j < n; ++j) x[j] *= cs[j];
+    return r;
+}
+
+// Overlap model (paper, Sections "Modeling Operation Overlap" and "Models
+// Demonstrated"): features are split into overhead (group 0), global memory
+// (group 1) and on-chip (group 2) costs,
+//     g = c_ovh + c_g s(c_g - c_o) + c_o s(c_o - c_g),   s(x) = (tanh(e x) + 1)/2,
+// which, with s(-x) = 1 - s(x), equals c_ovh + c_o + (c_g - c_o) s(c_g - c_o).
+struct Overlap {
+    int rows, cols;
+    const double* F;
+    const int32_t* group;
+    void costs(const double* p, int k, double* co, double* cg, double* cc) const {
+        double a = 0, b = 0, c = 0;
+        for (int j = 0; j < cols; ++j) {
+            const double v = p[j] * F[(size_t)k * cols + j];
+            if (group[j] == 0) a += v;
+            else if (group[j] == 1) b += v;
+            else c += v;
+        }
+        *co = a;
+        *cg = b;
+        *cc = c;
+    }
+    double eval(const double* p, double edge, int k) const {
+        double co, cg, cc;
+        costs(p, k, &co, &cg, &cc);
+        const double d = cg - cc;
+        return co + cc + d * 0.5 * (std::tanh(edge * d) + 1.0);
+    }
+};
 
 }  // namespace
 }  // namespace dg
@@ -135,6 +193,137 @@ dg_status perf_model_fit(int32_t rows, int32_t cols, const double* F, const doub
     }
     if (rank) *rank = r;
     if (cond) *cond = r ? smax / smin_kept : INFINITY;
+    return DG_OK;
+}
+
+dg_status perf_model_predict_overlap(int32_t rows, int32_t cols, const double* F,
+                                     const int32_t* group, const double* p, double edge,
+                                     double* t_out) {
+    set_error("");
+    if (rows < 0 || cols <= 0 || (rows > 0 && (!F || !group || !p || !t_out)))
+        return fail(DG_EINVAL, "perf_model_predict_overlap: bad arguments");
+    Overlap M{rows, cols, F, group};
+    for (int k = 0; k < rows; ++k) t_out[k] = M.eval(p, edge, k);
+    return DG_OK;
+}
+
+dg_status perf_model_fit_overlap(int32_t rows, int32_t cols, const double* F, const int32_t* group,
+                                 const double* t, int32_t relative, double* p, double* edge,
+                                 double* resid, int32_t* iters) {
+    set_error("");
+    if (rows <= 0 || cols <= 0 || !F || !group || !t || !p || !edge)
+        return fail(DG_EINVAL, "perf_model_fit_overlap: bad arguments");
+    for (int j = 0; j < cols; ++j)
+        if (group[j] < 0 || group[j] > 2) return fail(DG_EINVAL, "perf_model_fit_overlap: group");
+    for (int64_t k = 0; k < (int64_t)rows * cols; ++k)
+        if (!std::isfinite(F[k])) return fail(DG_EINVAL, "perf_model_fit_overlap: non-finite feature");
+    double tmed = 0;
+    {
+        std::vector<double> ts(t, t + rows);
+        for (double v : ts)
+            if (!(v > 0) || !std::isfinite(v)) return fail(DG_EINVAL, "perf_model_fit_overlap: t must be > 0");
+        std::nth_element(ts.begin(), ts.begin() + rows / 2, ts.end());
+        tmed = ts[rows / 2];
+    }
+    Overlap M{rows, cols, F, group};
+    const int np = cols + 1;  // parameters + edge
+    // Unknowns are scaled so that every one is O(1): p_j = q_j * sc_j with
+    // sc_j = 1 / ||f_j / t||, edge = q_e / tmed.
+    std::vector<double> sc(np);
+    for (int j = 0; j < cols; ++j) {
+        double s = 0;
+        for (int k = 0; k < rows; ++k) {
+            const double a = F[(size_t)k * cols + j] / (relative ? t[k] : 1.0);
+            s += a * a;
+        }
+        sc[j] = s > 0 ? 1.0 / std::sqrt(s) : 0.0;
+    }
+    sc[cols] = 1.0 / tmed;
+    std::vector<double> q(np);
+    // start: the caller's p if any entry is non-zero (e.g. a linear fit,
+    // magnitudes taken), else equal shares; edge = 5 / median(t)
+    bool given = false;
+    for (int j = 0; j < cols; ++j) given |= p[j] != 0.0;
+    for (int j = 0; j < cols; ++j)
+        q[j] = (given && sc[j] > 0) ? std::fabs(p[j]) / sc[j] : 1.0 / std::sqrt((double)cols);
+    q[cols] = (*edge > 0) ? *edge * tmed : 5.0;
+
+    auto residuals = [&](const std::vector<double>& qq, std::vector<double>& r) {
+        std::vector<double> pp(cols);
+        for (int j = 0; j < cols; ++j) pp[j] = qq[j] * sc[j];
+        const double e = qq[cols] * sc[cols];
+        double ss = 0;
+        for (int k = 0; k < rows; ++k) {
+            const double g = M.eval(pp.data(), e, k);
+            r[k] = relative ? 1.0 - g / t[k] : t[k] - g;
+            ss += r[k] * r[k];
+        }
+        return ss;
+    };
+    std::vector<double> r(rows), rn(rows), J((size_t)rows * np);
+    double cost = residuals(q, r);
+    double lambda = 1e-3;
+    int it = 0;
+    for (; it < 500; ++it) {
+        // Jacobian of the residual in the scaled unknowns
+        std::vector<double> pp(cols);
+        for (int j = 0; j < cols; ++j) pp[j] = q[j] * sc[j];
+        const double e = q[cols] * sc[cols];
+        for (int k = 0; k < rows; ++k) {
+            double co, cg, cc;
+            M.costs(pp.data(), k, &co, &cg, &cc);
+            const double d = cg - cc;
+            const double th = std::tanh(e * d);
+            const double s1 = 0.5 * (th + 1.0);
+            const double ds = 0.5 * e * (1.0 - th * th);  // s'(d)
+            const double dg_dcg = s1 + d * ds, dg_dcc = 1.0 - s1 - d * ds;
+            const double w = relative ? -1.0 / t[k] : -1.0;
+            for (int j = 0; j < cols; ++j) {
+                const double f = F[(size_t)k * cols + j];
+                const double dg = group[j] == 0 ? f : group[j] == 1 ? f * dg_dcg : f * dg_dcc;
+                J[(size_t)k * np + j] = w * dg * sc[j];
+            }
+            J[(size_t)k * np + cols] = w * (0.5 * d * d * (1.0 - th * th)) * sc[cols];
+        }
+        // Marquardt step: min || [J; sqrt(lambda) diag(|J_j|)] dq + [r; 0] ||
+        std::vector<double> dn(np);
+        for (int j = 0; j < np; ++j) {
+            double s = 0;
+            for (int k = 0; k < rows; ++k) s += J[(size_t)k * np + j] * J[(size_t)k * np + j];
+            dn[j] = std::sqrt(s);
+        }
+        bool improved = false;
+        for (int tries = 0; tries < 30 && !improved; ++tries) {
+            std::vector<double> A((size_t)(rows + np) * np, 0.0), b(rows + np, 0.0);
+            for (int k = 0; k < rows; ++k) {
+                for (int j = 0; j < np; ++j) A[(size_t)k * np + j] = J[(size_t)k * np + j];
+                b[k] = -r[k];
+            }
+            for (int j = 0; j < np; ++j) A[(size_t)(rows + j) * np + j] = std::sqrt(lambda) * (dn[j] > 0 ? dn[j] : 1.0);
+            std::vector<double> dq;
+            lstsq(A, rows + np, np, b, dq);
+            std::vector<double> qn(np);
+            for (int j = 0; j < np; ++j) qn[j] = q[j] + dq[j];
+            if (qn[cols] <= 0) qn[cols] = q[cols] * 0.5;  // the edge stays positive
+            const double cn = residuals(qn, rn);
+            if (std::isfinite(cn) && cn < cost) {
+                const double rel = (cost - cn) / std::max(cost, 1e-300);
+                q = qn;
+                r = rn;
+                cost = cn;
+                lambda = std::max(lambda / 3.0, 1e-12);
+                improved = true;
+                if (rel < 1e-12) it = 1 << 20;  // converged
+            } else {
+                lambda *= 4.0;
+            }
+        }
+        if (!improved) break;
+    }
+    for (int j = 0; j < cols; ++j) p[j] = q[j] * sc[j];
+    *edge = q[cols] * sc[cols];
+    if (resid) *resid = std::sqrt(cost);
+    if (iters) *iters = it;
     return DG_OK;
 }
 

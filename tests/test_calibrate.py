@@ -1,0 +1,66 @@
+"""Host logic of the calibration harness on synthetic timings (CPU only):
+a consistent linear timing law is recovered (held-out MAPE ~ 0), injected
+10x outliers are dropped by the timing rule, the held-out split is seeded and
+stratified per family."""
+import json
+
+import numpy as np
+
+from paper_1904_09538_amd import calibrate as C
+
+
+def _synthetic_rows(L, law):
+    names = L.feature_names()
+    rows = []
+    for v in C.dg_variants():
+        tile = dict(v["tile"])
+        tile.setdefault("elems_per_wave", 16)
+        tile.update(waves=4, groups_per_cu=2, d_panels=min(4, 3 * ((v["nunit"] + 15) // 16)))
+        f = L.perf_features_count("dg", "f32", v["nelem"], v["nunit"], 3, tile, 256)
+        rows.append({**v, "tile": tile, "features": f.tolist()})
+    for v in C.stencil_variants():
+        rows.append({**v, "features": L.perf_features_count("stencil", "f32", v["n"]).tolist()})
+    for v in C.matmul_variants():
+        rows.append({**v, "features": L.perf_features_count("matmul", "f32", v["n"]).tolist()})
+    for v in C.empty_variants():
+        rows.append({**v, "features": L.perf_features_count("empty", "f32", v["wgs"]).tolist()})
+    for r in rows:
+        f = dict(zip(names, r["features"]))
+        used = C.MODELS.get(r["family"], ["launch", "workgroups"])
+        r["t"] = {"mean": sum(law.get(k, 0.0) * f[k] for k in used)}
+    return {"meta": True, "device": "synthetic", "num_cu": 256, "feature_names": names,
+            "trials": 0, "protocol": "synthetic"}, rows
+
+
+def test_fit_recovers_linear_law(tmp_path):
+    from paper_1904_09538_amd import _lib as L
+    law = {"launch": 4e-6, "workgroups": 2e-9, "gld_dg_u": 1 / 5e12, "gld_dg_u_l2": 1 / 20e12,
+           "gld_dg_d": 1 / 30e12, "gst_dg_out": 1 / 6e12, "lds_bytes": 1 / 60e12,
+           "mfma_f32": 1 / 150e12, "gld_st_u": 1 / 5e12, "gst_st_res": 1 / 6e12,
+           "valu_f32": 1 / 50e12, "barrier_x_wg": 1e-9, "gld_mm_ab": 1 / 9e12, "gst_mm_c": 1 / 6e12}
+    meta, rows = _synthetic_rows(L, law)
+    path = tmp_path / "cal.jsonl"
+    with open(path, "w") as fh:
+        fh.write(json.dumps(meta) + "\n")
+        for r in rows:
+            fh.write(json.dumps(r) + "\n")
+    s = C.fit_all(str(path), kinds={"dg": "linear", "matmul": "linear"})
+    for fam in ("dg", "stencil", "matmul"):
+        assert s["families"][fam]["mape_heldout"] < 1e-6, fam
+    assert s["mape_heldout_all"] < 1e-6
+
+
+def test_heldout_split_is_seeded():
+    a = C.split_heldout(24)
+    b = C.split_heldout(24)
+    assert np.array_equal(a[0], b[0]) and len(a[1]) == 5
+    assert set(a[0]).isdisjoint(a[1]) and len(a[0]) + len(a[1]) == 24
+
+
+def test_outlier_rule_and_metrics():
+    s = np.array([1.0] * 59 + [12.0])
+    med = np.median(s)
+    kept = s[s <= 10 * med]
+    assert kept.size == 59
+    assert C.mape([1.1, 0.9], [1.0, 1.0]) == 0.1 or abs(C.mape([1.1, 0.9], [1.0, 1.0]) - 0.1) < 1e-12
+    assert abs(C.geomean([1.1, 1.2], [1.0, 1.0]) - np.sqrt(0.1 * 0.2)) < 1e-12

@@ -120,3 +120,24 @@ def test_fit_rank_deficient_and_errors(L):
         L.perf_model_fit(F, -t, relative=True)
     with pytest.raises(L.DGError):
         L.perf_model_fit(np.full((2, 2), np.nan), np.ones(2))
+
+
+def test_overlap_fit_matches_oracle(L):
+    """The library's Levenberg-Marquardt fit of the overlap model reaches the
+    same minimiser as the oracle's library least-squares routine."""
+    from oracle import model as M
+    rng = np.random.default_rng(12)
+    F = np.column_stack([np.ones(50), rng.integers(16, 4096, 50), rng.uniform(1e8, 1e10, 50),
+                         rng.uniform(1e8, 1e10, 50), rng.uniform(1e11, 1e13, 50)])
+    group = [0, 0, 1, 1, 2]
+    p_true = np.array([5e-6, 2e-9, 2e-13, 1.5e-13, 7e-15])
+    t = M.overlap_predict(F, group, p_true, 3e4) * rng.uniform(0.97, 1.03, 50)
+    p0 = p_true * rng.uniform(0.7, 1.4, 5)
+    a = L.perf_model_fit_overlap(F, t, group, p0=p0, edge0=2e4)
+    b = M.overlap_fit(F, t, group, p0, 2e4)
+    pa = L.perf_model_predict_overlap(F, group, a["p"], a["edge"])
+    pb = M.overlap_predict(F, group, b["p"], b["edge"])
+    assert abs(a["resid"] - b["resid"]) <= 1e-6 * b["resid"] + 1e-12
+    np.testing.assert_allclose(pa, pb, rtol=1e-5)
+    np.testing.assert_allclose(L.perf_model_predict_overlap(F, group, a["p"], a["edge"]),
+                               M.overlap_predict(F, group, a["p"], a["edge"]), rtol=1e-12)

@@ -65,3 +65,27 @@ def test_predict_mape_geomean():
     assert M.mape([1.1, 1.8], [1.0, 2.0]) == pytest.approx(0.1)
     assert M.geomean_rel_err([1.1, 1.8], [1.0, 2.0]) == pytest.approx(0.1)
     assert M.geomean_rel_err([1.0, 2.2], [1.0, 2.0]) == pytest.approx(math.sqrt(1e-6 * 0.1))
+
+
+def test_overlap_model_shape():
+    """The switched sum reduces to max(c_g, c_o) + c_ovh when the edge is sharp
+    and to the average of the two when the costs are equal."""
+    F = np.array([[1.0, 2.0, 5.0], [1.0, 6.0, 1.0], [1.0, 3.0, 3.0]])
+    group = [0, 1, 2]
+    p = [1.0, 1.0, 1.0]
+    t = M.overlap_predict(F, group, p, edge=1e6)
+    np.testing.assert_allclose(t, [1 + 5, 1 + 6, 1 + 3], rtol=1e-12)
+    t0 = M.overlap_predict(F, group, p, edge=0.0)
+    np.testing.assert_allclose(t0, [1 + 3.5, 1 + 3.5, 1 + 3], rtol=1e-12)
+
+
+def test_overlap_fit_recovers_law():
+    rng = np.random.default_rng(11)
+    F = np.column_stack([np.ones(40), rng.integers(16, 4096, 40), rng.uniform(1e8, 1e10, 40),
+                         rng.uniform(1e8, 1e10, 40), rng.uniform(1e11, 1e13, 40)])
+    group = [0, 0, 1, 1, 2]
+    p_true = np.array([5e-6, 2e-9, 2e-13, 1.5e-13, 7e-15])
+    edge_true = 3e4
+    t = M.overlap_predict(F, group, p_true, edge_true)
+    fit = M.overlap_fit(F, t, group, p_true * rng.uniform(0.7, 1.4, 5), edge_true * 0.6)
+    assert np.max(np.abs(M.overlap_predict(F, group, fit["p"], fit["edge"]) / t - 1)) < 1e-6
