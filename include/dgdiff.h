@@ -172,10 +172,10 @@ enum {
     PF_LAUNCH = 0,       /* kernel launches */
     PF_WORKGROUPS,       /* work-groups */
     PF_BARRIER_X_WG,     /* barriers met by one work-item x work-groups */
-    PF_GLD_DG_U,         /* DG element-data loads, bytes (first operator group) */
+    PF_GLD_DG_U,         /* DG element-data 16-byte vector loads, bytes (first operator group) */
     PF_GLD_DG_U_L2,      /* DG element-data re-loads by further operator groups (L2) */
     PF_GLD_DG_D,         /* DG operator loads while staging into LDS, bytes */
-    PF_GST_DG_OUT,       /* DG output stores, bytes */
+    PF_GST_DG_OUT,       /* DG output 16-byte vector stores, bytes */
     PF_GLD_ST_U,         /* stencil grid loads, bytes */
     PF_GST_ST_RES,       /* stencil result stores, bytes */
     PF_GLD_MM_AB,        /* matmul operand loads, bytes */
@@ -187,6 +187,9 @@ enum {
     PF_MFMA_FP8,
     PF_VALU_F32,         /* vector-ALU flops */
     PF_VALU_F64,
+    PF_GLD_DG_U_UNAL,    /* DG element-data loads on the unaligned-row paths, bytes */
+    PF_GST_DG_OUT_UNAL,  /* DG output stores of unaligned rows (scalar), bytes */
+    PF_WAVE_TILES,       /* DG element tiles processed by a wave, summed over operator groups */
     PF_COUNT
 };
 

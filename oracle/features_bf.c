@@ -24,7 +24,8 @@
 
 /* feature slots, in the order of the library's interface */
 enum { F_LAUNCH, F_WG, F_BAR, F_U, F_U_L2, F_D, F_OUT, F_ST_U, F_ST_RES, F_MM_AB, F_MM_C, F_LDS,
-       F_MFMA_F64, F_MFMA_F32, F_MFMA_BF16, F_MFMA_FP8, F_VALU_F32, F_VALU_F64, F_N };
+       F_MFMA_F64, F_MFMA_F32, F_MFMA_BF16, F_MFMA_FP8, F_VALU_F32, F_VALU_F64, F_U_UNAL, F_OUT_UNAL,
+       F_WAVE_TILES, F_N };
 
 enum { K_DG = 0, K_STENCIL = 1, K_MATMUL = 2, K_EMPTY = 3 };
 enum { T_F64 = 0, T_F32 = 1, T_BF16 = 2, T_FP8 = 3 };
@@ -101,11 +102,13 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
             c[F_LDS] += lowp ? el : sz;
         }
         c[F_BAR] += 1;
-        const int tag = pg == 0 ? F_U : F_U_L2;
+        /* element-data tag: re-reads by groups > 0, else by access path */
+        const int tag = pg != 0 ? F_U_L2 : vec_in ? F_U : F_U_UNAL;
         for (int64_t tile = stream; tile < ntiles; tile += nstreams) {
             for (int w = 0; w < waves; ++w) {
                 const int64_t e0 = tile * Te + (int64_t)w * 16 * cb;
                 if (e0 >= E) continue;
+                c[F_WAVE_TILES] += 1;
                 /* element data */
                 if (lowp) {
                     for (int q = 0; q < cb; ++q)
@@ -180,7 +183,7 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                                 if (i < n) c[F_OUT] += 4 * osz;
                             } else {
                                 for (int r = 0; r < 4; ++r)
-                                    if (i + r < n) c[F_OUT] += osz;
+                                    if (i + r < n) c[F_OUT_UNAL] += osz;
                             }
                         }
                 }

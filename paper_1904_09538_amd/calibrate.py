@@ -40,8 +40,9 @@ SEED_SPLIT = 4
 # model expressions: the features each family's model uses (the paper builds one
 # model per application, with global-memory, on-chip and overhead terms)
 # and the cost group of each feature (0 overhead, 1 global memory, 2 on-chip)
-GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0,
-         "gld_dg_u": 1, "gld_dg_u_l2": 1, "gld_dg_d": 1, "gst_dg_out": 1,
+GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0,
+         "gld_dg_u": 1, "gld_dg_u_unal": 1, "gld_dg_u_l2": 1, "gld_dg_d": 1, "gst_dg_out": 1,
+         "gst_dg_out_unal": 1,
          "gld_st_u": 1, "gst_st_res": 1, "gld_mm_ab": 1, "gst_mm_c": 1,
          "lds_bytes": 2, "mfma_f64": 2, "mfma_f32": 2, "mfma_bf16": 2, "mfma_fp8": 2,
          "valu_f32": 2, "valu_f64": 2}
@@ -49,8 +50,8 @@ GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0,
 # the stencil (little overlap observed there)
 KIND = {"dg": "overlap", "stencil": "linear", "matmul": "overlap"}
 MODELS = {
-    "dg": ["launch", "workgroups", "gld_dg_u", "gld_dg_u_l2", "gld_dg_d", "gst_dg_out",
-           "lds_bytes", "mfma_f32"],
+    "dg": ["launch", "workgroups", "wave_tiles", "gld_dg_u", "gld_dg_u_unal", "gld_dg_u_l2",
+           "gld_dg_d", "gst_dg_out", "gst_dg_out_unal", "lds_bytes", "mfma_f32"],
     "stencil": ["launch", "workgroups", "gld_st_u", "gst_st_res", "lds_bytes", "valu_f32"],
     "matmul": ["launch", "workgroups", "barrier_x_wg", "gld_mm_ab", "gst_mm_c", "lds_bytes",
                "mfma_f32"],

@@ -17,8 +17,12 @@
 //   - VALU flops: per lane that computes them;
 //   - barriers: per work-item (the paper's rule), multiplied by work-groups;
 //   - work-groups and kernel launches.
-// Loads of an element tile by the second and later operator groups of the DG
-// kernel are tagged separately (they are L2 re-reads, not HBM traffic).
+// Memory accesses are tagged by access pattern, as the paper does: DG element
+// data on the 16-byte vector path vs. the unaligned-row paths, output rows
+// stored as vectors vs. scalars, and loads of an element tile by the second
+// and later operator groups (L2 re-reads, not HBM traffic).  The number of
+// element tiles a wave processes (summed over operator groups) carries the
+// fixed per-tile latency.
 // A brute-force enumerator of the same schedule in the test oracle must give
 // identical int64 counts.
 #include "dg_kernel.hpp"
@@ -51,9 +55,10 @@ dg_status count_dg_fp(const perf_kernel_desc* d, int64_t* c) {
     c[PF_WORKGROUPS] = P.grid;
     c[PF_BARRIER_X_WG] = P.grid;  // one barrier after the operator staging
     c[PF_GLD_DG_D] = 8 * P.slots * (int64_t)M * n * n * (int64_t)sz;
-    c[PF_GLD_DG_U] = E * n * (int64_t)sz;
+    c[P.vec_in ? PF_GLD_DG_U : PF_GLD_DG_U_UNAL] = E * n * (int64_t)sz;
     c[PF_GLD_DG_U_L2] = (int64_t)(P.ngroups - 1) * E * n * (int64_t)sz;
-    c[PF_GST_DG_OUT] = E * M * n * (int64_t)sz;
+    c[n % 4 == 0 ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] = E * M * n * (int64_t)sz;
+    c[PF_WAVE_TILES] = nwt * P.ngroups;
     c[PF_LDS_BYTES] = 8 * P.slots * P.panels_total * 16 * KP * (int64_t)sz  // staging stores
                       + nwt * P.panels_total * 64 * kq * (int64_t)sz      // operand reads
                       + (P.use_slab ? (int64_t)P.ngroups * 2 * E * n * (int64_t)sz : 0);
@@ -76,9 +81,10 @@ dg_status count_dg_lowp(const perf_kernel_desc* d, int64_t* c) {
     c[PF_WORKGROUPS] = P.grid;
     c[PF_BARRIER_X_WG] = P.grid;
     c[PF_GLD_DG_D] = 8 * P.slots * (int64_t)M * n * n * eg;
-    c[PF_GLD_DG_U] = E * n * eg;
+    c[n % 8 == 0 ? PF_GLD_DG_U : PF_GLD_DG_U_UNAL] = E * n * eg;
     c[PF_GLD_DG_U_L2] = (int64_t)(P.ngroups - 1) * E * n * eg;
-    c[PF_GST_DG_OUT] = E * M * n * 4;
+    c[n % 4 == 0 ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] = E * M * n * 4;
+    c[PF_WAVE_TILES] = nwt * P.ngroups;
     c[PF_LDS_BYTES] = 8 * P.slots * P.panels_total * 16 * KP * P.lds_esz +
                       nwt * P.panels_total * P.ks * 64 * 8 * P.lds_esz;
     c[fmt == 1 ? PF_MFMA_FP8 : PF_MFMA_BF16] = nwt * P.panels_total * P.ks * (int64_t)P.cb * 16384;
@@ -129,7 +135,8 @@ dg_status count_matmul(const perf_kernel_desc* d, int64_t* c) {
 const char* kNames[PF_COUNT] = {
     "launch", "workgroups", "barrier_x_wg", "gld_dg_u", "gld_dg_u_l2", "gld_dg_d", "gst_dg_out",
     "gld_st_u", "gst_st_res", "gld_mm_ab", "gst_mm_c", "lds_bytes", "mfma_f64", "mfma_f32",
-    "mfma_bf16", "mfma_fp8", "valu_f32", "valu_f64"};
+    "mfma_bf16", "mfma_fp8", "valu_f32", "valu_f64", "gld_dg_u_unal", "gst_dg_out_unal",
+    "wave_tiles"};
 
 }  // namespace
 }  // namespace dg
