@@ -190,6 +190,7 @@ enum {
     PF_GLD_DG_U_UNAL,    /* DG element-data loads on the unaligned-row paths, bytes */
     PF_GST_DG_OUT_UNAL,  /* DG output stores of unaligned rows (scalar), bytes */
     PF_WAVE_TILES,       /* DG element tiles processed by a wave, summed over operator groups */
+    PF_SERIAL_STEPS,     /* longest chain of loop iterations one work-group walks (latency) */
     PF_COUNT
 };
 

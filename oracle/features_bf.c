@@ -25,7 +25,7 @@
 /* feature slots, in the order of the library's interface */
 enum { F_LAUNCH, F_WG, F_BAR, F_U, F_U_L2, F_D, F_OUT, F_ST_U, F_ST_RES, F_MM_AB, F_MM_C, F_LDS,
        F_MFMA_F64, F_MFMA_F32, F_MFMA_BF16, F_MFMA_FP8, F_VALU_F32, F_VALU_F64, F_U_UNAL, F_OUT_UNAL,
-       F_WAVE_TILES, F_N };
+       F_WAVE_TILES, F_SERIAL, F_N };
 
 enum { K_DG = 0, K_STENCIL = 1, K_MATMUL = 2, K_EMPTY = 3 };
 enum { T_F64 = 0, T_F32 = 1, T_BF16 = 2, T_FP8 = 3 };
@@ -104,7 +104,9 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
         c[F_BAR] += 1;
         /* element-data tag: re-reads by groups > 0, else by access path */
         const int tag = pg != 0 ? F_U_L2 : vec_in ? F_U : F_U_UNAL;
+        int64_t steps = 0;
         for (int64_t tile = stream; tile < ntiles; tile += nstreams) {
+            ++steps;
             for (int w = 0; w < waves; ++w) {
                 const int64_t e0 = tile * Te + (int64_t)w * 16 * cb;
                 if (e0 >= E) continue;
@@ -189,6 +191,7 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                 }
             }
         }
+        if (steps > c[F_SERIAL]) c[F_SERIAL] = steps;
     }
     return 0;
 }
@@ -215,6 +218,7 @@ static void stencil_walk(int dtype, int64_t n, int64_t* c) {
                     const int active = j0 < n;
                     const int self_halo = lane == 63 || j0 + 4 >= n;
                     const int64_t i_lo = by * R, i_hi = mini(n, i_lo + R);
+                    if (i_hi - i_lo > c[F_SERIAL]) c[F_SERIAL] = i_hi - i_lo;
                     /* rows i_lo .. i_hi+1 are loaded once each */
                     for (int64_t r = i_lo; r < i_hi + 2; ++r) {
                         if (active) c[F_ST_U] += 16;
@@ -235,6 +239,7 @@ static void stencil_walk(int dtype, int64_t n, int64_t* c) {
                 for (int t = 0; t < 256; ++t) {
                     const int64_t j = bx * 64 + (t & 63), i = by * 4 + (t >> 6);
                     if (i >= n || j >= n) continue;
+                    c[F_SERIAL] = 1;
                     c[F_ST_U] += 5 * sz;
                     c[F_ST_RES] += sz;
                     c[dtype == T_F64 ? F_VALU_F64 : F_VALU_F32] += 5;
@@ -253,6 +258,11 @@ static void matmul_walk(int64_t n, int64_t* c) {
         for (int64_t bx = 0; bx < g; ++bx) {
             const int64_t row0 = by * 128, col0 = bx * 128;
             c[F_BAR] += 1 + nk;   /* barriers one work-item meets, once per work-group */
+            {
+                int64_t steps = 0;
+                for (int64_t kc = 0; kc < nk; ++kc) ++steps;
+                if (steps > c[F_SERIAL]) c[F_SERIAL] = steps;
+            }
             for (int t = 0; t < 256; ++t) {
                 for (int64_t kc = 0; kc < nk; ++kc) {
                     const int64_t k0 = kc * 16;

@@ -15,9 +15,11 @@ occasional ~10x anomalies seen on AMD hardware); the model input is the mean
 of the kept samples.
 
 Measurement set: the DG forward in FP32 for hexahedral orders p = 2..5
-(nunit 27, 64, 125, 216) at 2^16..2^21 elements with several launch shapes,
-the five-point stencil at n = 1024..16384, square matmul at n = 512..8192, and
-empty kernels with 16..65536 work-groups (launch and work-group costs).
+(nunit 27, 64, 125, 216) at 2^16..2^21 elements with five launch shapes each,
+the five-point stencil at nine n in 1024..16384, square matmul at nine n in
+512..8192, and empty kernels with 16..65536 work-groups (launch and
+work-group costs).  The fitted models use the linear form for the stencil and
+the overlap form for DG and matmul, as the paper does.
 20% of each family's variants are held out (seeded) and scored by MAPE and
 by the geometric mean of relative error.
 
@@ -40,7 +42,7 @@ SEED_SPLIT = 4
 # model expressions: the features each family's model uses (the paper builds one
 # model per application, with global-memory, on-chip and overhead terms)
 # and the cost group of each feature (0 overhead, 1 global memory, 2 on-chip)
-GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0,
+GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0, "serial_steps": 0,
          "gld_dg_u": 1, "gld_dg_u_unal": 1, "gld_dg_u_l2": 1, "gld_dg_d": 1, "gst_dg_out": 1,
          "gst_dg_out_unal": 1,
          "gld_st_u": 1, "gst_st_res": 1, "gld_mm_ab": 1, "gst_mm_c": 1,
@@ -50,11 +52,11 @@ GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0,
 # the stencil (little overlap observed there)
 KIND = {"dg": "overlap", "stencil": "linear", "matmul": "overlap"}
 MODELS = {
-    "dg": ["launch", "workgroups", "wave_tiles", "gld_dg_u", "gld_dg_u_unal", "gld_dg_u_l2",
+    "dg": ["launch", "workgroups", "wave_tiles", "serial_steps", "gld_dg_u", "gld_dg_u_unal", "gld_dg_u_l2",
            "gld_dg_d", "gst_dg_out", "gst_dg_out_unal", "lds_bytes", "mfma_f32"],
     "stencil": ["launch", "workgroups", "gld_st_u", "gst_st_res", "lds_bytes", "valu_f32"],
-    "matmul": ["launch", "workgroups", "barrier_x_wg", "gld_mm_ab", "gst_mm_c", "lds_bytes",
-               "mfma_f32"],
+    "matmul": ["launch", "workgroups", "serial_steps", "barrier_x_wg", "gld_mm_ab", "gst_mm_c",
+               "lds_bytes", "mfma_f32"],
 }
 
 
@@ -80,7 +82,8 @@ def dg_variants(quick=False):
 
 
 def stencil_variants(quick=False):
-    ns = [1024, 2048, 4096, 8192, 16384] if not quick else [1024, 4096, 16384]
+    ns = ([1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384] if not quick
+          else [1024, 4096, 16384])
     return [{"family": "stencil", "n": n} for n in ns]
 
 

@@ -22,7 +22,9 @@
 // stored as vectors vs. scalars, and loads of an element tile by the second
 // and later operator groups (L2 re-reads, not HBM traffic).  The number of
 // element tiles a wave processes (summed over operator groups) carries the
-// fixed per-tile latency.
+// fixed per-tile latency; the longest chain of loop iterations one work-group
+// walks (its element tiles, k-chunks or strip rows) carries the latency of
+// launches too small to fill the GPU.
 // A brute-force enumerator of the same schedule in the test oracle must give
 // identical int64 counts.
 #include "dg_kernel.hpp"
@@ -59,6 +61,7 @@ dg_status count_dg_fp(const perf_kernel_desc* d, int64_t* c) {
     c[PF_GLD_DG_U_L2] = (int64_t)(P.ngroups - 1) * E * n * (int64_t)sz;
     c[n % 4 == 0 ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] = E * M * n * (int64_t)sz;
     c[PF_WAVE_TILES] = nwt * P.ngroups;
+    c[PF_SERIAL_STEPS] = ceil_div(P.ntiles, 8 * P.slots);  // tiles of the busiest stream
     c[PF_LDS_BYTES] = 8 * P.slots * P.panels_total * 16 * KP * (int64_t)sz  // staging stores
                       + nwt * P.panels_total * 64 * kq * (int64_t)sz      // operand reads
                       + (P.use_slab ? (int64_t)P.ngroups * 2 * E * n * (int64_t)sz : 0);
@@ -85,6 +88,7 @@ dg_status count_dg_lowp(const perf_kernel_desc* d, int64_t* c) {
     c[PF_GLD_DG_U_L2] = (int64_t)(P.ngroups - 1) * E * n * eg;
     c[n % 4 == 0 ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] = E * M * n * 4;
     c[PF_WAVE_TILES] = nwt * P.ngroups;
+    c[PF_SERIAL_STEPS] = ceil_div(P.ntiles, 8 * P.slots);
     c[PF_LDS_BYTES] = 8 * P.slots * P.panels_total * 16 * KP * P.lds_esz +
                       nwt * P.panels_total * P.ks * 64 * 8 * P.lds_esz;
     c[fmt == 1 ? PF_MFMA_FP8 : PF_MFMA_BF16] = nwt * P.panels_total * P.ks * (int64_t)P.cb * 16384;
@@ -108,11 +112,13 @@ dg_status count_stencil(const perf_kernel_desc* d, int64_t* c) {
         c[PF_GST_ST_RES] = n * A * 16;
         c[PF_LDS_BYTES] = rows_loaded * gx * 256 * 2 * 4;      // two shuffles per lane and row
         c[PF_VALU_F32] = n * gx * 256 * 20;                    // 4 outputs x 5 flops, every lane
+        c[PF_SERIAL_STEPS] = std::min(R, n);                   // rows of one strip
     } else {
         c[PF_WORKGROUPS] = ceil_div(n, 64) * ceil_div(n, 4);
         c[PF_GLD_ST_U] = n * n * 5 * (int64_t)sz;
         c[PF_GST_ST_RES] = n * n * (int64_t)sz;
         c[sz == 8 ? PF_VALU_F64 : PF_VALU_F32] = n * n * 5;
+        c[PF_SERIAL_STEPS] = 1;
     }
     return DG_OK;
 }
@@ -129,6 +135,7 @@ dg_status count_matmul(const perf_kernel_desc* d, int64_t* c) {
     c[PF_GST_MM_C] = 4 * n * n;
     c[PF_LDS_BYTES] = wg * nk * 256 * (64 + 128);  // chunk stores + operand reads
     c[PF_MFMA_F32] = wg * nk * 4 * 64 * 2048;
+    c[PF_SERIAL_STEPS] = nk;  // k-chunks of one work-group
     return DG_OK;
 }
 
@@ -136,7 +143,7 @@ const char* kNames[PF_COUNT] = {
     "launch", "workgroups", "barrier_x_wg", "gld_dg_u", "gld_dg_u_l2", "gld_dg_d", "gst_dg_out",
     "gld_st_u", "gst_st_res", "gld_mm_ab", "gst_mm_c", "lds_bytes", "mfma_f64", "mfma_f32",
     "mfma_bf16", "mfma_fp8", "valu_f32", "valu_f64", "gld_dg_u_unal", "gst_dg_out_unal",
-    "wave_tiles"};
+    "wave_tiles", "serial_steps"};
 
 }  // namespace
 }  // namespace dg
