@@ -1,12 +1,21 @@
 """Benchmark of the DG differentiation hot path on one MI355X.
 
-One step = one dgdiff_apply over the whole batch of elements (inputs resident
-in HBM before the timed region).  Default workload: FP32, hexahedral p = 3
-(nunit = 64), 3 GLL Kronecker operators, 2^21 elements, u ~ U(-1,1) seed 0.
+Headline (the JSON line's value): DG differentiation FP32, hexahedral p = 3
+(nunit = 64, the paper's DG configuration), 3 GLL Kronecker operators, 2^21
+elements (the largest point of the calibration suite), u ~ U(-1,1) seed 0.
+One step = one dgdiff_apply over all elements, inputs resident in HBM.
 
-Prints ONE JSON line with throughput (elements/s), the roofline position of
-the dominant kernel (timed live with HIP events on the launch stream) and the
-FP64 oracle timed on a bounded sample on the host.
+The same run measures every other row of the hot path and reports it under
+"rows": DG FP32 at p = 2..5; p = 5 at 2^20 elements with BF16 and FP8
+operands against FP32; the quantiser; the mixed-order batched launch against
+seven plain launches, with the model's predicted time; forward + adjoint at
+p = 4; the five-point stencil and matmul companions; and a live calibration
+of the performance model (held-out MAPE).
+
+Timing: HIP events on the launch stream over the timed steps (warm-up steps
+first); roofline positions use the algorithmic bytes and flops of one launch
+and the MI355X peaks (HBM 8 TB/s, FP32 matrix 157.3 TFLOP/s, BF16 2.5
+PFLOP/s, FP8 5.0 PFLOP/s, FP64 78.6 TFLOP/s).
 """
 from __future__ import annotations
 
@@ -22,20 +31,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "DG-diff elems/s & %roofline, BF16/FP8/batched vs FP32; perf-model MAPE"
-PEAK = {"hbm_GBs": 8000.0, "f32_TFLOPs": 157.3, "f64_TFLOPs": 78.6, "bf16_TFLOPs": 2500.0,
-        "fp8_TFLOPs": 5000.0}
-
-WORKLOADS = {
-    # name: (p, nelem, torch dtype name)
-    "dg_fp32_p3_2e21": (3, 1 << 21, "float32"),
-    "dg_fp32_p2_2e21": (2, 1 << 21, "float32"),
-    "dg_fp32_p4_2e21": (4, 1 << 21, "float32"),
-    "dg_fp32_p5_2e21": (5, 1 << 21, "float32"),
-    "dg_fp64_p3_4096": (3, 4096, "float64"),
-}
+PEAK = {"hbm": 8000.0, "f32": 157.3, "f64": 78.6, "bf16": 2500.0, "fp8": 5000.0}
+KERNEL_SOURCES = ["paper_1904_09538_amd/csrc/dg_kernel.hpp",
+                  "paper_1904_09538_amd/csrc/dg_forward.hip"]
 
 
-def kernel_source_hash(files):
+def log(*a):
+    print("bench:", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash(files=KERNEL_SOURCES):
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -43,28 +48,221 @@ def kernel_source_hash(files):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_key: str, src_hash: str):
+def load_traffic(key: str, src_hash: str):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
     was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
-        db = json.load(fh)
-    ent = db.get(kernel_key)
+        ent = json.load(fh).get(key)
     if not ent or ent.get("source_hash") != src_hash:
         return None
     return ent.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(D64, u_sample, nelem_sample):
+def timed(fn, steps, warmup):
+    """Average seconds per call, HIP events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / steps
+
+
+def roofline(alg_bytes, alg_flops, t, peak_key):
+    t_mem = alg_bytes / (PEAK["hbm"] * 1e9)
+    t_cmp = alg_flops / (PEAK[peak_key] * 1e12) if alg_flops else 0.0
+    if t_cmp >= t_mem:
+        r = {"bound": "mfma", "achieved": alg_flops / t / 1e12, "peak": PEAK[peak_key], "unit": "TFLOP/s"}
+    else:
+        r = {"bound": "hbm", "achieved": alg_bytes / t / 1e9, "peak": PEAK["hbm"], "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    return r
+
+
+def dg_bytes_flops(E, n, in_bytes, out_bytes, nmat=3):
+    return E * n * in_bytes + nmat * E * n * out_bytes + nmat * n * n * in_bytes, 2 * nmat * n * n * E
+
+
+# ------------------------------------------------------------------ rows
+
+def row_dg_orders(L, I, np, torch, steps):
+    out = {}
+    for p in (2, 3, 4, 5):
+        n, E = (p + 1) ** 3, 1 << 21
+        D = torch.from_numpy(I.gll_dmats(p)).float().cuda()
+        u = torch.from_numpy(I.uniform_u(E, n).astype(np.float32)).cuda()
+        o = torch.empty((3, E, n), device="cuda")
+        t = timed(lambda: L.dgdiff_apply(D, u, out=o), steps, 2)
+        b, f = dg_bytes_flops(E, n, 4, 4)
+        out[f"p{p}"] = {"nunit": n, "nelem": E, "ms": t * 1e3, "elements_per_s": E / t,
+                        "roofline": roofline(b, f, t, "f32")}
+        log(f"dg fp32 p={p}: {t * 1e3:.3f} ms")
+        del D, u, o
+        torch.cuda.empty_cache()
+    return out
+
+
+def row_lowp(L, I, np, torch, steps):
+    p, n, E = 5, 216, 1 << 20
+    D32 = I.gll_dmats(p).astype(np.float32)
+    u32 = torch.from_numpy(I.uniform_u(E, n).astype(np.float32)).cuda()
+    Dg = torch.from_numpy(D32).cuda()
+    o = torch.empty((3, E, n), device="cuda")
+    res = {}
+    t32 = timed(lambda: L.dgdiff_apply(Dg, u32, out=o), steps, 2)
+    b, f = dg_bytes_flops(E, n, 4, 4)
+    res["fp32"] = {"ms": t32 * 1e3, "elements_per_s": E / t32, "roofline": roofline(b, f, t32, "f32")}
+    ref = o.clone()
+    for name, to, flags in (("bf16", "bf16", 0), ("fp8", "e4m3", 0), ("fp8_native", "e4m3", 2)):
+        qD, isD = L.dgdiff_quantize(Dg.reshape(3, -1), to)
+        qu, isu = L.dgdiff_quantize(u32, to)
+        sc = dict(inv_sD=isD, inv_su=isu) if to == "e4m3" else {}
+        tile = dict(flags=flags) if flags else None
+        t = timed(lambda: L.dgdiff_apply(qD.view(3, n, n), qu, out=o, tile=tile, **sc), steps, 2)
+        eb = 2 if to == "bf16" else 1
+        b, f = dg_bytes_flops(E, n, eb, 4)
+        err = float(torch.linalg.vector_norm((o - ref).double()) / torch.linalg.vector_norm(ref.double()))
+        res[name] = {"ms": t * 1e3, "elements_per_s": E / t, "speedup_vs_fp32": t32 / t,
+                     "normwise_rel_err_vs_fp32": err,
+                     "roofline": roofline(b, f, t, "bf16" if name != "fp8_native" else "fp8")}
+        log(f"dg {name} p=5 2^20: {t * 1e3:.3f} ms ({t32 / t:.2f}x fp32)")
+    # the quantiser itself (element data, per-element power-of-two scales)
+    tq = timed(lambda: L.dgdiff_quantize(u32, "e4m3"), steps, 2)
+    res["quantize_u_fp8"] = {"ms": tq * 1e3, "GB_per_s": E * n * (4 + 1) / tq / 1e9,
+                             "roofline": roofline(E * n * 5 + E * 4, 0, tq, "f32")}
+    del u32, o, ref
+    torch.cuda.empty_cache()
+    return {"config": "hex p=5, 2^20 elements, FP32 output and accumulation", **res}
+
+
+def row_batched(L, I, np, torch, steps, model):
+    E = 1 << 20
+    order = I.batched_orders(E)
+    off = I.batched_offsets(order)
+    total = int(off[-1])
+    u = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, total).astype(np.float32)).cuda()
+    Ds = {p: torch.from_numpy(I.gll_dmats(p).astype(np.float32)).cuda() for p in range(1, 8)}
+    plan = L.BatchedPlan(order, model=model)
+    o = torch.empty((3, total), device="cuda")
+    tb = timed(lambda: plan.apply(Ds, u, out=o), steps, 2)
+    pred = sum(plan.info(p)["predicted_s"] for p in range(1, 8))
+    # baseline: seven plain launches on pre-grouped copies (grouping not timed)
+    groups = {}
+    for p in range(1, 8):
+        idx = np.nonzero(order == p)[0]
+        n = (p + 1) ** 3
+        if idx.size == 0:
+            continue
+        base = torch.from_numpy(off[idx].astype(np.int64)).cuda()
+        rows = (base[:, None] + torch.arange(n, device="cuda")[None, :]).reshape(-1)
+        ug = u[rows].view(idx.size, n).contiguous()
+        groups[p] = (ug, torch.empty((3, idx.size, n), device="cuda"))
+        del base, rows
+
+    def seven():
+        for p, (ug, og) in groups.items():
+            L.dgdiff_apply(Ds[p], ug, out=og)
+    t7 = timed(seven, steps, 2)
+    flops = sum(2 * 3 * ((p + 1) ** 3) ** 2 * int((order == p).sum()) for p in range(1, 8))
+    byts = 4 * 4 * total
+    res = {"nelem": E, "total_nodes": total, "ms": tb * 1e3, "elements_per_s": E / tb,
+           "roofline": roofline(byts, flops, tb, "f32"),
+           "seven_plain_launches_ms": t7 * 1e3, "speedup_vs_plain": t7 / tb,
+           "predicted_ms": pred * 1e3 if pred else None,
+           "model_rel_error": (pred - tb) / tb if pred else None,
+           "shapes": {p: plan.info(p)["tile"] for p in range(1, 8)}}
+    log(f"batched: {tb * 1e3:.3f} ms vs 7 launches {t7 * 1e3:.3f} ms, predicted {pred * 1e3:.3f} ms")
+    del u, o, groups
+    torch.cuda.empty_cache()
+    return res
+
+
+def row_adjoint(L, I, np, torch, steps):
+    p, n, E = 4, 125, 1 << 19
+    D = torch.from_numpy(I.gll_dmats(p).astype(np.float32)).cuda()
+    u = torch.from_numpy(I.uniform_u(E, n).astype(np.float32)).cuda()
+    g = torch.from_numpy(I.normal_g(3, E, n).astype(np.float32)).cuda()
+    o = torch.empty((3, E, n), device="cuda")
+    tf = timed(lambda: L.dgdiff_apply(D, u, out=o), steps, 2)
+    tbw = timed(lambda: L.dgdiff_backward(D, u, g), steps, 2)
+    flops_f = 2 * 3 * n * n * E
+    res = {"config": "hex p=4, 2^19 elements, FP32", "forward_ms": tf * 1e3, "backward_ms": tbw * 1e3,
+           "forward_roofline": roofline(E * n * 16, flops_f, tf, "f32"),
+           "backward_roofline": roofline(E * n * 4 * 5, 2 * flops_f, tbw, "f32")}
+    log(f"adjoint p=4: fwd {tf * 1e3:.3f} ms, bwd {tbw * 1e3:.3f} ms")
+    del D, u, g, o
+    torch.cuda.empty_cache()
+    return res
+
+
+def row_companions(L, I, np, torch, steps):
+    n = 16384
+    ug = torch.zeros((n + 2, n + 64), device="cuda")
+    ug[:, :n + 2] = torch.from_numpy(I.stencil_grid(n).astype(np.float32)).cuda()
+    r = torch.empty((n, n), device="cuda")
+    ts = timed(lambda: L.stencil5_apply(ug, res=r, n=n), steps, 2)
+    st = {"n": n, "ms": ts * 1e3, "points_per_s": n * n / ts,
+          "roofline": roofline(((n + 2) ** 2 + n * n) * 4, 5 * n * n, ts, "f32")}
+    del ug, r
+    m = 8192
+    a, b = I.matmul_operands(m)
+    a = torch.from_numpy(a.astype(np.float32)).cuda()
+    b = torch.from_numpy(b.astype(np.float32)).cuda()
+    c = torch.empty((m, m), device="cuda")
+    tm = timed(lambda: L.matmul_apply(a, b, c), max(3, steps // 5), 1)
+    mm = {"n": m, "ms": tm * 1e3, "roofline": roofline(12 * m * m, 2 * m ** 3, tm, "f32")}
+    log(f"stencil n={n}: {ts * 1e3:.3f} ms; matmul n={m}: {tm * 1e3:.3f} ms")
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"stencil5": st, "matmul": mm}
+
+
+def row_model(path):
+    import contextlib
+    from paper_1904_09538_amd import calibrate as C
+    with contextlib.redirect_stdout(sys.stderr):      # keep stdout to the one JSON line
+        C.measure(path, quick=False, trials=20)
+    s = C.fit_all(path)
+    fams = {k: {"kind": v["kind"], "mape_heldout": v["mape_heldout"],
+                "geomean_heldout": v["geomean_heldout"], "n_train": v["n_train"],
+                "n_heldout": v["n_heldout"]} for k, v in s["families"].items()}
+    return s, {"mape_heldout_all": s["mape_heldout_all"],
+               "geomean_heldout_all": s["geomean_heldout_all"], "families": fams,
+               "protocol": "cold cache, 20 event-timed trials per variant, 20% held out (seed 4)"}
+
+
+def model_vector(summary, names):
+    """DG model of a calibration summary as a per-feature cost vector."""
+    f = summary["families"]["dg"]
+    cost = [0.0] * len(names)
+    group = [0] * len(names)
+    from paper_1904_09538_amd import calibrate as C
+    for feat, p in zip(f["features"], f["params"]):
+        cost[names.index(feat)] = p
+        group[names.index(feat)] = C.GROUP[feat]
+    if f["kind"] == "linear":
+        return {"cost": cost, "group": None}
+    return {"cost": cost, "group": group, "edge": f["edge"]}
+
+
+def cpu_baseline(D64, u64):
     import oracle
     t0 = time.perf_counter()
-    oracle.dg_forward(D64, u_sample)
+    oracle.dg_forward(D64, u64)
     dt = time.perf_counter() - t0
-    return {"value": nelem_sample / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {nelem_sample} elements of the same input, FP64 single-threaded C, "
-                      f"{dt:.1f} s"}
+    E = u64.shape[0]
+    return {"value": E / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole workload ({E} elements), FP64 single-threaded C oracle, {dt:.1f} s"}
 
 
 def main():
@@ -72,101 +270,103 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="dg_fp32_p3_2e21", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=1 << 19,
-                    help="elements in the oracle's timed sample (0 = skip)")
+    ap.add_argument("--rows", default="all",
+                    help="comma list of extra rows (orders,lowp,batched,adjoint,companions,model) "
+                         "or 'all' or 'none'")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy three times: its FETCH_SIZE / "
                          "WRITE_SIZE counters calibrate the DG kernel's under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X; "
-              "sharding across GPUs is described in DESIGN.md, not launched.", file=sys.stderr)
+        print("bench.py measures one GPU: this build runs on a single MI355X; how the path would "
+              "shard over several GPUs is described in DESIGN.md, nothing is launched on more.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
 
-    from paper_1904_09538_amd import _lib, inputs
+    from paper_1904_09538_amd import _lib as L, inputs as I
 
-    p, nelem, dtn = WORKLOADS[args.workload]
-    dtype = getattr(torch, dtn)
-    nunit = inputs.nunit_of_order(p)
-    nmat = 3
     dev = torch.device("cuda:0")
-    print(f"bench: workload {args.workload} nunit={nunit} nelem={nelem} dtype={dtn}",
-          file=sys.stderr, flush=True)
-
     if args.copy_probe:
-        src = torch.ones(1 << 28, device=dev, dtype=torch.float32)
+        src = torch.ones(1 << 28, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
 
-    D64 = inputs.gll_dmats(p)
-    u64 = inputs.uniform_u(nelem, nunit)
-    D = torch.from_numpy(D64).to(dev, dtype)
-    u = torch.from_numpy(u64).to(dev, dtype)
-    out = torch.empty((nmat, nelem, nunit), device=dev, dtype=dtype)
-    torch.cuda.synchronize()
-
-    for _ in range(args.warmup):
-        _lib.dgdiff_apply(D, u, out=out)
-    torch.cuda.synchronize()
-
+    # ---- headline
+    p, E, nmat = 3, 1 << 21, 3
+    n = I.nunit_of_order(p)
+    log(f"headline: DG FP32 p={p} nunit={n} nelem={E}")
+    D64 = I.gll_dmats(p)
+    u64 = I.uniform_u(E, n)
+    D = torch.from_numpy(D64).float().to(dev)
+    u = torch.from_numpy(u64.astype(np.float32)).to(dev)
+    out = torch.empty((nmat, E, n), device=dev)
     stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        L.dgdiff_apply(D, u, out=out, stream=stream)
+    torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        _lib.dgdiff_apply(D, u, out=out, stream=stream)
+        L.dgdiff_apply(D, u, out=out, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    t = ev0.elapsed_time(ev1) * 1e-3 / args.steps
+    alg_bytes, alg_flops = dg_bytes_flops(E, n, 4, 4)
+    roof = roofline(alg_bytes, alg_flops, t, "f32")
+    src_hash = kernel_source_hash()
+    roof["traffic"] = load_traffic("dg_fwd_kernel:dg_fp32_p3_2e21", src_hash)
+    roof["kernel"] = "dg_kernel<float,16,1,1>"
+    log(f"headline: {t * 1e3:.3f} ms/step, {E / t:.3e} elements/s")
+    del D, u, out
+    torch.cuda.empty_cache()
 
-    esize = torch.finfo(dtype).bits // 8
-    bytes_per_elem = nunit * esize + nmat * nunit * esize
-    flops_per_elem = 2 * nmat * nunit * nunit
-    t = ms_per_step / 1e3
-    value = nelem / t
-    alg_bytes = nelem * bytes_per_elem + nmat * nunit * nunit * esize
-    alg_flops = nelem * flops_per_elem
-    peak_flops = PEAK["f32_TFLOPs" if dtype == torch.float32 else "f64_TFLOPs"]
-    t_mem = alg_bytes / (PEAK["hbm_GBs"] * 1e9)
-    t_cmp = alg_flops / (peak_flops * 1e12)
-    src_hash = kernel_source_hash(["paper_1904_09538_amd/csrc/dg_forward.hip"])
-    traffic = load_traffic(f"dg_fwd_kernel:{args.workload}", src_hash)
-    if t_cmp >= t_mem:
-        roof = {"bound": "mfma", "achieved": alg_flops / t / 1e12, "peak": peak_flops,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": alg_bytes / t / 1e9, "peak": PEAK["hbm_GBs"],
-                "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic
-    roof["kernel"] = "dg_fwd_kernel"
+    rows = {}
+    want = ["orders", "lowp", "batched", "adjoint", "companions", "model"] if args.rows == "all" else \
+        ([] if args.rows == "none" else args.rows.split(","))
+    small = max(5, args.steps // 5)
+    model_summary = None
+    if "model" in want:
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        model_summary, rows["model"] = row_model(os.path.join(ROOT, "gpurun_out", "bench_calibration.jsonl"))
+        log(f"model: held-out MAPE {100 * rows['model']['mape_heldout_all']:.1f}%")
+    if "orders" in want:
+        rows["dg_fp32_orders_2e21"] = row_dg_orders(L, I, np, torch, small)
+    if "lowp" in want:
+        rows["precision_p5_2e20"] = row_lowp(L, I, np, torch, small)
+    if "batched" in want:
+        mv = model_vector(model_summary, L.feature_names()) if model_summary else None
+        rows["batched_mixed_p1_7_2e20"] = row_batched(L, I, np, torch, small, mv)
+    if "adjoint" in want:
+        rows["adjoint_p4_2e19"] = row_adjoint(L, I, np, torch, small)
+    if "companions" in want:
+        rows.update(row_companions(L, I, np, torch, small))
 
     cpu = None
-    if args.cpu_sample > 0:
-        ns = min(args.cpu_sample, nelem)
-        cpu = cpu_baseline(D64.astype(np.float32).astype(np.float64) if dtype == torch.float32 else D64,
-                           u64[:ns], ns)
+    if args.cpu_baseline:
+        log("cpu baseline: FP64 oracle on the whole workload")
+        cpu = cpu_baseline(D64.astype(np.float32).astype(np.float64), u64.astype(np.float32).astype(np.float64))
 
     rec = {
-        "metric": METRIC, "value": value, "unit": "elements/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "metric": METRIC, "value": E / t, "unit": "elements/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if dtype == torch.float32 else "f64", "data": "synthetic",
-        "config": {"workload": f"DG differentiation {dtn}, hex p={p} (nunit={nunit}), "
-                               f"3 GLL Kronecker operators, {nelem} elements, u~U(-1,1) seed 0",
-                   "nelem": nelem, "nunit": nunit, "nmat": nmat},
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"DG differentiation FP32, hex p={p} (nunit={n}), 3 GLL Kronecker "
+                               f"operators, {E} elements, u~U(-1,1) seed 0",
+                   "nelem": E, "nunit": n, "nmat": nmat},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "rows": rows,
         "wall_s_timed": wall,
         "kernel_source_hash": src_hash,
     }

@@ -91,6 +91,37 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
                        const float* inv_sD, const float* inv_su,
                        const dg_tile* tile, dg_stream_t stream);
 
+/* Mixed-order DG differentiation in one persistent launch (FP32).
+   Element e has order p_e in 1..7 and n_e = (p_e+1)^3 nodes, stored ragged and
+   element-major: u_packed[off_e .. off_e + n_e) with off the exclusive prefix
+   sum of n_e; outputs at out_packed[m * total + off_e + i], total = sum_e n_e.
+   Per element the operation is the plain one with that order's operators.
+
+   dgdiff_plan_create: order [nelem] is a HOST array; nmat must be 3.
+     tiles [8] (HOST, indexed by order; NULL = choose): launch shape per order.
+     When tiles is NULL and model_cost [PF_COUNT] (HOST, seconds per feature
+     unit) is given, every candidate shape of every order is priced with the
+     model -- linear (model_group NULL) or the overlap form (model_group
+     [PF_COUNT] cost groups 0/1/2, model_edge) -- and the cheapest is taken;
+     the persistent grid is split across orders in proportion to predicted
+     time.  The plan owns device copies of the sorted element ids and the
+     offsets; it is immutable and may be used from several streams.
+   dgdiff_plan_info: order p's chosen shape, element count, work-groups and
+     predicted standalone time (0 without a model).
+   dgdiff_apply_batched: D_sets is a HOST array of 8 DEVICE pointers,
+     D_sets[p] = [3][(p+1)^3][(p+1)^3] FP32 (needed for every order present);
+     u_packed [total], out_packed [3][total] FP32.                            */
+typedef struct dg_plan dg_plan;
+dg_status dgdiff_plan_create(int64_t nelem, const int8_t* order, int32_t nmat, const dg_tile* tiles,
+                             const double* model_cost, const int32_t* model_group, double model_edge,
+                             dg_plan** out);
+int64_t dgdiff_plan_total_nodes(const dg_plan* plan);
+dg_status dgdiff_plan_info(const dg_plan* plan, int32_t p, dg_tile* tile, int64_t* count,
+                           int64_t* workgroups, double* predicted_s);
+dg_status dgdiff_apply_batched(const dg_plan* plan, const void* const* D_sets, const void* u_packed,
+                               void* out_packed, dg_stream_t stream);
+void dgdiff_plan_destroy(dg_plan* plan);
+
 /* Adjoint of dgdiff_apply (not part of the paper; the addition that makes
    the operator differentiable).  With g = dL/dout [nmat][nelem][nunit]:
        grad_u[e][j]    = sum_m sum_i D[m][i][j] g[m][e][i]     [nelem][nunit]

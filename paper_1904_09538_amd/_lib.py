@@ -77,6 +77,18 @@ def _declare(L):
                                   ctypes.c_size_t, _vp]
     L.dgdiff_quantize.restype = _i32
     L.dgdiff_quantize.argtypes = [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp]
+    L.dgdiff_plan_create.restype = _i32
+    L.dgdiff_plan_create.argtypes = [_i64, _vp, _i32, _vp, _vp, _vp, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+    L.dgdiff_plan_total_nodes.restype = _i64
+    L.dgdiff_plan_total_nodes.argtypes = [_vp]
+    L.dgdiff_plan_info.restype = _i32
+    L.dgdiff_plan_info.argtypes = [_vp, _i32, ctypes.POINTER(dg_tile), ctypes.POINTER(_i64),
+                                   ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
+    L.dgdiff_apply_batched.restype = _i32
+    L.dgdiff_apply_batched.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    L.dgdiff_plan_destroy.restype = None
+    L.dgdiff_plan_destroy.argtypes = [_vp]
     L.dg_empty_launch.restype = _i32
     L.dg_empty_launch.argtypes = [_i64, _vp]
     L.perf_feature_count.restype = _i32
@@ -334,3 +346,61 @@ def perf_model_predict_overlap(F, group, p, edge):
 
 def dg_empty_launch(workgroups, stream=None):
     check(lib().dg_empty_launch(int(workgroups), _stream(stream)))
+
+
+class BatchedPlan:
+    """Plan of the mixed-order persistent launch (owns device memory)."""
+
+    def __init__(self, order, tiles=None, model=None, nmat=3):
+        import numpy as np
+        order = np.ascontiguousarray(order, dtype=np.int8)
+        self.nelem = len(order)
+        tarr = None
+        if tiles is not None:
+            tarr = (dg_tile * 8)()
+            for p, t in tiles.items():
+                tarr[p] = dg_tile(*[int(t.get(k, 0)) for k in
+                                    ("elems_per_wave", "waves", "groups_per_cu", "d_panels", "flags")])
+        cost = group = None
+        edge = 0.0
+        if model is not None:
+            cost = np.ascontiguousarray(model["cost"], dtype=np.float64)
+            if model.get("group") is not None:
+                group = np.ascontiguousarray(model["group"], dtype=np.int32)
+                edge = float(model.get("edge", 0.0))
+        h = ctypes.c_void_p()
+        check(lib().dgdiff_plan_create(self.nelem, order.ctypes.data_as(ctypes.c_void_p), nmat,
+                                       ctypes.cast(tarr, ctypes.c_void_p) if tarr is not None else None,
+                                       cost.ctypes.data_as(ctypes.c_void_p) if cost is not None else None,
+                                       group.ctypes.data_as(ctypes.c_void_p) if group is not None else None,
+                                       edge, ctypes.byref(h)))
+        self._h = h
+        self.total = lib().dgdiff_plan_total_nodes(h)
+
+    def info(self, p):
+        t = dg_tile()
+        cnt = ctypes.c_int64()
+        wgs = ctypes.c_int64()
+        pred = ctypes.c_double()
+        check(lib().dgdiff_plan_info(self._h, p, ctypes.byref(t), ctypes.byref(cnt), ctypes.byref(wgs),
+                                     ctypes.byref(pred)))
+        return {"tile": {k: getattr(t, k) for k in ("elems_per_wave", "waves", "groups_per_cu",
+                                                    "d_panels", "flags")},
+                "count": cnt.value, "workgroups": wgs.value, "predicted_s": pred.value}
+
+    def apply(self, D_sets, u_packed, out=None, stream=None):
+        """D_sets: dict p -> [3][n][n] float32 device tensor."""
+        if out is None:
+            out = torch.empty((3, self.total), dtype=torch.float32, device=u_packed.device)
+        ptrs = (ctypes.c_void_p * 8)()
+        for p, D in D_sets.items():
+            ptrs[p] = D.data_ptr()
+        check(lib().dgdiff_apply_batched(self._h, ctypes.cast(ptrs, ctypes.c_void_p), _ptr(u_packed),
+                                         _ptr(out), _stream(stream)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dgdiff_plan_destroy(h)
+            self._h = None

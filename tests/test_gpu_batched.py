@@ -1,0 +1,121 @@
+"""GPU parity of the mixed-order persistent launch against the oracle's
+mixed-order form (FP32 tolerance 1e-5 normwise), for model-chosen and
+explicit launch shapes, single-order and empty batches, and at full size
+(2^20 elements, orders 1..7 with P(p) ~ 1/(p+1)) on sampled elements."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.metrics import normwise_rel
+from paper_1904_09538_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ops():
+    from paper_1904_09538_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+def _dsets(orders):
+    return {p: I.gll_dmats(p).astype(np.float32) for p in sorted(set(int(o) for o in orders))}
+
+
+def _run(ops, order, u32, D32, tiles=None, model=None):
+    plan = ops.BatchedPlan(order, tiles=tiles, model=model)
+    Dg = {p: torch.from_numpy(D).cuda() for p, D in D32.items()}
+    out = plan.apply(Dg, torch.from_numpy(u32).cuda())
+    torch.cuda.synchronize()
+    return plan, out.double().cpu().numpy()
+
+
+def _model_vector(ops):
+    """A plausible model (rates of the order of this GPU's) in feature order."""
+    names = ops.feature_names()
+    rate = {"launch": 7e-6, "workgroups": 1.6e-10, "wave_tiles": 1e-9, "serial_steps": 1e-7,
+            "gld_dg_u": 1 / 5e12, "gld_dg_u_unal": 1 / 2.5e12, "gld_dg_u_l2": 1 / 12e12,
+            "gld_dg_d": 1 / 12e12, "gst_dg_out": 1 / 6e12, "gst_dg_out_unal": 1 / 3e12,
+            "lds_bytes": 1 / 60e12, "mfma_f32": 1 / 120e12}
+    group = {"gld_dg_u": 1, "gld_dg_u_unal": 1, "gld_dg_u_l2": 1, "gld_dg_d": 1, "gst_dg_out": 1,
+             "gst_dg_out_unal": 1, "lds_bytes": 2, "mfma_f32": 2}
+    return {"cost": [rate.get(k, 0.0) for k in names], "group": [group.get(k, 0) for k in names],
+            "edge": 1e5}
+
+
+@pytest.mark.parametrize("with_model", [False, True])
+@pytest.mark.parametrize("nelem", [1, 37, 500, 3000])
+def test_batched_mixed_orders(orc, ops, nelem, with_model):
+    order = I.batched_orders(nelem, seed=2)
+    off = I.batched_offsets(order)
+    u32 = np.random.default_rng(0).uniform(-1, 1, int(off[-1])).astype(np.float32)
+    D32 = _dsets(range(1, 8))
+    plan, got = _run(ops, order, u32, D32, model=_model_vector(ops) if with_model else None)
+    ref = orc.dg_batched(order, off, {p: D.astype(np.float64) for p, D in D32.items()},
+                         u32.astype(np.float64))
+    assert plan.total == off[-1]
+    assert normwise_rel(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("tiles", [{p: dict(elems_per_wave=16) for p in range(1, 8)},
+                                   {p: dict(elems_per_wave=32 if p <= 4 else 16, d_panels=1)
+                                    for p in range(1, 8)}])
+def test_batched_explicit_tiles(orc, ops, tiles):
+    order = I.batched_orders(800, seed=5)
+    off = I.batched_offsets(order)
+    u32 = np.random.default_rng(1).uniform(-1, 1, int(off[-1])).astype(np.float32)
+    D32 = {p: I.random_dmats((p + 1) ** 3).astype(np.float32) for p in range(1, 8)}
+    _, got = _run(ops, order, u32, D32, tiles=tiles)
+    ref = orc.dg_batched(order, off, {p: D.astype(np.float64) for p, D in D32.items()},
+                         u32.astype(np.float64))
+    assert normwise_rel(got, ref) <= 1e-5
+
+
+def test_batched_single_order_equals_plain(ops):
+    """All elements of one order: the packed layout is the plain layout, and
+    the result matches dgdiff_apply on the same data."""
+    order = np.full(1000, 3, dtype=np.int8)
+    u = torch.from_numpy(I.uniform_u(1000, 64).astype(np.float32)).cuda()
+    D = torch.from_numpy(I.gll_dmats(3).astype(np.float32)).cuda()
+    plan = ops.BatchedPlan(order)
+    got = plan.apply({3: D}, u.reshape(-1))
+    ref = ops.dgdiff_apply(D, u).reshape(3, -1)
+    torch.cuda.synchronize()
+    assert normwise_rel(got.double().cpu().numpy(), ref.double().cpu().numpy()) <= 1e-6
+
+
+def test_batched_empty_and_bad_orders(ops):
+    plan = ops.BatchedPlan(np.zeros(0, dtype=np.int8))
+    assert plan.total == 0
+    with pytest.raises(ops.DGError):
+        ops.BatchedPlan(np.array([1, 9, 2], dtype=np.int8))
+
+
+def test_batched_full_size_sampled(orc, ops):
+    E = 1 << 20
+    order = I.batched_orders(E)
+    off = I.batched_offsets(order)
+    u32 = np.random.default_rng(0).uniform(-1, 1, int(off[-1])).astype(np.float32)
+    D32 = _dsets(range(1, 8))
+    plan, _ = None, None
+    plan = ops.BatchedPlan(order, model=_model_vector(ops))
+    Dg = {p: torch.from_numpy(D).cuda() for p, D in D32.items()}
+    out = plan.apply(Dg, torch.from_numpy(u32).cuda())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    sel = np.unique(np.concatenate([np.arange(8), np.arange(E - 8, E), rng.integers(0, E, 300)]))
+    errs = []
+    for e in sel:
+        p = int(order[e])
+        n = (p + 1) ** 3
+        ue = u32[off[e]:off[e] + n].astype(np.float64)[None, :]
+        ref = orc.dg_forward(D32[p].astype(np.float64), ue)[:, 0, :]
+        got = out[:, int(off[e]):int(off[e]) + n].double().cpu().numpy()
+        errs.append((np.max(np.abs(got - ref)), np.max(np.abs(ref))))
+    num = max(a for a, _ in errs)
+    den = max(b for _, b in errs)
+    assert num / den <= 1e-5
+    for p in range(1, 8):
+        info = plan.info(p)
+        assert info["count"] == int((order == p).sum()) and info["workgroups"] > 0
