@@ -244,30 +244,45 @@ dg_status perf_features_count(const perf_kernel_desc* d, int64_t* counts);
 dg_status dgdiff_resolve_tile(dg_dtype in_t, int32_t nmat, int64_t nelem, int32_t nunit,
                               dg_tile* tile);
 
+/* Flags of the model fits.  DG_FIT_RELATIVE: minimise the relative error
+   (the paper's scale_features_by_output, Section "Computing Model
+   Parameters").  DG_FIT_NONNEG: keep every cost parameter >= 0 (the paper's
+   interpretability criterion, Section "Assumptions and Limitations": a cost model that
+   needs negative weights is not one).                                       */
+#define DG_FIT_RELATIVE 1
+#define DG_FIT_NONNEG 2
+
 /* Fit a linear model t ~ F p (F [rows][cols] row-major FP64 features, t
-   [rows] seconds): the p [cols] minimising ||t - F p||_2, or with relative = 1
-   the relative error ||1 - diag(1/t) F p||_2 (the paper's
-   scale_features_by_output).  Columns are equilibrated, the system is solved
-   by an FP64 SVD (no normal equations), singular values below 1e-12 of the
-   largest are dropped and the minimum-norm solution is returned: a
-   rank-deficient F is not an error (*rank < cols).  *resid = residual norm
-   at the solution, *cond = condition number of the kept part.  Each output
-   pointer except p may be NULL.  DG_EINVAL: rows or cols <= 0, non-finite
-   input, or t <= 0 with relative = 1.                                       */
+   [rows] seconds): the p [cols] minimising ||t - F p||_2, or with
+   DG_FIT_RELATIVE the relative error ||1 - diag(1/t) F p||_2.  Columns are
+   equilibrated, the system is solved by an FP64 SVD (no normal equations),
+   singular values below 1e-12 of the largest are dropped and the
+   minimum-norm solution is returned: a rank-deficient F is not an error
+   (*rank < cols).  With DG_FIT_NONNEG, when that solution has a negative
+   entry, p is instead the non-negative least-squares minimiser of the same
+   equilibrated system (Lawson-Hanson active set).  *resid = residual norm at
+   the solution, *cond = condition number of the kept part of the
+   unconstrained system.  Each output pointer except p may be NULL.
+   DG_EINVAL: rows or cols <= 0, non-finite input, unknown flags, or t <= 0
+   with DG_FIT_RELATIVE.                                                     */
 dg_status perf_model_fit(int32_t rows, int32_t cols, const double* F, const double* t,
-                         int32_t relative, double* p, double* resid, int32_t* rank, double* cond);
+                         int32_t flags, double* p, double* resid, int32_t* rank, double* cond);
 
 /* The paper's nonlinear overlap model (Sections "Modeling Operation Overlap"
    and "Models Demonstrated").  group[j] puts feature j into the overhead (0),
    global-memory (1) or on-chip (2) cost; with c_x = sum over group x of
    p_j F[k][j]:
        t_k ~ c_0 + c_1 s(c_1 - c_2) + c_2 s(c_2 - c_1),  s(x) = (tanh(edge x) + 1) / 2.
-   Fitted by Levenberg-Marquardt in FP64 on the relative (or absolute)
-   residual; every step is an augmented least-squares solve by SVD (no normal
-   equations).  On entry a non-zero p (e.g. a linear fit) and edge > 0 seed
-   the iteration; on exit they hold the fit.  *iters = iterations taken.     */
+   Fitted by Levenberg-Marquardt in FP64 on the relative (DG_FIT_RELATIVE)
+   or absolute residual; every step is an augmented least-squares solve by SVD
+   (no normal equations).  With DG_FIT_NONNEG each step is projected onto
+   p >= 0, parameters held at zero while the gradient points out of the
+   orthant.  On entry a non-zero p (e.g. a linear fit; magnitudes are taken)
+   and edge > 0 seed the iteration; on exit they hold the fit.  *iters =
+   iterations taken.  DG_EINVAL: bad sizes, groups outside 0..2, unknown
+   flags, non-finite features or t <= 0.                                     */
 dg_status perf_model_fit_overlap(int32_t rows, int32_t cols, const double* F, const int32_t* group,
-                                 const double* t, int32_t relative, double* p, double* edge,
+                                 const double* t, int32_t flags, double* p, double* edge,
                                  double* resid, int32_t* iters);
 dg_status perf_model_predict_overlap(int32_t rows, int32_t cols, const double* F,
                                      const int32_t* group, const double* p, double edge,

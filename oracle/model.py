@@ -14,6 +14,14 @@ zero, and the minimum-norm solution is taken in the equilibrated coordinates;
 the parameters are then un-scaled.  A library SVD least-squares routine
 (numpy.linalg.lstsq) is the solve step.
 
+Non-negative fit (``nonneg=True``): the paper's interpretability criterion
+(Section "Assumptions and Limitations") rejects models whose fit needs negative
+weights, since extra work never lowers cost.  Then, if the unconstrained
+minimiser has a negative entry, the parameters are the non-negative
+least-squares minimiser of the same row-scaled, equilibrated system, with a
+library NNLS routine (scipy.optimize.nnls) as the solve step; the overlap fit
+passes the bounds p >= 0 to its library nonlinear solver.
+
 Prediction (Section "Predicting Cost"): t_hat = f . p for new feature rows.
 Error statistics: the mean absolute percentage error and the geometric mean of
 relative error (Section "Results").
@@ -25,7 +33,7 @@ import numpy as np
 RCOND = 1e-12
 
 
-def fit(F, t, relative: bool = True):
+def fit(F, t, relative: bool = True, nonneg: bool = False):
     """Returns dict(p, resid, rank, cond, negative)."""
     F = np.array(F, dtype=np.float64, copy=True)
     t = np.array(t, dtype=np.float64, copy=True)
@@ -44,6 +52,9 @@ def fit(F, t, relative: bool = True):
     scale = np.where(norms > 0, 1.0 / np.where(norms > 0, norms, 1.0), 0.0)
     As = A * scale[None, :]
     y, _, rank, sv = np.linalg.lstsq(As, b, rcond=RCOND)
+    if nonneg and np.any(y < 0):
+        from scipy.optimize import nnls
+        y = nnls(As, b, maxiter=50 * As.shape[1])[0]
     p = y * scale
     r = b - A @ p
     nz = sv[sv > RCOND * sv[0]] if sv.size and sv[0] > 0 else sv[:0]
@@ -83,19 +94,23 @@ def overlap_predict(F, group, p, edge):
     return c[0] + c[1] * s(c[1] - c[2]) + c[2] * s(c[2] - c[1])
 
 
-def overlap_fit(F, t, group, p0, edge0):
+def overlap_fit(F, t, group, p0, edge0, nonneg: bool = False):
     """Relative least squares of the overlap model with a library nonlinear
     least-squares routine (scipy.optimize.least_squares, trust region),
-    unknowns scaled by their starting magnitudes."""
+    unknowns scaled by their starting magnitudes; with nonneg the cost
+    parameters are bounded below by zero."""
     from scipy.optimize import least_squares
     F = np.asarray(F, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64)
-    x0 = np.concatenate([np.asarray(p0, dtype=np.float64), [edge0]])
+    x0 = np.concatenate([np.abs(np.asarray(p0, dtype=np.float64)) if nonneg
+                         else np.asarray(p0, dtype=np.float64), [edge0]])
     scale = np.where(np.abs(x0) > 0, np.abs(x0), 1.0)
 
     def res(z):
         x = z * scale
         return 1.0 - overlap_predict(F, group, x[:-1], x[-1]) / t
-    sol = least_squares(res, np.ones_like(x0), xtol=1e-15, ftol=1e-15, gtol=1e-15, max_nfev=20000)
+    lo = np.concatenate([np.zeros(x0.size - 1), [0.0]]) if nonneg else -np.inf
+    sol = least_squares(res, np.ones_like(x0), bounds=(lo, np.inf), xtol=1e-15, ftol=1e-15,
+                        gtol=1e-15, max_nfev=20000)
     x = sol.x * scale
     return {"p": x[:-1], "edge": float(x[-1]), "resid": float(np.linalg.norm(sol.fun))}

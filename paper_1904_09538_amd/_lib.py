@@ -283,8 +283,17 @@ def resolve_tile(dtype, nmat, nelem, nunit, tile=None):
     return {k: getattr(t, k) for k in ("elems_per_wave", "waves", "groups_per_cu", "d_panels", "flags")}
 
 
-def perf_model_fit(F, t, relative=True):
-    """FP64 least-squares fit; returns dict(p, resid, rank, cond)."""
+DG_FIT_RELATIVE = 1
+DG_FIT_NONNEG = 2
+
+
+def _fit_flags(relative, nonneg):
+    return (DG_FIT_RELATIVE if relative else 0) | (DG_FIT_NONNEG if nonneg else 0)
+
+
+def perf_model_fit(F, t, relative=True, nonneg=False):
+    """FP64 least-squares fit (non-negative with nonneg=True); returns
+    dict(p, resid, rank, cond, negative)."""
     import numpy as np
     F = np.ascontiguousarray(F, dtype=np.float64)
     t = np.ascontiguousarray(t, dtype=np.float64)
@@ -294,7 +303,8 @@ def perf_model_fit(F, t, relative=True):
     rank = ctypes.c_int32()
     cond = ctypes.c_double()
     dp = ctypes.POINTER(ctypes.c_double)
-    check(lib().perf_model_fit(rows, cols, F.ctypes.data_as(dp), t.ctypes.data_as(dp), int(relative),
+    check(lib().perf_model_fit(rows, cols, F.ctypes.data_as(dp), t.ctypes.data_as(dp),
+                               _fit_flags(relative, nonneg),
                                p.ctypes.data_as(dp), ctypes.byref(resid), ctypes.byref(rank),
                                ctypes.byref(cond)))
     return {"p": p, "resid": resid.value, "rank": rank.value, "cond": cond.value,
@@ -312,8 +322,9 @@ def perf_model_predict(F, p):
     return out
 
 
-def perf_model_fit_overlap(F, t, group, relative=True, p0=None, edge0=0.0):
-    """Nonlinear overlap model fit (LM, FP64); returns dict(p, edge, resid, iters)."""
+def perf_model_fit_overlap(F, t, group, relative=True, p0=None, edge0=0.0, nonneg=False):
+    """Nonlinear overlap model fit (LM, FP64; p >= 0 with nonneg=True);
+    returns dict(p, edge, resid, iters)."""
     import numpy as np
     F = np.ascontiguousarray(F, dtype=np.float64)
     t = np.ascontiguousarray(t, dtype=np.float64)
@@ -326,7 +337,8 @@ def perf_model_fit_overlap(F, t, group, relative=True, p0=None, edge0=0.0):
     dp = ctypes.POINTER(ctypes.c_double)
     check(lib().perf_model_fit_overlap(rows, cols, F.ctypes.data_as(dp),
                                        g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                       t.ctypes.data_as(dp), int(relative), p.ctypes.data_as(dp),
+                                       t.ctypes.data_as(dp), _fit_flags(relative, nonneg),
+                                       p.ctypes.data_as(dp),
                                        ctypes.byref(edge), ctypes.byref(resid), ctypes.byref(iters)))
     return {"p": p, "edge": edge.value, "resid": resid.value, "iters": iters.value}
 

@@ -15,6 +15,14 @@
 //   4. undo the column scaling.
 // Reported: the residual norm at the solution (logged by the paper as a model
 // adequacy signal), numerical rank and condition number of the kept part.
+//
+// Non-negative fit (DG_FIT_NONNEG).  The paper judges a model whose fit needs
+// negative weights inconsistent with the notion of cost (Section
+// "Assumptions and Limitations": interpretability).  With this flag the linear fit is the
+// non-negative least-squares minimiser, by the active-set method of Lawson and
+// Hanson (Solving Least Squares Problems, 1974, ch. 23) on the same row-scaled,
+// column-equilibrated system; the overlap fit keeps its cost parameters in the
+// non-negative orthant by an active-set projected Levenberg-Marquardt step.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -101,6 +109,85 @@ int lstsq(std::vector<double> A, int m, int n, const std::vector<double>& b, std
     return r;
 }
 
+// Non-negative least squares min ||A x - b||, x >= 0 (A m x n, columns
+// already equilibrated), by Lawson-Hanson: grow the passive set by the
+// variable of largest positive dual w = A^T (b - A x); solve the unconstrained
+// problem on the passive columns; if that leaves the orthant, step back to its
+// boundary along the segment and drop the variables that reached zero.
+void nnls(const std::vector<double>& A, int m, int n, const std::vector<double>& b,
+          std::vector<double>& x) {
+    x.assign(n, 0.0);
+    std::vector<char> passive(n, 0);
+    std::vector<double> w(n), s(n);
+    double anorm = 0;
+    for (double v : A) anorm = std::max(anorm, std::fabs(v));
+    double bnorm = 0;
+    for (double v : b) bnorm += v * v;
+    const double tol = 1e-13 * std::max(m, n) * std::max(anorm, 1.0) * std::sqrt(std::max(bnorm, 1.0));
+    auto dual = [&]() {
+        std::vector<double> r(b);
+        for (int k = 0; k < m; ++k)
+            for (int j = 0; j < n; ++j) r[k] -= A[(size_t)k * n + j] * x[j];
+        for (int j = 0; j < n; ++j) {
+            double v = 0;
+            for (int k = 0; k < m; ++k) v += A[(size_t)k * n + j] * r[k];
+            w[j] = v;
+        }
+    };
+    // solve on the passive columns (the rest held at zero)
+    auto solve_passive = [&]() {
+        std::vector<int> cols;
+        for (int j = 0; j < n; ++j)
+            if (passive[j]) cols.push_back(j);
+        const int c = (int)cols.size();
+        std::vector<double> Ap((size_t)m * c), y;
+        for (int k = 0; k < m; ++k)
+            for (int q = 0; q < c; ++q) Ap[(size_t)k * c + q] = A[(size_t)k * n + cols[q]];
+        lstsq(Ap, m, c, b, y);
+        std::fill(s.begin(), s.end(), 0.0);
+        for (int q = 0; q < c; ++q) s[cols[q]] = y[q];
+    };
+    for (int outer = 0; outer < 3 * n + 10; ++outer) {
+        dual();
+        int t = -1;
+        double wmax = tol;
+        for (int j = 0; j < n; ++j)
+            if (!passive[j] && w[j] > wmax) {
+                wmax = w[j];
+                t = j;
+            }
+        if (t < 0) break;
+        passive[t] = 1;
+        for (int inner = 0; inner < 3 * n + 10; ++inner) {
+            solve_passive();
+            bool feasible = true;
+            for (int j = 0; j < n; ++j)
+                if (passive[j] && s[j] <= 0) feasible = false;
+            if (feasible) {
+                x = s;
+                break;
+            }
+            double alpha = 1.0;
+            int hit = -1;
+            for (int j = 0; j < n; ++j)
+                if (passive[j] && s[j] <= 0) {
+                    const double a = x[j] / (x[j] - s[j]);
+                    if (hit < 0 || a < alpha) {
+                        alpha = a;
+                        hit = j;
+                    }
+                }
+            for (int j = 0; j < n; ++j) x[j] += alpha * (s[j] - x[j]);
+            x[hit] = 0.0;  // the blocking variable lands on the boundary exactly
+            for (int j = 0; j < n; ++j)
+                if (passive[j] && x[j] <= 0.0) {
+                    passive[j] = 0;
+                    x[j] = 0.0;
+                }
+        }
+    }
+}
+
 // Overlap model (paper, Sections "Modeling Operation Overlap" and "Models
 // Demonstrated"): features are split into overhead (group 0), global memory
 // (group 1) and on-chip (group 2) costs,
@@ -138,8 +225,10 @@ using namespace dg;
 extern "C" {
 
 dg_status perf_model_fit(int32_t rows, int32_t cols, const double* F, const double* t,
-                         int32_t relative, double* p, double* resid, int32_t* rank, double* cond) {
+                         int32_t flags, double* p, double* resid, int32_t* rank, double* cond) {
     set_error("");
+    const bool relative = flags & DG_FIT_RELATIVE, nonneg = flags & DG_FIT_NONNEG;
+    if (flags & ~(DG_FIT_RELATIVE | DG_FIT_NONNEG)) return fail(DG_EINVAL, "perf_model_fit: unknown flags");
     if (rows <= 0 || cols <= 0 || !F || !t || !p) return fail(DG_EINVAL, "perf_model_fit: bad arguments");
     for (int64_t k = 0; k < (int64_t)rows * cols; ++k)
         if (!std::isfinite(F[k])) return fail(DG_EINVAL, "perf_model_fit: non-finite feature");
@@ -181,6 +270,15 @@ dg_status perf_model_fit(int32_t rows, int32_t cols, const double* F, const doub
         const double coef = utb / sv[j];
         for (int i = 0; i < cols; ++i) y[i] += V[(size_t)i * cols + j] * coef;
     }
+    bool any_negative = false;
+    for (int j = 0; j < cols; ++j) any_negative |= y[j] < 0;
+    if (nonneg && any_negative) {
+        // A still holds the rotated columns; rebuild the equilibrated matrix
+        std::vector<double> Ae((size_t)rows * cols);
+        for (int k = 0; k < rows; ++k)
+            for (int j = 0; j < cols; ++j) Ae[(size_t)k * cols + j] = A0[(size_t)k * cols + j] * cs[j];
+        nnls(Ae, rows, cols, b, y);
+    }
     for (int j = 0; j < cols; ++j) p[j] = y[j] * cs[j];
     if (resid) {
         double s = 0;
@@ -208,9 +306,12 @@ dg_status perf_model_predict_overlap(int32_t rows, int32_t cols, const double* F
 }
 
 dg_status perf_model_fit_overlap(int32_t rows, int32_t cols, const double* F, const int32_t* group,
-                                 const double* t, int32_t relative, double* p, double* edge,
+                                 const double* t, int32_t flags, double* p, double* edge,
                                  double* resid, int32_t* iters) {
     set_error("");
+    const bool relative = flags & DG_FIT_RELATIVE, nonneg = flags & DG_FIT_NONNEG;
+    if (flags & ~(DG_FIT_RELATIVE | DG_FIT_NONNEG))
+        return fail(DG_EINVAL, "perf_model_fit_overlap: unknown flags");
     if (rows <= 0 || cols <= 0 || !F || !group || !t || !p || !edge)
         return fail(DG_EINVAL, "perf_model_fit_overlap: bad arguments");
     for (int j = 0; j < cols; ++j)
@@ -264,6 +365,7 @@ dg_status perf_model_fit_overlap(int32_t rows, int32_t cols, const double* F, co
     double cost = residuals(q, r);
     double lambda = 1e-3;
     int it = 0;
+    bool converged = false;
     for (; it < 500; ++it) {
         // Jacobian of the residual in the scaled unknowns
         std::vector<double> pp(cols);
@@ -292,6 +394,18 @@ dg_status perf_model_fit_overlap(int32_t rows, int32_t cols, const double* F, co
             for (int k = 0; k < rows; ++k) s += J[(size_t)k * np + j] * J[(size_t)k * np + j];
             dn[j] = std::sqrt(s);
         }
+        if (nonneg) {
+            // a cost parameter at zero whose descent direction points out of
+            // the orthant (gradient J^T r > 0 there) is held: its column is
+            // cleared, so the damping row alone fixes its step to zero
+            for (int j = 0; j < cols; ++j) {
+                if (q[j] > 0) continue;
+                double gj = 0;
+                for (int k = 0; k < rows; ++k) gj += J[(size_t)k * np + j] * r[k];
+                if (gj >= 0)
+                    for (int k = 0; k < rows; ++k) J[(size_t)k * np + j] = 0.0;
+            }
+        }
         bool improved = false;
         for (int tries = 0; tries < 30 && !improved; ++tries) {
             std::vector<double> A((size_t)(rows + np) * np, 0.0), b(rows + np, 0.0);
@@ -305,6 +419,8 @@ dg_status perf_model_fit_overlap(int32_t rows, int32_t cols, const double* F, co
             std::vector<double> qn(np);
             for (int j = 0; j < np; ++j) qn[j] = q[j] + dq[j];
             if (qn[cols] <= 0) qn[cols] = q[cols] * 0.5;  // the edge stays positive
+            if (nonneg)
+                for (int j = 0; j < cols; ++j) qn[j] = std::max(qn[j], 0.0);
             const double cn = residuals(qn, rn);
             if (std::isfinite(cn) && cn < cost) {
                 const double rel = (cost - cn) / std::max(cost, 1e-300);
@@ -313,12 +429,15 @@ dg_status perf_model_fit_overlap(int32_t rows, int32_t cols, const double* F, co
                 cost = cn;
                 lambda = std::max(lambda / 3.0, 1e-12);
                 improved = true;
-                if (rel < 1e-12) it = 1 << 20;  // converged
+                if (rel < 1e-12) converged = true;
             } else {
                 lambda *= 4.0;
             }
         }
-        if (!improved) break;
+        if (!improved || converged) {
+            ++it;
+            break;
+        }
     }
     for (int j = 0; j < cols; ++j) p[j] = q[j] * sc[j];
     *edge = q[cols] * sc[cols];

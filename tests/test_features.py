@@ -2,6 +2,7 @@
 enumeration of the same documented schedules (bit-exact int64), the paper's
 worked point-count example, and the library's FP64 model fit against the
 oracle fit (CPU only)."""
+import ctypes
 import itertools
 
 import numpy as np
@@ -141,3 +142,59 @@ def test_overlap_fit_matches_oracle(L):
     np.testing.assert_allclose(pa, pb, rtol=1e-5)
     np.testing.assert_allclose(L.perf_model_predict_overlap(F, group, a["p"], a["edge"]),
                                M.overlap_predict(F, group, a["p"], a["edge"]), rtol=1e-12)
+
+
+def _neg_linear_case(seed):
+    """A law whose last feature nearly duplicates another and enters with a
+    negative weight: the unconstrained fit goes below zero there."""
+    rng = np.random.default_rng(seed)
+    F = rng.uniform(1.0, 10.0, size=(40, 5)) * np.array([1.0, 1e3, 1e6, 1e9, 1e6])
+    F[:, 4] = 0.9 * F[:, 2] + rng.uniform(0, 3e5, 40)
+    t = F[:, :4] @ np.array([5e-6, 1e-9, 2e-12, 3e-15]) - 5e-13 * F[:, 4]
+    return F, t * rng.uniform(0.97, 1.03, 40)
+
+
+@pytest.mark.parametrize("seed", [5, 6, 7, 10])
+@pytest.mark.parametrize("rel", [True, False])
+def test_nonneg_fit_matches_oracle(L, seed, rel):
+    """Lawson-Hanson NNLS in the library against the oracle's library NNLS,
+    on systems whose unconstrained fit has a negative weight."""
+    from oracle import model as M
+    F, t = _neg_linear_case(seed)
+    assert M.fit(F, t, relative=rel)["negative"]
+    a = L.perf_model_fit(F, t, relative=rel, nonneg=True)
+    b = M.fit(F, t, relative=rel, nonneg=True)
+    assert np.all(a["p"] >= 0) and not a["negative"]
+    np.testing.assert_allclose(a["p"], b["p"], rtol=1e-8, atol=1e-12 * np.max(np.abs(b["p"])))
+    assert abs(a["resid"] - b["resid"]) <= 1e-9 * max(1.0, b["resid"])
+    # unconstrained entry point unchanged by the flag's existence
+    np.testing.assert_allclose(L.perf_model_fit(F, t, relative=rel)["p"],
+                               M.fit(F, t, relative=rel)["p"], rtol=1e-9)
+    with pytest.raises(L.DGError):           # unknown flag bit
+        f1 = np.ones(1)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.check(L.lib().perf_model_fit(1, 1, f1.ctypes.data_as(dp), f1.ctypes.data_as(dp), 8,
+                                       np.zeros(1).ctypes.data_as(dp), None, None, None))
+
+
+def test_overlap_fit_nonneg_matches_oracle(L):
+    """Projected LM against the oracle's bounded trust-region fit when the
+    data pull one cost parameter below zero: both stay in the orthant and
+    reach the same residual."""
+    from oracle import model as M
+    rng = np.random.default_rng(14)
+    F = np.column_stack([np.ones(50), rng.integers(16, 4096, 50), rng.uniform(1e8, 1e10, 50),
+                         rng.uniform(1e8, 1e10, 50), rng.uniform(1e10, 1e12, 50)])
+    group = [0, 0, 1, 1, 2]
+    p_true = np.array([5e-6, 0.0, 2e-13, 1.5e-13, 7e-15])
+    t = M.overlap_predict(F, group, p_true, 1e3) - 3e-10 * F[:, 1]
+    t = np.abs(t * rng.uniform(0.97, 1.03, 50))
+    p0 = np.array([5e-6, 1e-9, 2e-13, 1.5e-13, 7e-15]) * rng.uniform(0.7, 1.4, 5)
+    un = L.perf_model_fit_overlap(F, t, group, p0=p0, edge0=2e3)
+    assert np.any(un["p"] < 0)
+    a = L.perf_model_fit_overlap(F, t, group, p0=p0, edge0=2e3, nonneg=True)
+    b = M.overlap_fit(F, t, group, p0, 2e3, nonneg=True)
+    assert np.all(a["p"] >= 0) and np.all(b["p"] >= 0)
+    assert abs(a["resid"] - b["resid"]) <= 1e-8 * b["resid"]
+    np.testing.assert_allclose(L.perf_model_predict_overlap(F, group, a["p"], a["edge"]),
+                               M.overlap_predict(F, group, b["p"], b["edge"]), rtol=1e-6)

@@ -89,3 +89,77 @@ def test_overlap_fit_recovers_law():
     t = M.overlap_predict(F, group, p_true, edge_true)
     fit = M.overlap_fit(F, t, group, p_true * rng.uniform(0.7, 1.4, 5), edge_true * 0.6)
     assert np.max(np.abs(M.overlap_predict(F, group, fit["p"], fit["edge"]) / t - 1)) < 1e-6
+
+
+def _nnls_brute_force(A, b):
+    """Exact NNLS of a tiny system: over every support set S, the
+    unconstrained least-squares solution on S, kept if it is >= 0; the
+    feasible one of least residual is the minimiser (the optimum is the
+    unconstrained optimum on its own support)."""
+    import itertools
+    n = A.shape[1]
+    best, best_r = np.zeros(n), np.linalg.norm(b)
+    for k in range(1, n + 1):
+        for S in itertools.combinations(range(n), k):
+            x = np.zeros(n)
+            x[list(S)] = np.linalg.lstsq(A[:, S], b, rcond=None)[0]
+            if np.all(x >= 0):
+                r = np.linalg.norm(A @ x - b)
+                if r < best_r - 1e-14:
+                    best, best_r = x, r
+    return best
+
+
+def _negative_case(seed):
+    """Timings from a law with one cost column that the data would fit with a
+    negative weight: the last feature is nearly a difference of two others."""
+    rng = np.random.default_rng(seed)
+    F = rng.uniform(1.0, 10.0, size=(25, 4)) * np.array([1e3, 1e6, 1e9, 1e6])
+    F[:, 3] = 0.9 * F[:, 1] + rng.uniform(0, 3e5, 25)
+    t = F[:, :3] @ np.array([1e-6, 2e-9, 3e-12]) - 1e-9 * F[:, 3] * 0.5
+    t *= rng.uniform(0.95, 1.05, 25)
+    return F, np.abs(t) + 1e-6
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("relative", [True, False])
+def test_nonneg_fit_is_brute_force_nnls(seed, relative):
+    F, t = _negative_case(seed)
+    un = M.fit(F, t, relative=relative)
+    out = M.fit(F, t, relative=relative, nonneg=True)
+    assert np.all(out["p"] >= 0)
+    A = F / t[:, None] if relative else F
+    b = np.ones_like(t) if relative else t
+    sc = 1.0 / np.linalg.norm(A, axis=0)
+    ref = _nnls_brute_force(A * sc, b) * sc
+    np.testing.assert_allclose(out["p"], ref, rtol=1e-8, atol=1e-12 * np.max(np.abs(ref)))
+    if not un["negative"]:
+        np.testing.assert_allclose(out["p"], un["p"], rtol=1e-10)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_nonneg_fit_kkt(seed):
+    """Karush-Kuhn-Tucker conditions of min ||A p - b||, p >= 0: with
+    g = A^T (A p - b), g_j = 0 where p_j > 0 and g_j >= 0 where p_j = 0."""
+    F, t = _negative_case(seed)
+    p = M.fit(F, t, relative=True, nonneg=True)["p"]
+    A = F / t[:, None]
+    sc = 1.0 / np.linalg.norm(A, axis=0)
+    y = p / sc
+    g = (A * sc).T @ ((A * sc) @ y - 1.0)
+    tol = 1e-9 * np.sqrt(len(t))
+    assert np.all(y >= 0)
+    assert np.all(np.abs(g[y > 0]) <= tol)
+    assert np.all(g[y == 0] >= -tol)
+
+
+def test_overlap_fit_nonneg_bounds():
+    rng = np.random.default_rng(12)
+    F = np.column_stack([np.ones(40), rng.integers(16, 4096, 40), rng.uniform(1e8, 1e10, 40),
+                         rng.uniform(1e8, 1e10, 40), rng.uniform(1e11, 1e13, 40)])
+    group = [0, 0, 1, 1, 2]
+    p_true = np.array([5e-6, 0.0, 2e-13, 1.5e-13, 7e-15])
+    t = M.overlap_predict(F, group, p_true, 3e4) * rng.uniform(0.98, 1.02, 40)
+    fit = M.overlap_fit(F, t, group, np.abs(p_true) + 1e-10, 2e4, nonneg=True)
+    assert np.all(fit["p"] >= 0)
+    assert M.mape(M.overlap_predict(F, group, fit["p"], fit["edge"]), t) < 0.02
