@@ -83,6 +83,8 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
         use_slab = slab + panel_bytes <= 80 * 1024;
     }
     const int vec_out = n % 4 == 0;
+    /* unaligned rows that come through the wave slab leave through it too */
+    const int stage_out = !lowp && use_slab && !vec_out;
 
     c[F_LAUNCH] += 1;
     c[F_WG] += G;
@@ -158,6 +160,7 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                                 if (elx < nel && g * KQ + t < n) c[F_LDS] += sz;
                         }
                 }
+                const int64_t nel_w = mini(16LL * cb, E - e0);
                 /* panels */
                 for (int pp = 0; pp < np; ++pp) {
                     const int panel = p_lo + pp;
@@ -173,6 +176,29 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                             for (int t = 0; t < V; ++t)
                                 for (int q = 0; q < cb; ++q) c[sz == 8 ? F_MFMA_F64 : F_MFMA_F32] += 2048;
                         }
+                    }
+                    if (stage_out) {
+                        /* each lane puts its four results into the slab ... */
+                        for (int q = 0; q < cb; ++q)
+                            for (int lane = 0; lane < 64; ++lane) {
+                                const int cc = lane & 15, g = lane >> 4;
+                                if (q * 16 + cc >= nel_w) continue;
+                                for (int r = 0; r < 4; ++r)
+                                    if (i0 + 4 * g + r < n) c[F_LDS] += sz;
+                            }
+                        /* ... and after the last panel of this output slab in the
+                           group, the wave copies the staged rows out */
+                        const int m = panel / mblk;
+                        const int pf = (int)maxi(p_lo, (int64_t)m * mblk);
+                        const int pl = (int)mini(p_lo + np, (int64_t)(m + 1) * mblk);
+                        if (panel + 1 == pl) {
+                            const int64_t rows = mini((int64_t)(pl - m * mblk) * 16, n) - (pf - m * mblk) * 16;
+                            for (int64_t f = 0; f < nel_w * rows; ++f) {
+                                c[F_LDS] += sz;
+                                c[F_OUT] += sz;
+                            }
+                        }
+                        continue;
                     }
                     for (int q = 0; q < cb; ++q)
                         for (int lane = 0; lane < 64; ++lane) {

@@ -101,6 +101,7 @@ struct KArgs {
     int use_slab;       // unaligned rows go through the wave-private LDS slab
     int vec_out;        // out rows may be written as 16-byte vectors
     int nt_store;       // streaming (non-temporal) output stores
+    int stage_out;      // unaligned out rows: results staged in the wave's slab, written contiguously
 };
 
 __device__ inline int round_up_dev(int x, int v) { return (x + v - 1) / v * v; }
@@ -177,6 +178,44 @@ __device__ inline void stage_slab(const T* __restrict__ src, int64_t ew0, int ne
     for (int q = lane; q < nvec; q += 64)
         reinterpret_cast<vec_t*>(slab)[q] = reinterpret_cast<const vec_t*>(base)[q];
     for (int f = nvec * V + lane; f < len; f += 64) slab[f] = base[f];
+}
+
+// Write a wave's staged results: nel element rows of `rows` values (output
+// nodes r_lo .. r_lo+rows-1) from st[el*rows + ii] to dst[el*nunit + r_lo + ii]
+// (dst = the wave's first element row of one output slab).  Whole rows form
+// one contiguous range, written with 16-byte vectors where aligned; partial
+// rows go out as runs of consecutive scalars.  ACC adds to dst.
+template <typename T, bool ACC>
+__device__ inline void write_staged(const T* st, T* __restrict__ dst, int nel, int rows, int r_lo,
+                                    int nunit, int lane) {
+    typedef typename Mma<T>::vec_t vec_t;
+    constexpr int V = Mma<T>::V;
+    if (rows == nunit) {
+        const int len = nel * nunit;
+        int done = 0;
+        if (reinterpret_cast<uintptr_t>(dst) % 16 == 0) {
+            const int nv = len / V;
+            for (int q = lane; q < nv; q += 64) {
+                vec_t v = reinterpret_cast<const vec_t*>(st)[q];
+                if constexpr (ACC) v += reinterpret_cast<const vec_t*>(dst)[q];
+                reinterpret_cast<vec_t*>(dst)[q] = v;
+            }
+            done = nv * V;
+        }
+        for (int f = done + lane; f < len; f += 64) {
+            T v = st[f];
+            if constexpr (ACC) v += dst[f];
+            dst[f] = v;
+        }
+    } else {
+        for (int f = lane; f < nel * rows; f += 64) {
+            const int el = f / rows;
+            const int64_t o = (int64_t)el * nunit + r_lo + (f - el * rows);
+            T v = st[f];
+            if constexpr (ACC) v += dst[o];
+            dst[o] = v;
+        }
+    }
 }
 
 // ACC: out += result instead of out = result (a compile-time switch: as a
@@ -260,6 +299,7 @@ __global__ void __launch_bounds__(256) dg_kernel(KArgs a) {
             wave_lds_sync();  // slab reads done before the next tile overwrites it
         }
 
+        const int nel_w = (int)min<int64_t>(16 * CB, a.nelem - e0);  // valid elements of the wave
         for (int pp = 0; pp < np; ++pp) {
             const int panel = p_lo + pp;
             const int slab_o = panel / a.mblk;
@@ -282,6 +322,31 @@ __global__ void __launch_bounds__(256) dg_kernel(KArgs a) {
             }
             // Lane holds the results for nodes i0+4g .. i0+4g+3 of element column c.
             const int i = i0 + 4 * g;
+            if (a.stage_out) {
+                // rows [r_lo, r_hi) of output slab slab_o belong to this group;
+                // they are collected in the wave's slab (free once the element
+                // data sit in registers) and written when the slab's last
+                // panel of the group is done
+                const int pf = max(p_lo, slab_o * a.mblk);
+                const int pl = min(p_lo + np, (slab_o + 1) * a.mblk);
+                const int r_lo = (pf - slab_o * a.mblk) * 16;
+                const int rows = min((pl - slab_o * a.mblk) * 16, nunit) - r_lo;
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    const int el = cb * 16 + c;
+                    if (el >= nel_w) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (i + r < nunit) slab[el * rows + (i + r - r_lo)] = acc[cb][r];
+                }
+                if (panel + 1 == pl) {
+                    wave_lds_sync();
+                    write_staged<T, ACC>(slab, out + ((int64_t)slab_o * a.nelem + e0) * nunit, nel_w,
+                                         rows, r_lo, nunit, lane);
+                    wave_lds_sync();  // staged values read before the slab is reused
+                }
+                continue;
+            }
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
                 const int64_t e = e0 + cb * 16 + c;
@@ -447,6 +512,7 @@ dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, in
     a.src_aligned = reinterpret_cast<uintptr_t>(a.src) % 16 == 0;
     a.use_slab = P.use_slab;
     a.vec_out = (a.nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(a.out) % 16 == 0);
+    a.stage_out = a.use_slab && !a.vec_out;
     a.nt_store = (tile && (tile->flags & DG_TILE_NT_STORE)) ? 1 : 0;
     hipLaunchKernelGGL(fn, dim3((unsigned)P.grid), dim3(64 * waves), P.smem, s, a);
     DG_HIP_CHECK(hipGetLastError());
@@ -460,7 +526,9 @@ dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, in
 inline dg_status forward_cb(size_t tsize, int kq, bool rows_aligned, int epw, int* cb) {
     if (epw == 0) {
         const int w = kq * (int)tsize / 4;  // KQ in 32-bit registers
-        if (rows_aligned && w <= 16) *cb = 1;
+        // short rows: one column block (unaligned ones then fit the wave slab
+        // in both directions); measured fastest for p = 2 and p = 3
+        if (w <= 16) *cb = 1;
         else if (w <= 32) *cb = 4;
         else if (w <= 64) *cb = 2;
         else *cb = 1;

@@ -59,12 +59,16 @@ dg_status count_dg_fp(const perf_kernel_desc* d, int64_t* c) {
     c[PF_GLD_DG_D] = 8 * P.slots * (int64_t)M * n * n * (int64_t)sz;
     c[P.vec_in ? PF_GLD_DG_U : PF_GLD_DG_U_UNAL] = E * n * (int64_t)sz;
     c[PF_GLD_DG_U_L2] = (int64_t)(P.ngroups - 1) * E * n * (int64_t)sz;
-    c[n % 4 == 0 ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] = E * M * n * (int64_t)sz;
+    // unaligned rows read through the wave slab are also written through it:
+    // contiguous stores (plus one LDS write and read per output value)
+    const bool stage_out = P.use_slab && n % 4 != 0;
+    c[(n % 4 == 0 || stage_out) ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] = E * M * n * (int64_t)sz;
     c[PF_WAVE_TILES] = nwt * P.ngroups;
     c[PF_SERIAL_STEPS] = ceil_div(P.ntiles, 8 * P.slots);  // tiles of the busiest stream
     c[PF_LDS_BYTES] = 8 * P.slots * P.panels_total * 16 * KP * (int64_t)sz  // staging stores
                       + nwt * P.panels_total * 64 * kq * (int64_t)sz      // operand reads
-                      + (P.use_slab ? (int64_t)P.ngroups * 2 * E * n * (int64_t)sz : 0);
+                      + (P.use_slab ? (int64_t)P.ngroups * 2 * E * n * (int64_t)sz : 0)
+                      + (stage_out ? 2 * E * M * n * (int64_t)sz : 0);
     c[sz == 8 ? PF_MFMA_F64 : PF_MFMA_F32] = nwt * P.panels_total * kq * (int64_t)cb * 2048;
     return DG_OK;
 }

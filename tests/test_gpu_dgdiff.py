@@ -87,6 +87,24 @@ def test_tile_variants(orc, ops, nunit, tile):
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("nunit", [5, 27, 125])
+@pytest.mark.parametrize("tile", [dict(elems_per_wave=16, d_panels=1), dict(elems_per_wave=16, d_panels=3),
+                                  dict(elems_per_wave=32, d_panels=5), dict(elems_per_wave=16, waves=3),
+                                  dict(elems_per_wave=64, d_panels=2)])
+def test_unaligned_rows_staged_stores(orc, ops, dtype, nunit, tile):
+    """Rows that are not 16-byte multiples go through the wave's LDS slab in
+    both directions; panel groups that hold only part of an operator's rows
+    write partial rows.  Element counts with ragged last tiles."""
+    D = I.random_dmats(nunit)
+    for nelem in (1, 63, 1001):
+        u = I.uniform_u(nelem, nunit)
+        try:
+            _check(orc, ops, D, u, dtype, tile=tile)
+        except ops.DGError:
+            pytest.skip("launch shape not available for this problem")
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_integer_data_bit_exact(orc, ops, dtype):
     rng = np.random.default_rng(12)
     for nunit in (27, 64, 125):
