@@ -67,6 +67,8 @@ typedef struct {
                                 whose internal 32-product sums are coarser than FP32
                                 (default: widen FP8 exactly to BF16 and use the BF16
                                 matrix cores, with true FP32 accumulation) */
+#define DG_TILE_BATCH_GEMM 4 /* batched plans: run this order on the GEMM-tiled body
+                                (128 operator rows x 128 elements per work-group) */
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* dg_last_error(void);
@@ -99,6 +101,13 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
 
    dgdiff_plan_create: order [nelem] is a HOST array; nmat must be 3.
      tiles [8] (HOST, indexed by order; NULL = choose): launch shape per order.
+     Three kernel bodies serve the orders: one element per thread (orders 1
+     and 2 by default; reported as elems_per_wave 256), resident operator
+     panels with the elements streamed through (elems_per_wave 16 or 32,
+     d_panels; used when a tile gives elems_per_wave for an order below 3), and a
+     GEMM tiling of 128 stacked operator rows x 128 elements, used for orders
+     with nunit >= 64 and for any order whose tile sets DG_TILE_BATCH_GEMM
+     (its other tile fields are then ignored).
      When tiles is NULL and model_cost [PF_COUNT] (HOST, seconds per feature
      unit) is given, every candidate shape of every order is priced with the
      model -- linear (model_group NULL) or the overlap form (model_group

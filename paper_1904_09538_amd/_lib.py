@@ -34,6 +34,7 @@ class dg_tile(ctypes.Structure):
 
 DG_TILE_NT_STORE = 1
 DG_TILE_FP8_NATIVE = 2
+DG_TILE_BATCH_GEMM = 4
 
 DG_K_DGDIFF, DG_K_STENCIL5, DG_K_MATMUL, DG_K_EMPTY = range(4)
 

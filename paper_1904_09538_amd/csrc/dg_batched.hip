@@ -17,8 +17,10 @@
 // Kernel: a work-group finds its order from the block ranges, then runs the
 // same contraction as the plain kernel (operator panels resident in LDS, XCD
 // aware tile streams within the order's block range) on a gathered list of
-// element ids.  Rows are not 16-byte aligned in the packed layout, so element
-// data are read and outputs written with masked scalar accesses.
+// element ids.  Rows start at arbitrary 4-byte offsets in the packed layout;
+// element data are still read, and results written, as 16-byte vectors
+// (unaligned vector accesses, with value-by-value row tails).  Order 1 takes
+// one element per thread, orders 6 and 7 a GEMM tiling (see below).
 #include <algorithm>
 #include <cmath>
 #include <set>
@@ -54,11 +56,32 @@ namespace {
 
 using namespace kern;
 
-// Panels a work-group may hold for a given KQ (the 80 KB per-group budget).
-constexpr int max_panels(int kq) {
-    const int pb = 16 * (4 * kq + 4) * 4;
-    const int m = (80 * 1024) / pb;
-    return m < 1 ? 1 : m;
+// Four consecutive values of a row that starts at any 4-byte boundary:
+// `avail` values from p on belong to the row; the rest read as zero.  A
+// full in-range vector is one 16-byte load (the 16-byte copy from a 4-byte
+// aligned address is left to the compiler, which issues a single vector load
+// on this target); row tails are loaded value by value.
+__device__ inline f32x4 load4(const float* p, bool ok, int avail) {
+    f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (!ok || avail <= 0) return v;
+    if (avail >= 4) {
+        __builtin_memcpy(&v, p, 16);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (q < avail) v[q] = p[q];
+    }
+    return v;
+}
+
+__device__ inline void store4(float* p, f32x4 v, int avail) {
+    if (avail >= 4) {
+        __builtin_memcpy(p, &v, 16);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (q < avail) p[q] = v[q];
+    }
 }
 
 template <int KQ, int CB>
@@ -66,13 +89,6 @@ __device__ void batched_body(const BArgs& a, const BOrder& o, int64_t lb, float*
     typedef f32x4 vec_t;
     constexpr int KP = 4 * KQ;
     constexpr int LD = KP + 4;
-    // Large orders walk the contraction in chunks of 32 nodes per lane group
-    // and keep the accumulators of all their resident panels (at most
-    // max_panels) live across chunks: 32 element values per column block in
-    // registers instead of KQ.
-    constexpr int KC = KQ <= 32 ? KQ : 32;
-    constexpr int NCH = (KQ + KC - 1) / KC;
-    constexpr int MAXP = NCH == 1 ? 1 : max_panels(KQ);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int c = lane & 15, g = lane >> 4;
@@ -100,84 +116,237 @@ __device__ void batched_body(const BArgs& a, const BOrder& o, int64_t lb, float*
     for (int64_t tile = stream; tile < o.ntiles; tile += o.nstreams) {
         const int64_t k0 = tile * tile_elems + (int64_t)wave * 16 * CB;  // position in the id list
         if (k0 >= o.count) continue;
-        int64_t eid[CB], base[CB];
+        // lane (c, g) reads nodes g*KQ .. g*KQ+KQ-1 of element column c as
+        // 16-byte loads from wherever the row starts
+        int64_t base[CB];
+        bool ok[CB];
+        float bv[CB][KQ];
 #pragma unroll
         for (int q = 0; q < CB; ++q) {
             const int64_t k = k0 + q * 16 + c;
-            eid[q] = k < o.count ? a.perm[o.ids + k] : -1;
-            base[q] = eid[q] >= 0 ? a.off[eid[q]] : 0;
+            ok[q] = k < o.count;
+            base[q] = ok[q] ? a.off[a.perm[o.ids + k]] : 0;
+#pragma unroll
+            for (int t = 0; t < KQ; t += 4) {
+                const f32x4 v = load4(a.u + base[q] + g * KQ + t, ok[q], n - g * KQ - t);
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) bv[q][t + s4] = v[s4];
+            }
         }
-        for (int pp0 = 0; pp0 < np; pp0 += MAXP) {
-            f32x4 acc[MAXP][CB];
+        for (int pp = 0; pp < np; ++pp) {
+            f32x4 acc[CB];
 #pragma unroll
-            for (int pq = 0; pq < MAXP; ++pq)
+            for (int q = 0; q < CB; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const float* arow = dl + (pp * 16 + c) * LD + g * KQ;
 #pragma unroll
-                for (int q = 0; q < CB; ++q) acc[pq][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-            // NCH == 1: one chunk per panel, panels one after another
-            for (int pq1 = 0; pq1 < (NCH == 1 ? min(MAXP, np - pp0) : 1); ++pq1) {
+            for (int t = 0; t < KQ; t += 4) {
+                const vec_t av = *reinterpret_cast<const vec_t*>(arow + t);
 #pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    const int k_lo = ch * KC;
-                    float b[CB][KC];
+                for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-                    for (int q = 0; q < CB; ++q) {
-                        const float* row = a.u + base[q] + g * KQ + k_lo;
+                    for (int q = 0; q < CB; ++q)
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], bv[q][t + s4], acc[q], 0, 0, 0);
+            }
+            // lane holds output nodes i .. i+3 of element column c
+            const int panel = p_lo + pp;
+            const int m = panel / o.mblk;
+            const int i = (panel % o.mblk) * 16 + 4 * g;
 #pragma unroll
-                        for (int t = 0; t < KC; ++t)
-                            b[q][t] = (eid[q] >= 0 && k_lo + t < KQ && g * KQ + k_lo + t < n) ? row[t]
-                                                                                               : 0.0f;
-                    }
+            for (int q = 0; q < CB; ++q)
+                if (ok[q] && i < n) store4(a.out + (int64_t)m * a.total + base[q] + i, acc[q], n - i);
+        }
+    }
+}
+
+constexpr int GBM = 128, GBN = 128, GBK = 16, GLD = GBK + 4;
+constexpr size_t kGemmLds = (size_t)2 * (GBM + GBN) * GLD * 4;
+constexpr int kGemmMinNunit = 343;
+
+__device__ void gemm_body(const BArgs& a, const BOrder& o, int64_t lb, float* sm) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 15, g = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int n = o.nunit;
+    const int R = a.nmat * n;  // stacked operator rows
+    const int RB = (R + GBM - 1) / GBM;
+    const int EB = (int)((o.count + GBN - 1) / GBN);
+    const int nk = (n + GBK - 1) / GBK;
+    float* As = sm;                    // [2][GBM][GLD]
+    float* Bs = sm + 2 * GBM * GLD;    // [2][GBN][GLD]
+    const int xcd = (int)(lb & 7);
+    const int kx = (int)(lb >> 3);
+    const int nbx = o.nstreams >> 3;  // work-groups of this order on each XCD
+    const int ntile_x = ((EB - xcd + 7) / 8) * RB;
+    const int my_tiles = kx < ntile_x ? (ntile_x - kx + nbx - 1) / nbx : 0;
+    // staging coordinates: A row ar, columns ah .. ah+7; B elements be and
+    // be+64, nodes bq .. bq+3
+    const int ar = tid >> 1, ah = (tid & 1) * 8;
+    const int be = tid >> 2, bq = (tid & 3) * 4;
+
+    // The (tile, chunk) steps of this work-group run as one pipeline: the
+    // operands of step s+1 are fetched into registers while step s
+    // multiplies, across tile boundaries, so a tile's first chunk is already
+    // in flight during the previous tile's last chunk and its epilogue.
+    // Per tile (computed once): first element / operator row, and the
+    // staging rows' base pointers.
+    struct Tile {
+        int64_t e0;
+        int r0;
+        const float* arow;
+        const float* brow[2];
+        bool a_ok, b_ok[2];
+    };
+    auto make_tile = [&](int q, Tile& t) {
+        const int T = kx + q * nbx;
+        t.e0 = (int64_t)(xcd + 8 * (T / RB)) * GBN;
+        t.r0 = (T % RB) * GBM;
+        t.a_ok = t.r0 + ar < R;
+        t.arow = o.D + (int64_t)(t.a_ok ? t.r0 + ar : 0) * n;
 #pragma unroll
-                    for (int pq = 0; pq < MAXP; ++pq) {
-                        const int pp = pp0 + (NCH == 1 ? pq1 : pq);
-                        if ((NCH == 1 && pq > 0) || pp >= np) continue;
-                        const float* arow = dl + (pp * 16 + c) * LD + g * KQ + k_lo;
+        for (int h = 0; h < 2; ++h) {
+            const int64_t kb_ = t.e0 + be + 64 * h;
+            t.b_ok[h] = kb_ < o.count;
+            t.brow[h] = a.u + (t.b_ok[h] ? a.off[a.perm[o.ids + kb_]] : 0);
+        }
+    };
+    float ra[8], rbv[2][4];
+    auto load = [&](const Tile& t, int kc) {
+        const int k0 = kc * GBK;
 #pragma unroll
-                        for (int t = 0; t < KC; t += 4) {
-                            if (k_lo + t >= KQ) continue;
-                            const vec_t av = *reinterpret_cast<const vec_t*>(arow + t);
+        for (int h = 0; h < 2; ++h) {
+            const int j = k0 + ah + 4 * h;
+            f32x4 v = load4(t.arow + j, t.a_ok, n - j);
 #pragma unroll
-                            for (int s4 = 0; s4 < 4; ++s4)
+            for (int q4 = 0; q4 < 4; ++q4) ra[4 * h + q4] = v[q4];
+        }
 #pragma unroll
-                                for (int q = 0; q < CB; ++q)
-                                    acc[pq][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                                        av[s4], b[q][t + s4], acc[pq][q], 0, 0, 0);
+        for (int h = 0; h < 2; ++h) {
+            const f32x4 v = load4(t.brow[h] + k0 + bq, t.b_ok[h], n - k0 - bq);
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) rbv[h][q4] = v[q4];
+        }
+    };
+    auto store = [&](int buf) {
+        float* ad = As + (buf * GBM + ar) * GLD + ah;
+        *reinterpret_cast<f32x4*>(ad) = f32x4{ra[0], ra[1], ra[2], ra[3]};
+        *reinterpret_cast<f32x4*>(ad + 4) = f32x4{ra[4], ra[5], ra[6], ra[7]};
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            *reinterpret_cast<f32x4*>(Bs + (buf * GBN + be + 64 * h) * GLD + bq) =
+                f32x4{rbv[h][0], rbv[h][1], rbv[h][2], rbv[h][3]};
+    };
+    const int nsteps = my_tiles * nk;
+    if (nsteps == 0) return;
+    Tile cur, nxt;
+    make_tile(0, cur);
+    load(cur, 0);
+    store(0);
+    __syncthreads();
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int q = 0, kc = 0;
+    for (int st = 0; st < nsteps; ++st) {
+        const int buf = st & 1;
+        const bool more = st + 1 < nsteps;
+        if (more) {
+            if (kc + 1 < nk) {
+                load(cur, kc + 1);
+            } else {
+                make_tile(q + 1, nxt);
+                load(nxt, 0);
+            }
+        }
+        f32x4 av[4], bv[4];
+#pragma unroll
+        for (int tm = 0; tm < 4; ++tm)
+            av[tm] = *reinterpret_cast<const f32x4*>(As + (buf * GBM + wm * 64 + tm * 16 + c) * GLD + 4 * g);
+#pragma unroll
+        for (int tn = 0; tn < 4; ++tn)
+            bv[tn] = *reinterpret_cast<const f32x4*>(Bs + (buf * GBN + wn * 64 + tn * 16 + c) * GLD + 4 * g);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < 4; ++tn)
+                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tm][s4], bv[tn][s4], acc[tm][tn], 0,
+                                                                       0, 0);
+        if (kc + 1 == nk) {
+            // tile done: lane holds stacked rows r0 + wm*64 + tm*16 + 4g + r
+            // of element column wn*64 + tn*16 + c
+#pragma unroll
+            for (int tn = 0; tn < 4; ++tn) {
+                const int64_t kpos = cur.e0 + wn * 64 + tn * 16 + c;
+                if (kpos < o.count) {
+                    const int64_t eoff = a.off[a.perm[o.ids + kpos]];
+#pragma unroll
+                    for (int tm = 0; tm < 4; ++tm) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int row = cur.r0 + wm * 64 + tm * 16 + 4 * g + r;
+                            if (row >= R) continue;
+                            const int m = row / n;
+                            a.out[(int64_t)m * a.total + eoff + (row - m * n)] = acc[tm][tn][r];
                         }
                     }
                 }
-                if constexpr (NCH == 1) {
-                    const int pp = pp0 + pq1;
-                    const int panel = p_lo + pp;
-                    const int m = panel / o.mblk;
-                    const int i = (panel % o.mblk) * 16 + 4 * g;
 #pragma unroll
-                    for (int q = 0; q < CB; ++q) {
-                        if (eid[q] < 0) continue;
-                        float* dst = a.out + (int64_t)m * a.total + base[q] + i;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (i + r < n) dst[r] = acc[0][q][r];
-                        acc[0][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    }
-                }
+                for (int tm = 0; tm < 4; ++tm) acc[tm][tn] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
-            if constexpr (NCH > 1) {
+            kc = 0;
+            ++q;
+            cur = nxt;
+        } else {
+            ++kc;
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+// Order 1 (nunit 8): the operator stack is tiny (3 x 8 x 8) and the work
+// per element a few hundred flops, so the order is bound by moving element
+// data.  One thread takes one element:
+// it reads the element's row with 16-byte loads, applies the operators with
+// the node loops fully unrolled (operator entries are wave-uniform loads),
+// and writes each output row with 16-byte stores.  A wave keeps 64 element
+// rows in flight.
+template <int N>
+__device__ void valu_body(const BArgs& a, const BOrder& o, int64_t lb) {
+    constexpr int NV = (N + 3) / 4;
+    const float* __restrict__ D = o.D;
+    for (int64_t blk = lb; blk * 256 < o.count; blk += o.nstreams) {
+        const int64_t k = blk * 256 + threadIdx.x;
+        if (k >= o.count) continue;
+        const int64_t eoff = a.off[a.perm[o.ids + k]];
+        float x[4 * NV];
 #pragma unroll
-                for (int pq = 0; pq < MAXP; ++pq) {
-                    const int pp = pp0 + pq;
-                    if (pp >= np) continue;
-                    const int panel = p_lo + pp;
-                    const int m = panel / o.mblk;
-                    const int i = (panel % o.mblk) * 16 + 4 * g;  // four consecutive output nodes
+        for (int v = 0; v < NV; ++v) {
+            const f32x4 t = load4(a.u + eoff + 4 * v, true, N - 4 * v);
 #pragma unroll
-                    for (int q = 0; q < CB; ++q) {
-                        if (eid[q] < 0) continue;
-                        float* dst = a.out + (int64_t)m * a.total + base[q] + i;
+            for (int q = 0; q < 4; ++q) x[4 * v + q] = t[q];
+        }
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (i + r < n) dst[r] = acc[pq][q][r];
+        for (int m = 0; m < 3; ++m) {
+            float* dst = a.out + (int64_t)m * a.total + eoff;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 4 * v + q;
+                    if (i < N) {
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int j = 0; j < N; ++j) acc = __builtin_fmaf(D[(m * N + i) * N + j], x[j], acc);
+                        y[q] = acc;
                     }
                 }
+                store4(dst + 4 * v, y, N - 4 * v);
             }
         }
     }
@@ -186,7 +355,9 @@ __device__ void batched_body(const BArgs& a, const BOrder& o, int64_t lb, float*
 // kernel bodies instantiated: (order, column blocks per wave)
 #define DG_BATCHED_VARIANTS(X) \
     X(0, 4, 1) X(1, 4, 2) X(2, 8, 1) X(3, 8, 2) X(4, 16, 1) X(5, 16, 2) X(6, 32, 1) X(7, 32, 2) \
-    X(8, 56, 1) X(10, 88, 1) X(11, 128, 1)
+    X(8, 56, 1)
+
+constexpr int kGemmVariant = 20, kValu8Variant = 21;
 
 __global__ void __launch_bounds__(256) dg_batched_kernel(BArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -202,6 +373,12 @@ __global__ void __launch_bounds__(256) dg_batched_kernel(BArgs a) {
         break;
         DG_BATCHED_VARIANTS(X)
 #undef X
+        case kGemmVariant:
+            gemm_body(a, o, lb, dl);
+            break;
+        case kValu8Variant:
+            valu_body<8>(a, o, lb);
+            break;
         default:
             break;
     }
@@ -292,7 +469,15 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
         const int mblk = (int)ceil_div(n, 16);
         const int panels = nmat * mblk;
         const size_t panel_bytes = (size_t)16 * (4 * kq + 4) * 4;
-        const int max_ppg = std::max<int>(1, (int)std::min<size_t>(panels, kBatchLds / panel_bytes));
+        // operator panels that fit the per-group LDS budget
+        auto max_ppg_for = [&](int) { return (int)std::min<size_t>(panels, kBatchLds / panel_bytes); };
+        // kernel body of this order: one element per thread (order 1), GEMM
+        // tiling (orders 6, 7, or when asked for) or resident operator panels
+        const bool force_gemm = tiles && (tiles[p].flags & DG_TILE_BATCH_GEMM);
+        const bool force_panels = tiles && tiles[p].elems_per_wave && !force_gemm;
+        const bool use_valu = n == 8 && !force_gemm && !force_panels;
+        const bool use_gemm = !use_valu && (n >= kGemmMinNunit || force_gemm);
+        const bool use_panels = !use_valu && !use_gemm;
         std::vector<dg_tile> cands;
         if (tiles && tiles[p].elems_per_wave) {
             dg_tile t = tiles[p];
@@ -302,6 +487,11 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
             }
             // operator panels per work-group: as many as the per-group LDS allows
             // unless given (balanced over the groups either way)
+            const int max_ppg = max_ppg_for(t.elems_per_wave / 16);
+            if (max_ppg < 1) {
+                delete P;
+                return fail(DG_EUNSUPPORTED, "dgdiff_plan_create: tile does not fit the LDS");
+            }
             const int want = t.d_panels > 0 ? std::min(t.d_panels, max_ppg) : max_ppg;
             t.d_panels = (int)ceil_div(panels, ceil_div(panels, want));
             t.waves = 4;
@@ -310,11 +500,12 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
         } else {
             // operator-group counts reachable within the LDS budget (a few of
             // the smallest), each with balanced groups
-            std::set<int> ngs;
-            for (int ppg = max_ppg; ppg >= 1 && ngs.size() < 5; --ppg)
-                ngs.insert((int)ceil_div(panels, ppg));
+            // (for the other bodies the ranked shape only prices the order)
             for (int cb : {1, 2}) {
-                if (variant_of(kq, cb) < 0) continue;
+                if (use_panels && variant_of(kq, cb) < 0) continue;
+                std::set<int> ngs;
+                for (int ppg = max_ppg_for(cb); ppg >= 1 && ngs.size() < 5; --ppg)
+                    ngs.insert((int)ceil_div(panels, ppg));
                 for (int ng : ngs) {
                     const int ppg = (int)ceil_div(panels, ng);
                     dg_tile t = {};
@@ -366,16 +557,39 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
         b.nunit = n;
         b.mblk = mblk;
         b.panels_total = panels;
-        b.ppg = std::max(1, std::min(po.tile.d_panels, panels));
-        b.ngroups = (int)ceil_div(panels, b.ppg);
-        b.cb = cb;
-        b.variant = variant_of(kq, cb);
-        b.ntiles = ceil_div(po.count, (int64_t)16 * cb * 4);
-        if (b.variant < 0 || (size_t)b.ppg * panel_bytes > 160 * 1024) {
+        size_t lds;
+        if (use_valu) {
+            // order 1: one element per thread
+            po.tile = dg_tile{256, 4, 0, 0, 0};
+            b.ppg = 1;
+            b.ngroups = 1;
+            b.cb = 1;
+            b.variant = kValu8Variant;
+            b.ntiles = ceil_div(po.count, (int64_t)256);
+            lds = 0;
+        } else if (use_gemm) {
+            // large orders: GEMM tiling (GBM operator rows x GBN elements); the
+            // ranked resident-panel shape serves only as the cost prediction
+            po.tile = dg_tile{GBN, 4, 1, GBM / 16, DG_TILE_BATCH_GEMM};
+            b.ppg = 1;
+            b.ngroups = 1;
+            b.cb = 1;
+            b.variant = kGemmVariant;
+            b.ntiles = ceil_div((int64_t)nmat * n, (int64_t)GBM) * ceil_div(po.count, (int64_t)GBN);
+            lds = kGemmLds;
+        } else {
+            b.ppg = std::max(1, std::min(po.tile.d_panels, panels));
+            b.ngroups = (int)ceil_div(panels, b.ppg);
+            b.cb = cb;
+            b.variant = variant_of(kq, cb);
+            b.ntiles = ceil_div(po.count, (int64_t)16 * cb * 4);
+            lds = (size_t)b.ppg * panel_bytes;
+        }
+        if (b.variant < 0 || lds > 160 * 1024) {
             delete P;
             return fail(DG_EUNSUPPORTED, "dgdiff_plan_create: launch shape not available");
         }
-        P->smem = std::max(P->smem, (size_t)b.ppg * panel_bytes);
+        P->smem = std::max(P->smem, lds);
     }
     // work-group split: resident capacity shared in proportion to predicted time
     int per_cu = 1;
@@ -386,11 +600,15 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
     per_cu = std::max(per_cu, 1);
     const double capacity = (double)per_cu * dev.num_cu;
     // an order's weight: its predicted time (floored, since a fitted model
-    // can go negative outside the sizes it was calibrated on), else its flops
+    // can go negative outside the sizes it was calibrated on), else a
+    // roofline estimate at the rates the bodies sustain on this GPU, about
+    // 80 TFLOP/s and 2.5 TB/s (flops alone would starve the memory-bound low
+    // orders)
     auto weight = [&](int p) {
         const PlanOrder& po = P->ord[p];
-        return cost ? std::max(po.predicted_s, 1e-7)
-                    : (double)po.count * std::pow((double)(p + 1), 6.0);
+        if (cost) return std::max(po.predicted_s, 1e-7);
+        const double nn = std::pow((double)(p + 1), 3.0);
+        return std::max(6.0 * nn * nn * po.count / 80e12, 16.0 * nn * po.count / 2.5e12);
     };
     double wsum = 0;
     for (int p = 1; p <= 7; ++p)

@@ -72,6 +72,20 @@ def test_batched_explicit_tiles(orc, ops, tiles):
     assert normwise_rel(got, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("nelem", [1, 70, 2500])
+def test_batched_gemm_body_all_orders(orc, ops, nelem):
+    """Every order forced onto the GEMM-tiled body (large orders use it by
+    default): ragged row and element blocks, unaligned operator rows."""
+    order = I.batched_orders(nelem, seed=7)
+    off = I.batched_offsets(order)
+    u32 = np.random.default_rng(2).uniform(-1, 1, int(off[-1])).astype(np.float32)
+    D32 = {p: I.random_dmats((p + 1) ** 3).astype(np.float32) for p in range(1, 8)}
+    _, got = _run(ops, order, u32, D32, tiles={p: dict(flags=ops.DG_TILE_BATCH_GEMM) for p in range(1, 8)})
+    ref = orc.dg_batched(order, off, {p: D.astype(np.float64) for p, D in D32.items()},
+                         u32.astype(np.float64))
+    assert normwise_rel(got, ref) <= 1e-5
+
+
 def test_batched_single_order_equals_plain(ops):
     """All elements of one order: the packed layout is the plain layout, and
     the result matches dgdiff_apply on the same data."""
