@@ -113,8 +113,11 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
      model -- linear (model_group NULL) or the overlap form (model_group
      [PF_COUNT] cost groups 0/1/2, model_edge) -- and the cheapest is taken;
      the persistent grid is split across orders in proportion to predicted
-     time.  The plan owns device copies of the sorted element ids and the
-     offsets; it is immutable and may be used from several streams.
+     time; GEMM-body orders are drained from a shared tile pool that every
+     work-group joins after its own share, which absorbs estimate errors.
+     The plan owns device copies of the sorted element ids and the offsets
+     and the pool's cursors: calls that use one plan must not overlap in time
+     (issue them on one stream).
    dgdiff_plan_info: order p's chosen shape, element count, work-groups and
      predicted standalone time (0 without a model).
    dgdiff_apply_batched: D_sets is a HOST array of 8 DEVICE pointers,

@@ -50,6 +50,8 @@ struct BArgs {
     int waves;
     int64_t blk_lo[9];    // block range of order p: [blk_lo[p], blk_lo[p+1])
     BOrder ord[8];
+    int* ctr;             // [9]: GEMM tile pool cursor per XCD, finished work-groups
+    int pool;             // some order runs on the GEMM body
 };
 
 namespace {
@@ -159,70 +161,52 @@ __device__ void batched_body(const BArgs& a, const BOrder& o, int64_t lb, float*
 }
 
 constexpr int GBM = 128, GBN = 128, GBK = 16, GLD = GBK + 4;
+constexpr int kGemmVariant = 20, kValu8Variant = 21;
 constexpr size_t kGemmLds = (size_t)2 * (GBM + GBN) * GLD * 4;
 constexpr int kGemmMinNunit = 343;
 
-__device__ void gemm_body(const BArgs& a, const BOrder& o, int64_t lb, float* sm) {
+// One GEMM tile: element block eb (GBN elements of the order's id list) x
+// operator row block rb (GBM stacked rows), the contraction double-buffered
+// through LDS in chunks of GBK nodes.
+__device__ void gemm_tile(const BArgs& a, const BOrder& o, int64_t eb, int rb, float* sm) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int c = lane & 15, g = lane >> 4;
     const int wm = wave >> 1, wn = wave & 1;
     const int n = o.nunit;
     const int R = a.nmat * n;  // stacked operator rows
-    const int RB = (R + GBM - 1) / GBM;
-    const int EB = (int)((o.count + GBN - 1) / GBN);
     const int nk = (n + GBK - 1) / GBK;
     float* As = sm;                    // [2][GBM][GLD]
     float* Bs = sm + 2 * GBM * GLD;    // [2][GBN][GLD]
-    const int xcd = (int)(lb & 7);
-    const int kx = (int)(lb >> 3);
-    const int nbx = o.nstreams >> 3;  // work-groups of this order on each XCD
-    const int ntile_x = ((EB - xcd + 7) / 8) * RB;
-    const int my_tiles = kx < ntile_x ? (ntile_x - kx + nbx - 1) / nbx : 0;
+    const int64_t e0 = eb * GBN;
+    const int r0 = rb * GBM;
     // staging coordinates: A row ar, columns ah .. ah+7; B elements be and
     // be+64, nodes bq .. bq+3
     const int ar = tid >> 1, ah = (tid & 1) * 8;
     const int be = tid >> 2, bq = (tid & 3) * 4;
-
-    // The (tile, chunk) steps of this work-group run as one pipeline: the
-    // operands of step s+1 are fetched into registers while step s
-    // multiplies, across tile boundaries, so a tile's first chunk is already
-    // in flight during the previous tile's last chunk and its epilogue.
-    // Per tile (computed once): first element / operator row, and the
-    // staging rows' base pointers.
-    struct Tile {
-        int64_t e0;
-        int r0;
-        const float* arow;
-        const float* brow[2];
-        bool a_ok, b_ok[2];
-    };
-    auto make_tile = [&](int q, Tile& t) {
-        const int T = kx + q * nbx;
-        t.e0 = (int64_t)(xcd + 8 * (T / RB)) * GBN;
-        t.r0 = (T % RB) * GBM;
-        t.a_ok = t.r0 + ar < R;
-        t.arow = o.D + (int64_t)(t.a_ok ? t.r0 + ar : 0) * n;
+    const bool a_ok = r0 + ar < R;
+    const float* arow = o.D + (int64_t)(a_ok ? r0 + ar : 0) * n;
+    bool b_ok[2];
+    const float* brow[2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t kb_ = t.e0 + be + 64 * h;
-            t.b_ok[h] = kb_ < o.count;
-            t.brow[h] = a.u + (t.b_ok[h] ? a.off[a.perm[o.ids + kb_]] : 0);
-        }
-    };
+    for (int h = 0; h < 2; ++h) {
+        const int64_t kb_ = e0 + be + 64 * h;
+        b_ok[h] = kb_ < o.count;
+        brow[h] = a.u + (b_ok[h] ? a.off[a.perm[o.ids + kb_]] : 0);
+    }
     float ra[8], rbv[2][4];
-    auto load = [&](const Tile& t, int kc) {
+    auto load = [&](int kc) {
         const int k0 = kc * GBK;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int j = k0 + ah + 4 * h;
-            f32x4 v = load4(t.arow + j, t.a_ok, n - j);
+            const f32x4 v = load4(arow + j, a_ok, n - j);
 #pragma unroll
             for (int q4 = 0; q4 < 4; ++q4) ra[4 * h + q4] = v[q4];
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const f32x4 v = load4(t.brow[h] + k0 + bq, t.b_ok[h], n - k0 - bq);
+            const f32x4 v = load4(brow[h] + k0 + bq, b_ok[h], n - k0 - bq);
 #pragma unroll
             for (int q4 = 0; q4 < 4; ++q4) rbv[h][q4] = v[q4];
         }
@@ -236,11 +220,7 @@ __device__ void gemm_body(const BArgs& a, const BOrder& o, int64_t lb, float* sm
             *reinterpret_cast<f32x4*>(Bs + (buf * GBN + be + 64 * h) * GLD + bq) =
                 f32x4{rbv[h][0], rbv[h][1], rbv[h][2], rbv[h][3]};
     };
-    const int nsteps = my_tiles * nk;
-    if (nsteps == 0) return;
-    Tile cur, nxt;
-    make_tile(0, cur);
-    load(cur, 0);
+    load(0);
     store(0);
     __syncthreads();
     f32x4 acc[4][4];
@@ -248,18 +228,10 @@ __device__ void gemm_body(const BArgs& a, const BOrder& o, int64_t lb, float* sm
     for (int tm = 0; tm < 4; ++tm)
 #pragma unroll
         for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = f32x4{0.f, 0.f, 0.f, 0.f};
-    int q = 0, kc = 0;
-    for (int st = 0; st < nsteps; ++st) {
-        const int buf = st & 1;
-        const bool more = st + 1 < nsteps;
-        if (more) {
-            if (kc + 1 < nk) {
-                load(cur, kc + 1);
-            } else {
-                make_tile(q + 1, nxt);
-                load(nxt, 0);
-            }
-        }
+    for (int kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        const bool more = kc + 1 < nk;
+        if (more) load(kc + 1);
         f32x4 av[4], bv[4];
 #pragma unroll
         for (int tm = 0; tm < 4; ++tm)
@@ -275,36 +247,86 @@ __device__ void gemm_body(const BArgs& a, const BOrder& o, int64_t lb, float* sm
                 for (int tn = 0; tn < 4; ++tn)
                     acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[tm][s4], bv[tn][s4], acc[tm][tn], 0,
                                                                        0, 0);
-        if (kc + 1 == nk) {
-            // tile done: lane holds stacked rows r0 + wm*64 + tm*16 + 4g + r
-            // of element column wn*64 + tn*16 + c
-#pragma unroll
-            for (int tn = 0; tn < 4; ++tn) {
-                const int64_t kpos = cur.e0 + wn * 64 + tn * 16 + c;
-                if (kpos < o.count) {
-                    const int64_t eoff = a.off[a.perm[o.ids + kpos]];
-#pragma unroll
-                    for (int tm = 0; tm < 4; ++tm) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int row = cur.r0 + wm * 64 + tm * 16 + 4 * g + r;
-                            if (row >= R) continue;
-                            const int m = row / n;
-                            a.out[(int64_t)m * a.total + eoff + (row - m * n)] = acc[tm][tn][r];
-                        }
-                    }
-                }
-#pragma unroll
-                for (int tm = 0; tm < 4; ++tm) acc[tm][tn] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
-            kc = 0;
-            ++q;
-            cur = nxt;
-        } else {
-            ++kc;
-        }
         if (more) store(buf ^ 1);
         __syncthreads();
+    }
+    // lane holds stacked rows r0 + wm*64 + tm*16 + 4g + r of element column
+    // wn*64 + tn*16 + c
+#pragma unroll
+    for (int tn = 0; tn < 4; ++tn) {
+        const int64_t kpos = e0 + wn * 64 + tn * 16 + c;
+        if (kpos >= o.count) continue;
+        const int64_t eoff = a.off[a.perm[o.ids + kpos]];
+#pragma unroll
+        for (int tm = 0; tm < 4; ++tm) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = r0 + wm * 64 + tm * 16 + 4 * g + r;
+                if (row >= R) continue;
+                const int m = row / n;
+                a.out[(int64_t)m * a.total + eoff + (row - m * n)] = acc[tm][tn][r];
+            }
+        }
+    }
+}
+
+// Tiles of XCD pool x for a GEMM order: its element blocks eb = x (mod 8),
+// each with all RB operator row blocks.
+__device__ inline int64_t pool_tiles(const BOrder& o, int nmat, int x, int& RB) {
+    RB = (nmat * o.nunit + GBM - 1) / GBM;
+    const int64_t EB = (o.count + GBN - 1) / GBN;
+    return EB > x ? ((EB - x + 7) / 8) * RB : 0;
+}
+
+// The GEMM orders' tiles form one pool per XCD (highest order first).  Every
+// work-group drains its own XCD's pool, then the others', claiming one tile
+// at a time with an atomic cursor; the work-groups whose static share ran out
+// early thereby take over the remaining GEMM work, and the split needs no
+// exact cost estimate.  The last work-group to finish resets the cursors for
+// the next launch.
+__device__ void gemm_pool(const BArgs& a, float* sm) {
+    __shared__ int64_t claim;
+    const int x0 = (int)(blockIdx.x & 7);
+    for (int xi = 0; xi < 8; ++xi) {
+        const int x = (x0 + xi) & 7;
+        int64_t total = 0;
+        for (int p = 7; p >= 1; --p) {
+            const BOrder& o = a.ord[p];
+            if (o.variant != kGemmVariant || o.count == 0) continue;
+            int RB;
+            total += pool_tiles(o, a.nmat, x, RB);
+        }
+        while (true) {
+            // another XCD's drained pool is seen by a plain load, without
+            // one more atomic on its cursor
+            if (threadIdx.x == 0) {
+                const int seen =
+                    xi == 0 ? 0 : __hip_atomic_load(&a.ctr[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                claim = seen >= total ? total : atomicAdd(&a.ctr[x], 1);
+            }
+            __syncthreads();
+            int64_t t = claim;
+            __syncthreads();
+            if (t >= total) break;
+            for (int p = 7; p >= 1; --p) {
+                const BOrder& o = a.ord[p];
+                if (o.variant != kGemmVariant || o.count == 0) continue;
+                int RB;
+                const int64_t nt = pool_tiles(o, a.nmat, x, RB);
+                if (t < nt) {
+                    gemm_tile(a, o, x + 8 * (t / RB), (int)(t % RB), sm);
+                    break;
+                }
+                t -= nt;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&a.ctr[8], 1) == (int)gridDim.x - 1) {
+            for (int x = 0; x < 9; ++x) atomicExch(&a.ctr[x], 0);
+            __threadfence();
+        }
     }
 }
 
@@ -357,8 +379,6 @@ __device__ void valu_body(const BArgs& a, const BOrder& o, int64_t lb) {
     X(0, 4, 1) X(1, 4, 2) X(2, 8, 1) X(3, 8, 2) X(4, 16, 1) X(5, 16, 2) X(6, 32, 1) X(7, 32, 2) \
     X(8, 56, 1)
 
-constexpr int kGemmVariant = 20, kValu8Variant = 21;
-
 __global__ void __launch_bounds__(256) dg_batched_kernel(BArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     float* dl = reinterpret_cast<float*>(smem);
@@ -373,14 +393,15 @@ __global__ void __launch_bounds__(256) dg_batched_kernel(BArgs a) {
         break;
         DG_BATCHED_VARIANTS(X)
 #undef X
-        case kGemmVariant:
-            gemm_body(a, o, lb, dl);
-            break;
         case kValu8Variant:
             valu_body<8>(a, o, lb);
             break;
-        default:
+        default:  // GEMM orders: all their tiles come from the pool
             break;
+    }
+    if (a.pool) {
+        __syncthreads();  // the static part's LDS use ends before the pool's begins
+        gemm_pool(a, dl);
     }
 }
 
@@ -413,6 +434,7 @@ struct BatchPlan {
     int64_t grid = 0;
     int64_t* d_perm = nullptr;
     int64_t* d_off = nullptr;
+    int* d_ctr = nullptr;  // GEMM tile pool cursors (zero between launches)
     PlanOrder ord[8];
     double predicted_s = 0;
 };
@@ -604,11 +626,16 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
     // roofline estimate at the rates the bodies sustain on this GPU, about
     // 80 TFLOP/s and 2.5 TB/s (flops alone would starve the memory-bound low
     // orders)
+    // Orders on the GEMM body draw their tiles from the pool, which every
+    // work-group joins once its own share is done, so the split only has to
+    // keep the other orders from finishing last: their shares are sized 1.25x
+    // their estimate (the excess flows into the pool).
     auto weight = [&](int p) {
         const PlanOrder& po = P->ord[p];
-        if (cost) return std::max(po.predicted_s, 1e-7);
         const double nn = std::pow((double)(p + 1), 3.0);
-        return std::max(6.0 * nn * nn * po.count / 80e12, 16.0 * nn * po.count / 2.5e12);
+        const double w = cost ? std::max(po.predicted_s, 1e-7)
+                              : std::max(6.0 * nn * nn * po.count / 80e12, 16.0 * nn * po.count / 2.5e12);
+        return po.b.variant == kGemmVariant ? w : 1.25 * w;
     };
     double wsum = 0;
     for (int p = 1; p <= 7; ++p)
@@ -636,6 +663,8 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
     P->grid = lo;
     P->predicted_s = pred_total;
     // device copies of the id list and the offsets
+    DG_HIP_CHECK(hipMalloc(&P->d_ctr, sizeof(int) * 9));
+    DG_HIP_CHECK(hipMemset(P->d_ctr, 0, sizeof(int) * 9));
     if (nelem > 0) {
         DG_HIP_CHECK(hipMalloc(&P->d_perm, sizeof(int64_t) * nelem));
         DG_HIP_CHECK(hipMalloc(&P->d_off, sizeof(int64_t) * (nelem + 1)));
@@ -651,6 +680,7 @@ void batch_plan_destroy(BatchPlan* P) {
     if (!P) return;
     if (P->d_perm) (void)hipFree(P->d_perm);
     if (P->d_off) (void)hipFree(P->d_off);
+    if (P->d_ctr) (void)hipFree(P->d_ctr);
     delete P;
 }
 
@@ -665,6 +695,10 @@ dg_status batch_apply(const BatchPlan* P, const void* const* D_sets, const void*
     a.total = P->total;
     a.nmat = P->nmat;
     a.waves = P->waves;
+    a.ctr = P->d_ctr;
+    a.pool = 0;
+    for (int p = 1; p <= 7; ++p)
+        if (P->ord[p].present && P->ord[p].b.variant == kGemmVariant) a.pool = 1;
     int64_t lo = 0;
     for (int p = 1; p <= 7; ++p) {
         a.blk_lo[p] = lo;

@@ -86,6 +86,23 @@ def test_batched_gemm_body_all_orders(orc, ops, nelem):
     assert normwise_rel(got, ref) <= 1e-5
 
 
+def test_batched_plan_reuse(orc, ops):
+    """One plan, several launches in a row (the GEMM tile pool's cursors must
+    be back at zero for every launch), with different data each time."""
+    order = I.batched_orders(5000, seed=9)
+    off = I.batched_offsets(order)
+    D32 = _dsets(range(1, 8))
+    plan = ops.BatchedPlan(order)
+    Dg = {p: torch.from_numpy(D).cuda() for p, D in D32.items()}
+    for rep in range(4):
+        u32 = np.random.default_rng(10 + rep).uniform(-1, 1, int(off[-1])).astype(np.float32)
+        out = plan.apply(Dg, torch.from_numpy(u32).cuda())
+        torch.cuda.synchronize()
+        ref = orc.dg_batched(order, off, {p: D.astype(np.float64) for p, D in D32.items()},
+                             u32.astype(np.float64))
+        assert normwise_rel(out.double().cpu().numpy(), ref) <= 1e-5, rep
+
+
 def test_batched_single_order_equals_plain(ops):
     """All elements of one order: the packed layout is the plain layout, and
     the result matches dgdiff_apply on the same data."""
