@@ -48,7 +48,7 @@ typedef enum {
      elems_per_wave  element columns owned by one wave per tile: 16, 32 or 64
                      (1, 2 or 4 16-wide MFMA column blocks; 64 only while
                      nunit <= 128 in FP32 / nunit <= 64 in FP64)
-     waves           waves (64 lanes each) per work-group: 1..4
+     waves           waves (64 lanes each) per work-group: 1..8
      groups_per_cu   resident work-groups per compute unit of the persistent
                      grid; 0 = the occupancy maximum
      d_panels        16-row panels of the operator stack staged in LDS at a

@@ -205,7 +205,7 @@ dg_status launch_grad_u(int nmat, int64_t nelem, int nunit, const void* D, const
     const int kq = kq_for(nunit);
     if (kq < 0) return fail(DG_EUNSUPPORTED, "nunit too large for the DG kernel");
     const int waves = (tile && tile->waves) ? tile->waves : 4;
-    if (waves < 1 || waves > 4) return fail(DG_EINVAL, "tile.waves must be in 1..4");
+    if (waves < 1 || waves > 8) return fail(DG_EINVAL, "tile.waves must be in 1..8");
     KArgs a = {};
     a.nelem = nelem;
     a.nunit = nunit;

@@ -18,13 +18,13 @@ dg_status launch_fwd(int nmat, int64_t nelem, int nunit, const void* D, const vo
                      const dg_tile* tile, hipStream_t s) {
     const int kq = kq_for(nunit);
     if (kq < 0) return fail(DG_EUNSUPPORTED, "nunit too large for the DG kernel");
-    const int waves = (tile && tile->waves) ? tile->waves : 4;
-    if (waves < 1 || waves > 4) return fail(DG_EINVAL, "tile.waves must be in 1..4");
     const bool rows_aligned =
         (nunit % Mma<T>::V == 0) && (reinterpret_cast<uintptr_t>(u) % 16 == 0);
     int cb;
     dg_status st = forward_cb(sizeof(T), kq, rows_aligned, tile ? tile->elems_per_wave : 0, &cb);
     if (st != DG_OK) return st;
+    const int waves = (tile && tile->waves) ? tile->waves : forward_waves(sizeof(T), kq, cb, rows_aligned);
+    if (waves < 1 || waves > 8) return fail(DG_EINVAL, "tile.waves must be in 1..8");
     KArgs a = {};
     a.D = D;
     a.src = u;
@@ -51,10 +51,10 @@ dg_status resolve_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_
     const size_t ts = t == DG_F64 ? 8 : 4;
     const int kq = kq_for(nunit);
     if (kq < 0) return fail(DG_EUNSUPPORTED, "nunit too large for the DG kernel");
-    if (tile->waves == 0) tile->waves = 4;
     int cb;
     dg_status st = forward_cb(ts, kq, nunit % (int)(16 / ts) == 0, tile->elems_per_wave, &cb);
     if (st != DG_OK) return st;
+    if (tile->waves == 0) tile->waves = forward_waves(ts, kq, cb, nunit % (int)(16 / ts) == 0);
     tile->elems_per_wave = 16 * cb;
     DeviceInfo dev;
     st = current_device(&dev);

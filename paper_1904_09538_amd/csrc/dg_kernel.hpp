@@ -139,6 +139,27 @@ __device__ inline void stage_panels(const T* __restrict__ D, T* dl, int p0, int 
     }
 }
 
+// V consecutive values of a row that starts at any element-size boundary;
+// `avail` of them (from p on) belong to the row, the rest read as zero.  A
+// full vector is one 16-byte load (the 16-byte copy is left to the compiler,
+// which issues a single vector access on this target); row tails go value
+// by value.
+template <typename T>
+__device__ inline typename Mma<T>::vec_t load_vec_any(const T* p, bool ok, int avail) {
+    typedef typename Mma<T>::vec_t vec_t;
+    constexpr int V = Mma<T>::V;
+    vec_t v = vec_t(T(0));
+    if (!ok || avail <= 0) return v;
+    if (avail >= V) {
+        __builtin_memcpy(&v, p, 16);
+    } else {
+#pragma unroll
+        for (int t = 0; t < V - 1; ++t)
+            if (t < avail) v[t] = p[t];
+    }
+    return v;
+}
+
 // B fragments of one 16-element column block straight from global memory:
 // KQ contiguous nodes of the lane's element from node g*KQ; zero beyond nunit
 // or nelem.  Requires 16-byte aligned rows (vec_in).
@@ -220,8 +241,17 @@ __device__ inline void write_staged(const T* st, T* __restrict__ dst, int nel, i
 
 // ACC: out += result instead of out = result (a compile-time switch: as a
 // runtime branch it costs the FP32 kernels ~150 registers).
+// Work-groups of up to 8 waves for variants whose element operand takes at
+// most 64 registers (more waves then share one copy of the resident
+// operator panels); the register-heavy variants keep 4 waves so that they
+// may use the whole register file.
+template <typename T, int KQ, int CB, int NSEG>
+constexpr int dg_max_threads() {
+    return CB * NSEG * KQ * (int)sizeof(T) <= 256 ? 512 : 256;
+}
+
 template <typename T, int KQ, int CB, int NSEG, bool ACC = false>
-__global__ void __launch_bounds__(256) dg_kernel(KArgs a) {
+__global__ void __launch_bounds__((dg_max_threads<T, KQ, CB, NSEG>())) dg_kernel(KArgs a) {
     typedef typename Mma<T>::acc_t acc_t;
     typedef typename Mma<T>::vec_t vec_t;
     constexpr int V = Mma<T>::V;
@@ -268,16 +298,21 @@ __global__ void __launch_bounds__(256) dg_kernel(KArgs a) {
                 for (int cb = 0; cb < CB; ++cb)
                     load_b_global<T, KQ>(src + s * a.seg_stride, e0 + cb * 16 + c, g, a, b[s][cb]);
         } else if (!a.use_slab) {
-            // unaligned rows too long for a wave slab: masked scalar loads
+            // unaligned rows too long for a wave slab: 16-byte vectors from
+            // element-size boundaries, row tails value by value
 #pragma unroll
             for (int s = 0; s < NSEG; ++s)
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) {
                     const int64_t e = e0 + cb * 16 + c;
-                    const T* row = src + s * a.seg_stride + (e < a.nelem ? e : 0) * nunit + g * KQ;
+                    const bool ok = e < a.nelem;
+                    const T* row = src + s * a.seg_stride + (ok ? e : 0) * nunit + g * KQ;
 #pragma unroll
-                    for (int t = 0; t < KQ; ++t)
-                        b[s][cb][t] = (e < a.nelem && g * KQ + t < nunit) ? row[t] : T(0);
+                    for (int t = 0; t < KQ; t += V) {
+                        const vec_t v = load_vec_any<T>(row + t, ok, nunit - g * KQ - t);
+#pragma unroll
+                        for (int q = 0; q < V; ++q) b[s][cb][t + q] = v[q];
+                    }
                 }
         } else {
             const int nel = (int)min<int64_t>(16 * CB, a.nelem - e0);
@@ -371,10 +406,23 @@ __global__ void __launch_bounds__(256) dg_kernel(KArgs a) {
                             reinterpret_cast<f64x2*>(dst)[1] = hi;
                         }
                     }
-                } else {
+                } else if (i < nunit) {
+                    // unaligned row: 16-byte vectors from element-size
+                    // boundaries, the row tail value by value
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (i + r < nunit) dst[r] = acc[cb][r];
+                    for (int h = 0; h < 4 / V; ++h) {
+                        const int av = nunit - i - h * V;
+                        vec_t w;
+#pragma unroll
+                        for (int t = 0; t < V; ++t) w[t] = acc[cb][h * V + t];
+                        if (av >= V) {
+                            __builtin_memcpy(dst + h * V, &w, 16);
+                        } else {
+#pragma unroll
+                            for (int t = 0; t < V - 1; ++t)
+                                if (t < av) dst[h * V + t] = w[t];
+                        }
+                    }
                 }
             }
         }
@@ -483,6 +531,12 @@ dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, in
     DeviceInfo dev;
     dg_status st = current_device(&dev);
     if (st != DG_OK) return st;
+    {
+        hipFuncAttributes fa;
+        DG_HIP_CHECK(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(fn)));
+        if (64 * waves > fa.maxThreadsPerBlock)
+            return fail(DG_EINVAL, "tile.waves above 4 needs a shape whose element data fit 64 registers");
+    }
     const bool src_vec_ok = (a.nunit % Mma<T>::V == 0) &&
                             (reinterpret_cast<uintptr_t>(a.src) % 16 == 0) &&
                             (a.seg_stride % Mma<T>::V == 0);
@@ -526,12 +580,19 @@ dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, in
 inline dg_status forward_cb(size_t tsize, int kq, bool rows_aligned, int epw, int* cb) {
     if (epw == 0) {
         const int w = kq * (int)tsize / 4;  // KQ in 32-bit registers
-        // short rows: one column block (unaligned ones then fit the wave slab
-        // in both directions); measured fastest for p = 2 and p = 3
-        if (w <= 16) *cb = 1;
-        else if (w <= 32) *cb = 4;
-        else if (w <= 64) *cb = 2;
-        else *cb = 1;
+        if (tsize == 4) {
+            // FP32, measured on the hexahedral orders at 2^21 elements (with
+            // the wave counts of forward_waves): p = 3 one column block, p = 2
+            // and p = 4 (rows off 16-byte boundaries) two, p = 5 one
+            if (w <= 16) *cb = rows_aligned ? 1 : 2;
+            else if (w <= 32) *cb = 2;
+            else *cb = 1;
+        } else {
+            if (w <= 16) *cb = 1;
+            else if (w <= 32) *cb = 4;
+            else if (w <= 64) *cb = 2;
+            else *cb = 1;
+        }
     } else if (epw == 16) {
         *cb = 1;
     } else if (epw == 32) {
@@ -543,6 +604,16 @@ inline dg_status forward_cb(size_t tsize, int kq, bool rows_aligned, int epw, in
                     "tile.elems_per_wave must be 16 or 32 (or 64 for nunit <= 128 in FP32)");
     }
     return DG_OK;
+}
+
+// Default waves per work-group: 8 (two copies' worth of waves sharing one
+// set of resident operator panels) where the variant allows 512 threads and
+// it measured faster -- FP32 rows off 16-byte boundaries, and FP32 rows of
+// 128 or more nodes per lane group -- else 4.
+inline int forward_waves(size_t tsize, int kq, int cb, bool rows_aligned) {
+    const bool fits = cb * kq * (int)tsize <= 256;  // dg_max_threads() == 512
+    if (tsize == 4 && fits && (!rows_aligned || kq >= 32)) return 8;
+    return 4;
 }
 
 }  // namespace kern

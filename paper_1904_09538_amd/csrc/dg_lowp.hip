@@ -160,8 +160,15 @@ __device__ inline void lp_load_b(const typename LP<FMT>::G* __restrict__ u, int6
     }
 }
 
+// up to 8 waves per work-group while the element operand (KS*CB 16-byte
+// fragments) takes at most 56 registers
+template <int KS, int CB>
+constexpr int lp_max_threads() {
+    return KS * CB <= 14 ? 512 : 256;
+}
+
 template <int FMT, int KS, int CB>
-__global__ void __launch_bounds__(256) dg_lowp_kernel(LpArgs a) {
+__global__ void __launch_bounds__((lp_max_threads<KS, CB>())) dg_lowp_kernel(LpArgs a) {
     typedef typename LP<FMT>::L E;
     typedef typename LP<FMT>::G GE;
     typedef typename LP<FMT>::F F;
@@ -188,6 +195,12 @@ __global__ void __launch_bounds__(256) dg_lowp_kernel(LpArgs a) {
     const int p_lo = pg * a.ppg;
     const int np = min(a.ppg, a.panels_total - p_lo);
     lp_stage_panels<FMT, KS>(D, dl, p_lo, np, nunit, a.mblk);
+    // operator scales in LDS: a global load inside the panel loop would make
+    // every panel wait for all earlier stores (one counter covers loads and
+    // stores), serialising the loop
+    __shared__ float s_inv_sD[8];
+    if (threadIdx.x < 8) s_inv_sD[threadIdx.x] = (a.inv_sD && (int)threadIdx.x * a.mblk < a.panels_total)
+                                                     ? a.inv_sD[threadIdx.x] : 1.0f;
     __syncthreads();
 
     const int64_t tile_elems = (int64_t)nw * 16 * CB;
@@ -216,7 +229,7 @@ __global__ void __launch_bounds__(256) dg_lowp_kernel(LpArgs a) {
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) acc[cb] = LP<FMT>::mma(av, b[cb][s], acc[cb]);
             }
-            const float msc = a.inv_sD ? a.inv_sD[m] : 1.0f;
+            const float msc = s_inv_sD[m];
             const int i = i0 + 4 * g;
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
@@ -272,7 +285,7 @@ dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_til
     P->ks = (int)ceil_div(nunit, 32);
     if (P->ks > 16) return fail(DG_EUNSUPPORTED, "nunit too large");
     P->waves = (tile && tile->waves) ? tile->waves : 4;
-    if (P->waves < 1 || P->waves > 4) return fail(DG_EINVAL, "tile.waves must be in 1..4");
+    if (P->waves < 1 || P->waves > 8) return fail(DG_EINVAL, "tile.waves must be in 1..8");
     const int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : 32;
     if (epw == 16) P->cb = 1;
     else if (epw == 32) P->cb = 2;
@@ -306,6 +319,10 @@ dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_til
 static dg_status lp_occupancy(const LpPlan& P, int* per_cu) {
     lp_fn fn = lp_kernel(P.fmt, P.ks, P.cb);
     if (!fn) return fail(DG_EUNSUPPORTED, "no low-precision DG kernel instance");
+    hipFuncAttributes fa;
+    DG_HIP_CHECK(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(fn)));
+    if (64 * P.waves > fa.maxThreadsPerBlock)
+        return fail(DG_EINVAL, "tile.waves above 4 needs a shape whose element data fit 64 registers");
     DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
     DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, reinterpret_cast<const void*>(fn),

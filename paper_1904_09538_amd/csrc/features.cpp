@@ -169,7 +169,7 @@ dg_status perf_features_count(const perf_kernel_desc* d, int64_t* counts) {
         case DG_K_DGDIFF:
             if (d->nunit < 1 || d->nunit > 512 || d->nmat < 1 || d->nmat > 8)
                 return fail(DG_EUNSUPPORTED, "perf_features_count: DG sizes");
-            if (d->tile.waves < 1 || d->tile.waves > 4 || d->tile.elems_per_wave == 0 ||
+            if (d->tile.waves < 1 || d->tile.waves > 8 || d->tile.elems_per_wave == 0 ||
                 d->tile.groups_per_cu < 1 || d->tile.d_panels < 1 || d->num_cu < 1)
                 return fail(DG_EINVAL, "perf_features_count: DG needs a resolved tile and num_cu");
             if (d->n0 == 0) return DG_OK;

@@ -35,7 +35,7 @@ def _dg_cases():
             for _ in range(3):
                 nmat = int(rng.choice([1, 2, 3]))
                 E = int(rng.choice([1, 15, 17, 129, 300, 1000, 4097]))
-                waves = int(rng.choice([1, 2, 3, 4]))
+                waves = int(rng.choice([1, 2, 3, 4, 6, 8]))
                 epw = int(rng.choice([16, 32, 64]))
                 per_cu = int(rng.choice([1, 2, 3]))
                 P = nmat * ((nunit + 15) // 16)
