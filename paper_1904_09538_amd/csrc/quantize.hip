@@ -9,9 +9,10 @@
 //              (per_row = 1) or for the whole array; inv_scale = 1/s.  Scaling by a power of two is exact, so the
 //              de-scaling in the DG epilogue is exact too.
 //
-// One wave per row: a max-reduction over the row (order-independent, exact),
-// then the encode pass.  The whole-array scale runs one wave over everything;
-// it is meant for small operator stacks.
+// Rows up to 1024 values: one wave per row held in registers (below).  Longer
+// rows: one wave per row, a max-reduction over the row (order-independent,
+// exact), then the encode pass reading the row again.  The whole-array scale
+// runs one wave over everything; it is meant for small operator stacks.
 #include "common.hpp"
 
 namespace dg {
@@ -111,6 +112,107 @@ __global__ void __launch_bounds__(256) quantize_rows_kernel(int to_fp8, int64_t 
     }
 }
 
+// Rows of at most 256*NV values (every element row of the DG operands): lane
+// l owns values 4(l + 64k) .. +3, k < NV, held in registers between the max
+// pass and the encode pass; loads are 16-byte vectors from any 4-byte
+// boundary and each lane writes its four codes with one store.  A wave takes
+// four rows per step so that the later rows' loads are in flight while the
+// first is reduced and encoded.
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ inline f4v load4_any(const float* p, int avail) {
+    f4v v = {0.f, 0.f, 0.f, 0.f};
+    if (avail >= 4) {
+        __builtin_memcpy(&v, p, 16);
+    } else {
+        for (int t = 0; t < 3; ++t)
+            if (t < avail) v[t] = p[t];
+    }
+    return v;
+}
+
+template <int NV>
+__device__ inline void quantize_short_row(int to_fp8, int64_t r, int64_t cols, const f4v (&v)[NV],
+                                          void* __restrict__ q, float* __restrict__ inv_scale, int lane) {
+    if (!to_fp8) {
+        uint16_t* qr = static_cast<uint16_t*>(q) + r * cols;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int64_t c = 4 * (lane + 64 * k);
+            const int64_t avail = cols - c;
+            if (avail <= 0) continue;
+            uint16_t h[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) h[t] = bf16_rne(v[k][t]);
+            if (avail >= 4) {
+                __builtin_memcpy(qr + c, h, 8);
+            } else {
+                for (int t = 0; t < 3; ++t)
+                    if (t < avail) qr[c + t] = h[t];
+            }
+        }
+        if (inv_scale && lane == 0) inv_scale[r] = 1.0f;
+        return;
+    }
+    float amax = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float a = fabsf(v[k][t]);
+            amax = a > amax ? a : amax;  // NaN entries do not take part in the scale
+        }
+    amax = wave_max(amax);
+    const int ks = pow2_scale_exp_448(amax);
+    const float sc = exp2_bits(ks);
+    uint8_t* qr = static_cast<uint8_t*>(q) + r * cols;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const int64_t c = 4 * (lane + 64 * k);
+        const int64_t avail = cols - c;
+        if (avail <= 0) continue;
+        uint8_t b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[t] = e4m3_rne(v[k][t] * sc);
+        if (avail >= 4) {
+            __builtin_memcpy(qr + c, b, 4);
+        } else {
+            for (int t = 0; t < 3; ++t)
+                if (t < avail) qr[c + t] = b[t];
+        }
+    }
+    if (lane == 0) inv_scale[r] = exp2_bits(-ks);
+}
+
+template <int NV>
+__global__ void __launch_bounds__(256) quantize_short_rows_kernel(int to_fp8, int64_t rows, int64_t cols,
+                                                                 const float* __restrict__ x,
+                                                                 void* __restrict__ q,
+                                                                 float* __restrict__ inv_scale) {
+    constexpr int RS = 4;  // rows in flight per wave
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r0 = wave; r0 < rows; r0 += RS * nwaves) {
+        f4v v[RS][NV];
+#pragma unroll
+        for (int j = 0; j < RS; ++j) {
+            const int64_t r = r0 + j * nwaves;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                const int64_t c = 4 * (lane + 64 * k);
+                v[j][k] = r < rows ? load4_any(x + r * cols + c, (int)min<int64_t>(cols - c, 4))
+                                   : f4v{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RS; ++j) {
+            const int64_t r = r0 + j * nwaves;
+            if (r < rows) quantize_short_row<NV>(to_fp8, r, cols, v[j], q, inv_scale, lane);
+        }
+    }
+}
+
 }  // namespace
 
 dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, const float* x,
@@ -120,10 +222,27 @@ dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, 
         cols = rows * cols;
         rows = 1;
     }
+    const int fp8 = to == DG_FP8E4M3 ? 1 : 0;
+    if (cols <= 1024) {
+        // four rows per wave and step; 16384 waves fill the GPU several times
+        const int64_t waves = std::min<int64_t>(ceil_div(rows, 4), 16384);
+        const int64_t blocks = ceil_div(waves, 4);
+        if (cols <= 256)
+            hipLaunchKernelGGL(quantize_short_rows_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, fp8,
+                               rows, cols, x, q, inv_scale);
+        else if (cols <= 512)
+            hipLaunchKernelGGL(quantize_short_rows_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, fp8,
+                               rows, cols, x, q, inv_scale);
+        else
+            hipLaunchKernelGGL(quantize_short_rows_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, s, fp8,
+                               rows, cols, x, q, inv_scale);
+        DG_HIP_CHECK(hipGetLastError());
+        return DG_OK;
+    }
     const int64_t waves = std::min<int64_t>(rows, 65536);
     const int64_t blocks = ceil_div(waves, 4);
-    hipLaunchKernelGGL(quantize_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
-                       to == DG_FP8E4M3 ? 1 : 0, rows, cols, x, q, inv_scale);
+    hipLaunchKernelGGL(quantize_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, fp8, rows, cols, x, q,
+                       inv_scale);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
 }
