@@ -140,8 +140,10 @@ void dgdiff_plan_destroy(dg_plan* plan);
        grad_D[m][i][j] = sum_e g[m][e][i] u[e][j]               [nmat][nunit][nunit]
    t is DG_F32 or DG_F64 (all arrays of t).  Either output may be NULL (not
    computed).  grad_D is reduced over element splits into the caller's
-   workspace ws (>= dgdiff_backward_workspace(...) bytes; unused when grad_D
-   is NULL) and then summed in a fixed order: results are deterministic.
+   workspace ws (>= dgdiff_backward_workspace(...) bytes, a size that depends
+   on the current device's CU count and the kernel's occupancy there; unused
+   when grad_D is NULL) and then summed in a fixed order: results are
+   deterministic.
    nelem == 0 gives grad_D = 0 and touches no workspace.                     */
 size_t dgdiff_backward_workspace(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit);
 dg_status dgdiff_backward(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit, const void* D,

@@ -10,7 +10,7 @@
 //
 // grad_D is a GEMM C[(m,i)][j] = sum_e G_m^T[i][e] U[e][j] with a very long
 // contraction (the element count).  It is split: work-group (tile, split)
-// multiplies one 64x64 output tile over one contiguous element range on the
+// multiplies one 128x128 output tile over one contiguous element range on the
 // matrix cores and writes an FP32/FP64 partial tile to the caller's
 // workspace; a second kernel adds the partials of every entry in split order
 // 0, 1, 2, ...  The result is therefore deterministic (no atomics, no
@@ -24,9 +24,8 @@ using namespace kern;
 
 // ------------------------------------------------------------------ grad_D
 
-constexpr int GT = 64;      // output tile (rows i x cols j)
+constexpr int GT = 128;     // output tile (rows i x cols j): all of i and j up to nunit 128
 constexpr int GK = 16;      // elements per LDS chunk
-constexpr int GLD = GT + 4; // LDS row stride
 
 struct GdArgs {
     const void* g;
@@ -37,29 +36,38 @@ struct GdArgs {
     int nmat;
     int nunit;
     int ntile;            // ceil(nunit / GT)
-    int vec;              // 16-byte loads allowed
 };
 
+// Four consecutive values of a row from any element-size boundary (one or
+// two 16-byte loads, the copy left to the compiler); `avail` of them belong
+// to the row, the rest read as zero.
 template <typename T>
-__device__ inline void gd_load(const GdArgs& a, const T* __restrict__ gm, const T* __restrict__ u,
-                               int64_t e0, int64_t e_hi, int i0, int j0, int t, T (&rg)[4],
-                               T (&ru)[4]) {
-    const int el = t >> 4;           // element within the chunk
-    const int x = (t & 15) * 4;      // 4 consecutive nodes
-    const int64_t e = e0 + el;
-    const bool ev = e < e_hi;
-    const int n = a.nunit;
+__device__ inline void gd_load4(const T* p, bool ok, int avail, T (&v)[4]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        rg[q] = (ev && i0 + x + q < n) ? gm[e * n + i0 + x + q] : T(0);
-        ru[q] = (ev && j0 + x + q < n) ? u[e * n + j0 + x + q] : T(0);
+    for (int q = 0; q < 4; ++q) v[q] = T(0);
+    if (!ok || avail <= 0) return;
+    if (avail >= 4) {
+        __builtin_memcpy(v, p, 4 * sizeof(T));
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (q < avail) v[q] = p[q];
     }
 }
 
+// Partial grad_D tile: C[i][j] = sum over the split's elements of g_m[e][i] u[e][j].
+// A work-group owns a GT x GT tile (4 waves of 64 x 64, 4 x 4 MFMA tiles
+// each) and walks its elements in chunks of GK.  Each chunk of g and u rows
+// is loaded with 16-byte vectors and stored element-major in LDS with
+// 16-byte stores (sixteen lanes per row: no bank conflicts); lane group g
+// contracts elements 4g .. 4g+3 of the chunk, reading each operand value
+// with one LDS load.  Chunks are double-buffered: the next one is fetched
+// into registers while the current one is multiplied.
 template <typename T>
 __global__ void __launch_bounds__(256) grad_d_partial_kernel(GdArgs a) {
     typedef typename Mma<T>::acc_t acc_t;
-    __shared__ __attribute__((aligned(16))) T lds[2][2][GK * GLD];  // [buf][g|u]
+    constexpr int NP = GT + 16 / (int)sizeof(T);  // LDS row stride (nodes + padding)
+    __shared__ __attribute__((aligned(16))) T lds[2][2][GK * NP];  // [buf][g|u][element][node]
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -74,66 +82,81 @@ __global__ void __launch_bounds__(256) grad_d_partial_kernel(GdArgs a) {
     const int64_t split = blockIdx.y;
     const int64_t e_lo = split * a.split_len;
     const int64_t e_hi = min<int64_t>(a.nelem, e_lo + a.split_len);
-    const T* __restrict__ gm = static_cast<const T*>(a.g) + (int64_t)m * a.nelem * a.nunit;
+    const int n = a.nunit;
+    const T* __restrict__ gm = static_cast<const T*>(a.g) + (int64_t)m * a.nelem * n;
     const T* __restrict__ u = static_cast<const T*>(a.u);
 
-    acc_t acc[2][2];
+    // staging: thread t loads element el = t/16 of the chunk, nodes x .. x+7
+    const int el_s = t >> 4, x_s = (t & 15) * 8;
+    T rg[8], ru[8];
+    auto load = [&](int64_t e0) {
+        const int64_t e = e0 + el_s;
+        const bool ok = e < e_hi;
+        const int64_t eo = (ok ? e : 0) * n;
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+        for (int h = 0; h < 2; ++h) {
+            T v[4];
+            gd_load4<T>(gm + eo + i0 + x_s + 4 * h, ok, n - (i0 + x_s + 4 * h), v);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) acc[p][q] = acc_t(T(0));
+            for (int q = 0; q < 4; ++q) rg[4 * h + q] = v[q];
+            gd_load4<T>(u + eo + j0 + x_s + 4 * h, ok, n - (j0 + x_s + 4 * h), v);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ru[4 * h + q] = v[q];
+        }
+    };
+    auto store = [&](int buf) {
+        // one element row per sixteen lanes, 8 nodes per lane: 16-byte stores
+        __builtin_memcpy(&lds[buf][0][el_s * NP + x_s], rg, 8 * sizeof(T));
+        __builtin_memcpy(&lds[buf][1][el_s * NP + x_s], ru, 8 * sizeof(T));
+    };
+
+    acc_t acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = acc_t(T(0));
 
     const int64_t nchunk = e_hi > e_lo ? ceil_div(e_hi - e_lo, GK) : 0;
-    T rg[4], ru[4];
-    const int el_w = t >> 4, x_w = (t & 15) * 4;
     if (nchunk > 0) {
-        gd_load<T>(a, gm, u, e_lo, e_hi, i0, j0, t, rg, ru);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            lds[0][0][el_w * GLD + x_w + q] = rg[q];
-            lds[0][1][el_w * GLD + x_w + q] = ru[q];
-        }
+        load(e_lo);
+        store(0);
     }
     __syncthreads();
     for (int64_t kc = 0; kc < nchunk; ++kc) {
         const int buf = kc & 1;
-        if (kc + 1 < nchunk) gd_load<T>(a, gm, u, e_lo + (kc + 1) * GK, e_hi, i0, j0, t, rg, ru);
-        const T* Gs = lds[buf][0];
-        const T* Us = lds[buf][1];
+        const bool more = kc + 1 < nchunk;
+        if (more) load(e_lo + (kc + 1) * GK);
+        T av[4][4], bv[4][4];  // [tile][element 4g + s]
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int el = 4 * g + s;  // lane group g contracts elements 4g..4g+3 of the chunk
-            T av[2], bv[2];
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const T* Gr = &lds[buf][0][(4 * g + s4) * NP];
+            const T* Ur = &lds[buf][1][(4 * g + s4) * NP];
 #pragma unroll
-            for (int p = 0; p < 2; ++p) av[p] = Gs[el * GLD + wr * 32 + p * 16 + c];
+            for (int p = 0; p < 4; ++p) av[p][s4] = Gr[wr * 64 + p * 16 + c];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) bv[q] = Us[el * GLD + wc * 32 + q * 16 + c];
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int q = 0; q < 2; ++q) acc[p][q] = Mma<T>::step(av[p], bv[q], acc[p][q]);
+            for (int q = 0; q < 4; ++q) bv[q][s4] = Ur[wc * 64 + q * 16 + c];
         }
-        if (kc + 1 < nchunk) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                lds[buf ^ 1][0][el_w * GLD + x_w + q] = rg[q];
-                lds[buf ^ 1][1][el_w * GLD + x_w + q] = ru[q];
-            }
-        }
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] = Mma<T>::step(av[p][s4], bv[q][s4], acc[p][q]);
+        if (more) store(buf ^ 1);
         __syncthreads();
     }
 
     // accumulator register r of lane group g: row acc_row(g, r), column c
-    T* ws = static_cast<T*>(a.ws) + (split * a.nmat + m) * (int64_t)a.nunit * a.nunit;
+    T* ws = static_cast<T*>(a.ws) + (split * a.nmat + m) * (int64_t)n * n;
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wr * 32 + p * 16 + Mma<T>::acc_row(g, r);
-                const int j = j0 + wc * 32 + q * 16 + c;
-                if (i < a.nunit && j < a.nunit) ws[(int64_t)i * a.nunit + j] = acc[p][q][r];
+                const int i = i0 + wr * 64 + p * 16 + Mma<T>::acc_row(g, r);
+                const int j = j0 + wc * 64 + q * 16 + c;
+                if (i < n && j < n) ws[(int64_t)i * n + j] = acc[p][q][r];
             }
 }
 
@@ -148,19 +171,50 @@ __global__ void __launch_bounds__(256) grad_d_reduce_kernel(const T* __restrict_
     out[idx] = s;
 }
 
+// Partials are summed in two fixed-order stages (groups of kRedGroup splits,
+// then the group sums), so the result does not depend on scheduling.
+constexpr int64_t kRedGroup = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(256) grad_d_reduce_groups_kernel(const T* __restrict__ ws,
+                                                                   T* __restrict__ ws2, int64_t count,
+                                                                   int64_t nsplit) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count) return;
+    const int64_t k0 = (int64_t)blockIdx.y * kRedGroup;
+    const int64_t k1 = min<int64_t>(nsplit, k0 + kRedGroup);
+    T s = T(0);
+    for (int64_t k = k0; k < k1; ++k) s += ws[k * count + idx];  // fixed order
+    ws2[(int64_t)blockIdx.y * count + idx] = s;
+}
+
 struct SplitPlan {
     int64_t nsplit;
     int64_t split_len;
+    int64_t ngroups;  // ceil(nsplit / kRedGroup)
 };
 
-SplitPlan plan_splits(int nmat, int64_t nelem, int nunit) {
+// As many splits as make one full round of resident work-groups (the
+// kernel's occupancy on the current device): a second, partial round would
+// leave most of the GPU idle at the end.
+template <typename T>
+dg_status plan_splits(int nmat, int64_t nelem, int nunit, SplitPlan* sp) {
+    DeviceInfo dev;
+    dg_status st = current_device(&dev);
+    if (st != DG_OK) return st;
+    int per_cu = 1;
+    DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(grad_d_partial_kernel<T>), 256, 0));
+    per_cu = std::max(per_cu, 1);
     const int64_t tiles = (int64_t)nmat * ceil_div(nunit, GT) * ceil_div(nunit, GT);
-    const int64_t target = 2048;  // work-groups to fill 256 CUs several times over
-    int64_t ns = std::max<int64_t>(1, ceil_div(target, tiles));
+    const int64_t target = (int64_t)per_cu * dev.num_cu;
+    int64_t ns = std::max<int64_t>(1, target / tiles);
     ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(nelem, 256)));
-    int64_t len = round_up(ceil_div(std::max<int64_t>(nelem, 1), ns), GK);
-    ns = std::max<int64_t>(1, ceil_div(nelem, len));
-    return {ns, len};
+    const int64_t len = round_up(ceil_div(std::max<int64_t>(nelem, 1), ns), GK);
+    sp->nsplit = std::max<int64_t>(1, ceil_div(nelem, len));
+    sp->split_len = len;
+    sp->ngroups = ceil_div(sp->nsplit, kRedGroup);
+    return DG_OK;
 }
 
 template <typename T>
@@ -175,8 +229,10 @@ dg_status launch_grad_d(int nmat, int64_t nelem, int nunit, const void* u, const
         DG_HIP_CHECK(hipGetLastError());
         return DG_OK;
     }
-    const SplitPlan sp = plan_splits(nmat, nelem, nunit);
-    const size_t need = (size_t)sp.nsplit * count * sizeof(T);
+    SplitPlan sp;
+    dg_status st = plan_splits<T>(nmat, nelem, nunit, &sp);
+    if (st != DG_OK) return st;
+    const size_t need = (size_t)(sp.nsplit + sp.ngroups) * count * sizeof(T);
     if (!ws || ws_bytes < need) return fail(DG_EINVAL, "dgdiff_backward: workspace too small");
     GdArgs a;
     a.g = g;
@@ -187,12 +243,15 @@ dg_status launch_grad_d(int nmat, int64_t nelem, int nunit, const void* u, const
     a.nmat = nmat;
     a.nunit = nunit;
     a.ntile = (int)ceil_div(nunit, GT);
-    a.vec = 0;
     dim3 grid((unsigned)(nmat * a.ntile * a.ntile), (unsigned)sp.nsplit);
     hipLaunchKernelGGL(grad_d_partial_kernel<T>, grid, dim3(256), 0, s, a);
     DG_HIP_CHECK(hipGetLastError());
+    T* ws2 = static_cast<T*>(ws) + sp.nsplit * count;
+    hipLaunchKernelGGL(grad_d_reduce_groups_kernel<T>, dim3((unsigned)ceil_div(count, 256), (unsigned)sp.ngroups),
+                       dim3(256), 0, s, static_cast<const T*>(ws), ws2, count, sp.nsplit);
+    DG_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(grad_d_reduce_kernel<T>, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, s,
-                       static_cast<const T*>(ws), static_cast<T*>(grad_D), count, sp.nsplit);
+                       static_cast<const T*>(ws2), static_cast<T*>(grad_D), count, sp.ngroups);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
 }
@@ -245,8 +304,11 @@ dg_status launch_grad_u(int nmat, int64_t nelem, int nunit, const void* D, const
 
 size_t backward_workspace_bytes(dg_dtype t, int nmat, int64_t nelem, int nunit) {
     if (nelem <= 0) return 0;
-    const SplitPlan sp = plan_splits(nmat, nelem, nunit);
-    return (size_t)sp.nsplit * nmat * nunit * nunit * dtype_size(t);
+    SplitPlan sp;
+    const dg_status st = t == DG_F64 ? plan_splits<double>(nmat, nelem, nunit, &sp)
+                                     : plan_splits<float>(nmat, nelem, nunit, &sp);
+    if (st != DG_OK) return 0;
+    return (size_t)(sp.nsplit + sp.ngroups) * nmat * nunit * nunit * dtype_size(t);
 }
 
 dg_status launch_dg_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D,
