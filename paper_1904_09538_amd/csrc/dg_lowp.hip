@@ -284,13 +284,16 @@ dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_til
     P->fmt = fmt;
     P->ks = (int)ceil_div(nunit, 32);
     if (P->ks > 16) return fail(DG_EUNSUPPORTED, "nunit too large");
-    P->waves = (tile && tile->waves) ? tile->waves : 4;
-    if (P->waves < 1 || P->waves > 8) return fail(DG_EINVAL, "tile.waves must be in 1..8");
-    const int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : 32;
+    // defaults measured at p = 5 (2^20 elements): BF16 one column block, FP8
+    // two, both with 8 waves per work-group where the variant allows it
+    const int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : (fmt == 0 ? 16 : 32);
     if (epw == 16) P->cb = 1;
     else if (epw == 32) P->cb = 2;
     else if (epw == 64 && P->ks <= 8) P->cb = 4;
     else return fail(DG_EINVAL, "tile.elems_per_wave must be 16, 32 (or 64 for nunit <= 256)");
+    const int wdef = P->ks * P->cb <= 14 ? 8 : 4;  // lp_max_threads() allows 512 threads
+    P->waves = (tile && tile->waves) ? tile->waves : wdef;
+    if (P->waves < 1 || P->waves > 8) return fail(DG_EINVAL, "tile.waves must be in 1..8");
     P->lds_esz = fmt == 1 ? 1 : 2;
     P->mblk = (int)ceil_div(nunit, 16);
     P->panels_total = nmat * P->mblk;
