@@ -236,6 +236,8 @@ enum {
     PF_GST_DG_OUT_UNAL,  /* DG output stores of unaligned rows (scalar), bytes */
     PF_WAVE_TILES,       /* DG element tiles processed by a wave, summed over operator groups */
     PF_SERIAL_STEPS,     /* longest chain of loop iterations one work-group walks (latency) */
+    PF_LAT_STEPS,        /* DG: 64 x serial steps / resident waves per SIMD (per_cu x waves / 4):
+                            the tile latency left unhidden by other waves (launch configuration) */
     PF_COUNT
 };
 

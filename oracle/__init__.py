@@ -195,7 +195,7 @@ def matmul_select(a, b, ii, jj):
 FEATURES = ["launch", "workgroups", "barrier_x_wg", "gld_dg_u", "gld_dg_u_l2", "gld_dg_d",
             "gst_dg_out", "gld_st_u", "gst_st_res", "gld_mm_ab", "gst_mm_c", "lds_bytes",
             "mfma_f64", "mfma_f32", "mfma_bf16", "mfma_fp8", "valu_f32", "valu_f64",
-            "gld_dg_u_unal", "gst_dg_out_unal", "wave_tiles", "serial_steps"]
+            "gld_dg_u_unal", "gst_dg_out_unal", "wave_tiles", "serial_steps", "lat_steps"]
 KERNELS = {"dg": 0, "stencil": 1, "matmul": 2, "empty": 3}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
 

@@ -25,7 +25,7 @@
 /* feature slots, in the order of the library's interface */
 enum { F_LAUNCH, F_WG, F_BAR, F_U, F_U_L2, F_D, F_OUT, F_ST_U, F_ST_RES, F_MM_AB, F_MM_C, F_LDS,
        F_MFMA_F64, F_MFMA_F32, F_MFMA_BF16, F_MFMA_FP8, F_VALU_F32, F_VALU_F64, F_U_UNAL, F_OUT_UNAL,
-       F_WAVE_TILES, F_SERIAL, F_N };
+       F_WAVE_TILES, F_SERIAL, F_LAT, F_N };
 
 enum { K_DG = 0, K_STENCIL = 1, K_MATMUL = 2, K_EMPTY = 3 };
 enum { T_F64 = 0, T_F32 = 1, T_BF16 = 2, T_FP8 = 3 };
@@ -219,6 +219,9 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
         }
         if (steps > c[F_SERIAL]) c[F_SERIAL] = steps;
     }
+    /* latency left unhidden: the busiest stream's steps over resident waves
+       per SIMD (per_cu work-groups of `waves` waves on 4 SIMDs), x 64 */
+    c[F_LAT] = c[F_SERIAL] * 64 / ((int64_t)per_cu * waves);
     return 0;
 }
 

@@ -45,7 +45,7 @@ SEED_SPLIT = 4
 # model expressions: the features each family's model uses (the paper builds one
 # model per application, with global-memory, on-chip and overhead terms)
 # and the cost group of each feature (0 overhead, 1 global memory, 2 on-chip)
-GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0, "serial_steps": 0,
+GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0, "serial_steps": 0, "lat_steps": 0,
          "gld_dg_u": 1, "gld_dg_u_unal": 1, "gld_dg_u_l2": 1, "gld_dg_d": 1, "gst_dg_out": 1,
          "gst_dg_out_unal": 1,
          "gld_st_u": 1, "gst_st_res": 1, "gld_mm_ab": 1, "gst_mm_c": 1,
@@ -55,7 +55,8 @@ GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0, "seri
 # the stencil (little overlap observed there)
 KIND = {"dg": "overlap", "stencil": "linear", "matmul": "overlap"}
 MODELS = {
-    "dg": ["launch", "workgroups", "wave_tiles", "serial_steps", "gld_dg_u", "gld_dg_u_unal", "gld_dg_u_l2",
+    "dg": ["launch", "workgroups", "wave_tiles", "serial_steps", "lat_steps", "gld_dg_u", "gld_dg_u_unal",
+           "gld_dg_u_l2",
            "gld_dg_d", "gst_dg_out", "gst_dg_out_unal", "lds_bytes", "mfma_f32"],
     "stencil": ["launch", "workgroups", "gld_st_u", "gst_st_res", "lds_bytes", "valu_f32"],
     "matmul": ["launch", "workgroups", "serial_steps", "barrier_x_wg", "gld_mm_ab", "gst_mm_c",
@@ -238,6 +239,52 @@ def geomean(pred, meas):
     return float(np.exp(np.mean(np.log(r))))
 
 
+def kendall_tau(a, b):
+    """Kendall rank correlation (tau-a) of two equal-length sequences."""
+    n = len(a)
+    if n < 2:
+        return None
+    s = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            s += np.sign(a[i] - a[j]) * np.sign(b[i] - b[j])
+    return float(s) / (n * (n - 1) / 2)
+
+
+def ranking(keys, pred, meas):
+    """The paper's main use of a model: ranking equivalent variants.  Rows
+    with the same key (one problem, different launch shapes) form a group;
+    per group, the Kendall tau between predicted and measured times, whether
+    the predicted fastest is the measured fastest, and the slowdown of the
+    predicted choice against the measured best (regret)."""
+    groups = {}
+    for k, p, m in zip(keys, pred, meas):
+        groups.setdefault(k, []).append((p, m))
+    taus, hits, regrets = [], [], []
+    sep_ok = sep_n = 0
+    for k, v in groups.items():
+        if len(v) < 2:
+            continue
+        p = [x[0] for x in v]
+        m = [x[1] for x in v]
+        taus.append(kendall_tau(p, m))
+        pick = int(np.argmin(p))
+        hits.append(1.0 if m[pick] == min(m) else 0.0)
+        regrets.append(m[pick] / min(m) - 1.0)
+        # pairs whose measured times differ by at least 10%: ordered right?
+        for i in range(len(v)):
+            for j in range(i + 1, len(v)):
+                if max(m[i], m[j]) >= 1.1 * min(m[i], m[j]):
+                    sep_n += 1
+                    sep_ok += int((p[i] - p[j]) * (m[i] - m[j]) > 0)
+    if not taus:
+        return None
+    return {"groups": len(taus), "kendall_tau_mean": float(np.mean(taus)),
+            "top1_rate": float(np.mean(hits)), "regret_mean": float(np.mean(regrets)),
+            "regret_max": float(np.max(regrets)),
+            "pairs_apart_10pct": sep_n, "pairs_apart_10pct_ordered": (sep_ok / sep_n) if sep_n else None}
+
+
 def fit_family(meta, rows, family, L, kind=None, with_overhead_rows=True):
     """Fit one family's model on its training rows (plus the empty-kernel rows,
     which pin the launch and work-group costs) and score the held-out rows.
@@ -288,6 +335,10 @@ def fit_family(meta, rows, family, L, kind=None, with_overhead_rows=True):
     out["nonneg"] = one(True)[0]
     out["heldout"] = [{"variant": {k: fam[i][k] for k in fam[i] if k not in ("features", "t")},
                        "measured_s": float(t[i]), "predicted_s": float(pred[i])} for i in held]
+    if family == "dg":
+        # launch shapes of one problem (order, element count), ranked by the
+        # model fitted on the training rows
+        out["ranking"] = ranking([(r["p"], r["nelem"]) for r in fam], pred, t)
     return out
 
 

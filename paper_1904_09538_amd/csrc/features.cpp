@@ -65,6 +65,7 @@ dg_status count_dg_fp(const perf_kernel_desc* d, int64_t* c) {
     c[(n % 4 == 0 || stage_out) ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] = E * M * n * (int64_t)sz;
     c[PF_WAVE_TILES] = nwt * P.ngroups;
     c[PF_SERIAL_STEPS] = ceil_div(P.ntiles, 8 * P.slots);  // tiles of the busiest stream
+    c[PF_LAT_STEPS] = c[PF_SERIAL_STEPS] * 64 / ((int64_t)d->tile.groups_per_cu * d->tile.waves);
     c[PF_LDS_BYTES] = 8 * P.slots * P.panels_total * 16 * KP * (int64_t)sz  // staging stores
                       + nwt * P.panels_total * 64 * kq * (int64_t)sz      // operand reads
                       + (P.use_slab ? (int64_t)P.ngroups * 2 * E * n * (int64_t)sz : 0)
@@ -93,6 +94,7 @@ dg_status count_dg_lowp(const perf_kernel_desc* d, int64_t* c) {
     c[n % 4 == 0 ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] = E * M * n * 4;
     c[PF_WAVE_TILES] = nwt * P.ngroups;
     c[PF_SERIAL_STEPS] = ceil_div(P.ntiles, 8 * P.slots);
+    c[PF_LAT_STEPS] = c[PF_SERIAL_STEPS] * 64 / ((int64_t)d->tile.groups_per_cu * P.waves);
     c[PF_LDS_BYTES] = 8 * P.slots * P.panels_total * 16 * KP * P.lds_esz +
                       nwt * P.panels_total * P.ks * 64 * 8 * P.lds_esz;
     c[fmt == 1 ? PF_MFMA_FP8 : PF_MFMA_BF16] = nwt * P.panels_total * P.ks * (int64_t)P.cb * 16384;
@@ -147,7 +149,7 @@ const char* kNames[PF_COUNT] = {
     "launch", "workgroups", "barrier_x_wg", "gld_dg_u", "gld_dg_u_l2", "gld_dg_d", "gst_dg_out",
     "gld_st_u", "gst_st_res", "gld_mm_ab", "gst_mm_c", "lds_bytes", "mfma_f64", "mfma_f32",
     "mfma_bf16", "mfma_fp8", "valu_f32", "valu_f64", "gld_dg_u_unal", "gst_dg_out_unal",
-    "wave_tiles", "serial_steps"};
+    "wave_tiles", "serial_steps", "lat_steps"};
 
 }  // namespace
 }  // namespace dg

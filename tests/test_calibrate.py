@@ -1,3 +1,4 @@
+import pytest
 """Host logic of the calibration harness on synthetic timings (CPU only):
 a consistent linear timing law is recovered (held-out MAPE ~ 0), injected
 10x outliers are dropped by the timing rule, the held-out split is seeded and
@@ -67,3 +68,21 @@ def test_outlier_rule_and_metrics():
     assert kept.size == 59
     assert C.mape([1.1, 0.9], [1.0, 1.0]) == 0.1 or abs(C.mape([1.1, 0.9], [1.0, 1.0]) - 0.1) < 1e-12
     assert abs(C.geomean([1.1, 1.2], [1.0, 1.0]) - np.sqrt(0.1 * 0.2)) < 1e-12
+
+
+def test_ranking_statistics():
+    from paper_1904_09538_amd import calibrate as C
+    keys = [1, 1, 1, 2, 2, 2, 3]
+    meas = [3.0, 1.0, 2.0, 5.0, 6.0, 4.0, 9.0]
+    exact = C.ranking(keys, meas, meas)
+    assert exact["groups"] == 2 and exact["kendall_tau_mean"] == 1.0 and exact["top1_rate"] == 1.0
+    assert exact["regret_mean"] == 0.0 and exact["regret_max"] == 0.0
+    # pairs at least 10% apart: group 1 all 3, group 2 (5,6),(6,4),(5,4): 3
+    assert exact["pairs_apart_10pct"] == 6 and exact["pairs_apart_10pct_ordered"] == 1.0
+    rev = C.ranking(keys, [-x for x in meas], meas)
+    assert rev["kendall_tau_mean"] == -1.0 and rev["top1_rate"] == 0.0
+    assert rev["pairs_apart_10pct_ordered"] == 0.0
+    # group 1 picks 3.0 (best 1.0): regret 2; group 2 picks 6.0 (best 4.0): 0.5
+    assert rev["regret_max"] == pytest.approx(2.0) and rev["regret_mean"] == pytest.approx(1.25)
+    assert C.kendall_tau([1, 2, 3], [1, 3, 2]) == pytest.approx(1 / 3)
+    assert C.ranking([1, 2], [1.0, 2.0], [1.0, 2.0]) is None
