@@ -63,12 +63,22 @@ def load_traffic(key: str, src_hash: str):
     return ent.get("hbm_bytes_per_launch")
 
 
-def timed(fn, steps, warmup):
-    """Average seconds per call, HIP events on the current stream."""
+def timed(fn, steps, warmup, warm_s=0.04):
+    """Average seconds per call, HIP events on the current stream.
+
+    Warm-up runs at least `warmup` calls and at least `warm_s` seconds of
+    them: the first milliseconds of sustained load after idle run at a
+    transient clock (a few launches fast, then a dip, then a slow climb to
+    the steady rate), and the rows report the steady rate."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -238,7 +248,9 @@ def row_model(path):
     fams = {k: {"kind": v["kind"], "mape_heldout": v["mape_heldout"],
                 "geomean_heldout": v["geomean_heldout"], "negative_params": v["negative_params"],
                 "nonneg_mape_heldout": v["nonneg"]["mape_heldout"], "n_train": v["n_train"],
-                "n_heldout": v["n_heldout"]} for k, v in s["families"].items()}
+                "n_heldout": v["n_heldout"],
+                **({"ranking": v["ranking"]} if "ranking" in v else {})}
+            for k, v in s["families"].items()}
     return s, {"mape_heldout_all": s["mape_heldout_all"],
                "geomean_heldout_all": s["geomean_heldout_all"], "families": fams,
                "protocol": "cold cache, 60 event-timed trials per variant, 20% held out (seed 4); "
@@ -277,7 +289,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--rows", default="all",
                     help="comma list of extra rows (orders,lowp,batched,adjoint,companions,model) "
                          "or 'all' or 'none'")

@@ -8,9 +8,9 @@ namespace {
 using namespace kern;
 
 template <typename T>
-kern_fn forward_kernel(int kq, int cb) {
-    return cb == 4 ? pick_kernel<T, 4, 1>(kq) : cb == 2 ? pick_kernel<T, 2, 1>(kq)
-                                                       : pick_kernel<T, 1, 1>(kq);
+kern_fn forward_kernel(int kq, int cb, bool pair = false) {
+    return cb == 4 ? pick_kernel<T, 4, 1>(kq, pair) : cb == 2 ? pick_kernel<T, 2, 1>(kq, pair)
+                                                             : pick_kernel<T, 1, 1>(kq, pair);
 }
 
 template <typename T>
@@ -33,7 +33,8 @@ dg_status launch_fwd(int nmat, int64_t nelem, int nunit, const void* D, const vo
     a.seg_stride = 0;
     a.nunit = nunit;
     a.transpose = 0;
-    return launch<T, 1>(a, nmat, kq, cb, tile, waves, forward_kernel<T>(kq, cb), s);
+    return launch<T, 1>(a, nmat, kq, cb, tile, waves, forward_kernel<T>(kq, cb), s,
+                        forward_kernel<T>(kq, cb, true));
 }
 
 }  // namespace
@@ -65,7 +66,9 @@ dg_status resolve_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_
     if (st != DG_OK) return st;
     tile->d_panels = P.ppg;
     if (tile->groups_per_cu == 0) {
-        kern_fn fn = t == DG_F64 ? forward_kernel<double>(kq, cb) : forward_kernel<float>(kq, cb);
+        // the kernel a launch into 16-byte aligned output would take
+        const bool pair = pair_eligible(ts, nunit, nunit % 4 == 0, P);
+        kern_fn fn = t == DG_F64 ? forward_kernel<double>(kq, cb) : forward_kernel<float>(kq, cb, pair);
         if (!fn) return fail(DG_EUNSUPPORTED, "no DG kernel instance");
         DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));

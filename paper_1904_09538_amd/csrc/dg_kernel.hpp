@@ -39,6 +39,15 @@
 // the same tile sequence: the tile is fetched from HBM once and re-read from
 // that XCD's L2 by the other groups.
 //
+// Paired stores.  A lane's four results of one panel are 16 bytes of one
+// element row, so a panel's store writes 64-byte pieces of 16 rows.  FP32
+// rows of a multiple of 32 nodes are written through a variant that computes
+// two consecutive panels of one output slab together and trades halves
+// between lanes c and c^8 (a DPP rotation by 8 within each 16-lane row): each
+// of its two stores then covers 8 elements with 32 consecutive nodes, one
+// 128-byte run each, which for such rows is a whole cache line.  Results and
+// their rounding are unchanged.
+//
 // Unaligned rows.  When nunit is not a multiple of the 16-byte vector (or the
 // source is not 16-byte aligned) a wave copies its contiguous slab of element
 // data into a wave-private LDS area with aligned 16-byte loads and reads its
@@ -250,7 +259,7 @@ constexpr int dg_max_threads() {
     return CB * NSEG * KQ * (int)sizeof(T) <= 256 ? 512 : 256;
 }
 
-template <typename T, int KQ, int CB, int NSEG, bool ACC = false>
+template <typename T, int KQ, int CB, int NSEG, bool ACC = false, bool PAIR = false>
 __global__ void __launch_bounds__((dg_max_threads<T, KQ, CB, NSEG>())) dg_kernel(KArgs a) {
     typedef typename Mma<T>::acc_t acc_t;
     typedef typename Mma<T>::vec_t vec_t;
@@ -335,7 +344,65 @@ __global__ void __launch_bounds__((dg_max_threads<T, KQ, CB, NSEG>())) dg_kernel
         }
 
         const int nel_w = (int)min<int64_t>(16 * CB, a.nelem - e0);  // valid elements of the wave
-        for (int pp = 0; pp < np; ++pp) {
+        int pp_first = 0;
+        if constexpr (PAIR) {
+            static_assert(V == 4 && NSEG == 1 && !ACC, "paired stores: FP32 forward only");
+            // panel pairs (pp, pp+1) start at even panels of a group whose
+            // first panel is even, and slabs hold an even number of panels,
+            // so a pair never straddles two output slabs
+            for (; pp_first + 1 < np; pp_first += 2) {
+                const int panel = p_lo + pp_first;
+                const int slab_o = panel / a.mblk;
+                const int i0 = (panel % a.mblk) * 16;
+                acc_t accA[CB], accB[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    accA[cb] = acc_t(T(0));
+                    accB[cb] = acc_t(T(0));
+                }
+                const T* arowA = dl + (pp_first * 16 + c) * LD + g * KQ;
+                const T* arowB = arowA + 16 * LD;
+#pragma unroll
+                for (int t = 0; t < KQ; t += V) {
+                    const vec_t avA = *reinterpret_cast<const vec_t*>(arowA + t);
+                    const vec_t avB = *reinterpret_cast<const vec_t*>(arowB + t);
+#pragma unroll
+                    for (int q = 0; q < V; ++q)
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) {
+                            accA[cb] = Mma<T>::step(avA[q], b[0][cb][t + q], accA[cb]);
+                            accB[cb] = Mma<T>::step(avB[q], b[0][cb][t + q], accB[cb]);
+                        }
+                }
+                // lanes c < 8 keep panel A and take lane c+8's; lanes c >= 8
+                // keep panel B and take lane c-8's: store 1 holds elements
+                // c&7 (nodes i0 .. i0+31), store 2 elements 8 + (c&7)
+                const bool lo = c < 8;
+                const int i = i0 + (lo ? 0 : 16) + 4 * g;
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    f32x4 x1, x2;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float send = lo ? accB[cb][r] : accA[cb][r];
+                        const float got = __builtin_bit_cast(
+                            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, send),
+                                                               0x128 /* row_ror:8 */, 0xF, 0xF, false));
+                        x1[r] = lo ? accA[cb][r] : got;
+                        x2[r] = lo ? got : accB[cb][r];
+                    }
+                    const int64_t e1 = e0 + cb * 16 + (c & 7);
+                    const int64_t e2 = e1 + 8;
+                    if (i < nunit) {
+                        if (e1 < a.nelem)
+                            *reinterpret_cast<f32x4*>(out + ((int64_t)slab_o * a.nelem + e1) * nunit + i) = x1;
+                        if (e2 < a.nelem)
+                            *reinterpret_cast<f32x4*>(out + ((int64_t)slab_o * a.nelem + e2) * nunit + i) = x2;
+                    }
+                }
+            }
+        }
+        for (int pp = pp_first; pp < np; ++pp) {
             const int panel = p_lo + pp;
             const int slab_o = panel / a.mblk;
             const int i0 = (panel % a.mblk) * 16;
@@ -454,11 +521,18 @@ constexpr bool fits_registers() {
     return CB * NSEG * KQ * sizeof(T) <= (NSEG == 1 ? 1024u : 768u);
 }
 
+// pair: the paired-store variant (FP32 single-segment forward only; null
+// otherwise)
 template <typename T, int CB, int NSEG>
-kern_fn pick_kernel(int kq) {
-#define X(k)                                                            \
-    if constexpr (fits_registers<T, CB, NSEG, k>()) {                   \
-        if (kq == k) return dg_kernel<T, k, CB, NSEG>;                  \
+kern_fn pick_kernel(int kq, bool pair = false) {
+#define X(k)                                                                    \
+    if constexpr (fits_registers<T, CB, NSEG, k>()) {                           \
+        if (kq == k) {                                                          \
+            if (!pair) return dg_kernel<T, k, CB, NSEG>;                        \
+            if constexpr (sizeof(T) == 4 && NSEG == 1)                          \
+                return dg_kernel<T, k, CB, NSEG, false, true>;                  \
+            return nullptr;                                                     \
+        }                                                                       \
     }
     DG_KQ_LIST(X)
 #undef X
@@ -522,11 +596,18 @@ inline dg_status make_plan(size_t tsize, int nseg, int out_slabs, int64_t nelem,
     return DG_OK;
 }
 
-// Launch one contraction with the kernel fn; tile->groups_per_cu == 0 means
-// "occupancy maximum" (queried for fn).
+// The paired-store variant applies to FP32 rows of a multiple of 32 nodes
+// written as 16-byte vectors, with an even number of panels per group.
+inline bool pair_eligible(size_t tsize, int nunit, bool vec_out, const Plan& P) {
+    return tsize == 4 && vec_out && nunit % 32 == 0 && P.mblk % 2 == 0 && P.ppg % 2 == 0;
+}
+
+// Launch one contraction with the kernel fn (or fn_pair where the paired
+// stores apply); tile->groups_per_cu == 0 means "occupancy maximum" (queried
+// for the kernel launched).
 template <typename T, int NSEG>
 dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, int waves, kern_fn fn,
-                 hipStream_t s) {
+                 hipStream_t s, kern_fn fn_pair = nullptr) {
     if (!fn) return fail(DG_EUNSUPPORTED, "no DG kernel instance for this shape");
     DeviceInfo dev;
     dg_status st = current_device(&dev);
@@ -545,6 +626,8 @@ dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, in
     st = make_plan(sizeof(T), NSEG, out_slabs, a.nelem, a.nunit, kq, cb, waves,
                    tile ? tile->d_panels : 0, 1, dev.num_cu, src_vec_ok, &P);
     if (st != DG_OK) return st;
+    const bool vec_out = (a.nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(a.out) % 16 == 0);
+    if (fn_pair && pair_eligible(sizeof(T), a.nunit, vec_out, P)) fn = fn_pair;
     DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
     int per_cu = (tile && tile->groups_per_cu > 0) ? tile->groups_per_cu : 0;
@@ -565,7 +648,7 @@ dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, in
     a.vec_in = P.vec_in;
     a.src_aligned = reinterpret_cast<uintptr_t>(a.src) % 16 == 0;
     a.use_slab = P.use_slab;
-    a.vec_out = (a.nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(a.out) % 16 == 0);
+    a.vec_out = vec_out;
     a.stage_out = a.use_slab && !a.vec_out;
     a.nt_store = (tile && (tile->flags & DG_TILE_NT_STORE)) ? 1 : 0;
     hipLaunchKernelGGL(fn, dim3((unsigned)P.grid), dim3(64 * waves), P.smem, s, a);

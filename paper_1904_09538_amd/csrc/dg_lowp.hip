@@ -160,6 +160,111 @@ __device__ inline void lp_load_b(const typename LP<FMT>::G* __restrict__ u, int6
     }
 }
 
+// Operator panels p_lo .. p_lo+np-1 against the element fragments b of one
+// tile; results scaled and stored.  PAIR: two consecutive panels of one
+// output slab at a time (np pairs never straddle a slab: panels per slab and
+// per group are even), lanes c and c^8 trading halves (a DPP rotation by 8
+// within each 16-lane row) so that one store covers elements 0..7 and the
+// other 8..15, each element's 32 nodes i0 .. i0+31 in one 128-byte run.
+template <int FMT, int KS, int CB, bool PAIR>
+__device__ inline void lp_panels(const typename LP<FMT>::F (&b)[CB][KS], const float (&esc)[CB],
+                                 int64_t e0, int c, int g, int p_lo, int np,
+                                 const typename LP<FMT>::L* dl, const float* s_inv_sD,
+                                 const LpArgs& a) {
+    typedef typename LP<FMT>::L E;
+    typedef typename LP<FMT>::F F;
+    constexpr int KQ = 8 * KS;
+    constexpr int KP = 4 * KQ;
+    constexpr int LDE = KP + 16 / (int)sizeof(E);
+    const int nunit = a.nunit;
+    int pp = 0;
+    if constexpr (PAIR) {
+        for (; pp + 1 < np; pp += 2) {
+            const int panel = p_lo + pp;
+            const int m = panel / a.mblk;
+            const int i0 = (panel % a.mblk) * 16;
+            f32x4 accA[CB], accB[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                accA[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+                accB[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+            const E* arowA = dl + (pp * 16 + c) * LDE + g * KQ;
+            const E* arowB = arowA + 16 * LDE;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const F avA = *reinterpret_cast<const F*>(arowA + 8 * s);
+                const F avB = *reinterpret_cast<const F*>(arowB + 8 * s);
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    accA[cb] = LP<FMT>::mma(avA, b[cb][s], accA[cb]);
+                    accB[cb] = LP<FMT>::mma(avB, b[cb][s], accB[cb]);
+                }
+            }
+            const float msc = s_inv_sD[m];
+            const bool lo = c < 8;
+            const int i = i0 + (lo ? 0 : 16) + 4 * g;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                // scale with the lane's own element before the exchange
+                const float sc = msc * esc[cb];
+                const f32x4 vA = accA[cb] * sc;
+                const f32x4 vB = accB[cb] * sc;
+                f32x4 x1, x2;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float send = lo ? vB[r] : vA[r];
+                    const float got = __builtin_bit_cast(
+                        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, send),
+                                                           0x128 /* row_ror:8 */, 0xF, 0xF, false));
+                    x1[r] = lo ? vA[r] : got;
+                    x2[r] = lo ? got : vB[r];
+                }
+                const int64_t e1 = e0 + cb * 16 + (c & 7);
+                const int64_t e2 = e1 + 8;
+                if (i < nunit) {
+                    if (e1 < a.nelem)
+                        *reinterpret_cast<f32x4*>(a.out + ((int64_t)m * a.nelem + e1) * nunit + i) = x1;
+                    if (e2 < a.nelem)
+                        *reinterpret_cast<f32x4*>(a.out + ((int64_t)m * a.nelem + e2) * nunit + i) = x2;
+                }
+            }
+        }
+    }
+    for (; pp < np; ++pp) {
+        const int panel = p_lo + pp;
+        const int m = panel / a.mblk;
+        const int i0 = (panel % a.mblk) * 16;
+        f32x4 acc[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const E* arow = dl + (pp * 16 + c) * LDE + g * KQ;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const F av = *reinterpret_cast<const F*>(arow + 8 * s);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[cb] = LP<FMT>::mma(av, b[cb][s], acc[cb]);
+        }
+        const float msc = s_inv_sD[m];
+        const int i = i0 + 4 * g;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int64_t e = e0 + cb * 16 + c;
+            if (e >= a.nelem) continue;
+            const float sc = msc * esc[cb];  // product of powers of two: exact
+            const f32x4 v = acc[cb] * sc;
+            float* dst = a.out + ((int64_t)m * a.nelem + e) * nunit + i;
+            if (a.vec_out) {
+                if (i < nunit) *reinterpret_cast<f32x4*>(dst) = v;
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (i + r < nunit) dst[r] = v[r];
+            }
+        }
+    }
+}
+
 // up to 8 waves per work-group while the element operand (KS*CB 16-byte
 // fragments) takes at most 56 registers
 template <int KS, int CB>
@@ -167,7 +272,7 @@ constexpr int lp_max_threads() {
     return KS * CB <= 14 ? 512 : 256;
 }
 
-template <int FMT, int KS, int CB>
+template <int FMT, int KS, int CB, bool PAIR>
 __global__ void __launch_bounds__((lp_max_threads<KS, CB>())) dg_lowp_kernel(LpArgs a) {
     typedef typename LP<FMT>::L E;
     typedef typename LP<FMT>::G GE;
@@ -215,48 +320,17 @@ __global__ void __launch_bounds__((lp_max_threads<KS, CB>())) dg_lowp_kernel(LpA
             lp_load_b<FMT, KS>(u, e, g, a, b[cb]);
             esc[cb] = (a.inv_su && e < a.nelem) ? a.inv_su[e] : 1.0f;
         }
-        for (int pp = 0; pp < np; ++pp) {
-            const int panel = p_lo + pp;
-            const int m = panel / a.mblk;
-            const int i0 = (panel % a.mblk) * 16;
-            f32x4 acc[CB];
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-            const E* arow = dl + (pp * 16 + c) * LDE + g * KQ;
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const F av = *reinterpret_cast<const F*>(arow + 8 * s);
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) acc[cb] = LP<FMT>::mma(av, b[cb][s], acc[cb]);
-            }
-            const float msc = s_inv_sD[m];
-            const int i = i0 + 4 * g;
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                const int64_t e = e0 + cb * 16 + c;
-                if (e >= a.nelem) continue;
-                const float sc = msc * esc[cb];  // product of powers of two: exact
-                const f32x4 v = acc[cb] * sc;
-                float* dst = a.out + ((int64_t)m * a.nelem + e) * nunit + i;
-                if (a.vec_out) {
-                    if (i < nunit) *reinterpret_cast<f32x4*>(dst) = v;
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (i + r < nunit) dst[r] = v[r];
-                }
-            }
-        }
+        lp_panels<FMT, KS, CB, PAIR>(b, esc, e0, c, g, p_lo, np, dl, s_inv_sD, a);
     }
 }
 
 typedef void (*lp_fn)(LpArgs);
 
 template <int FMT, int CB>
-lp_fn pick_lp(int ks) {
+lp_fn pick_lp(int ks, bool pair) {
     switch (ks) {
 #define X(K) \
-    case K: return dg_lowp_kernel<FMT, K, CB>;
+    case K: return pair ? dg_lowp_kernel<FMT, K, CB, true> : dg_lowp_kernel<FMT, K, CB, false>;
         X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 #undef X
     }
@@ -266,10 +340,10 @@ lp_fn pick_lp(int ks) {
 constexpr size_t kLpBudget = 80 * 1024;
 constexpr size_t kLpMax = 160 * 1024;
 
-lp_fn lp_kernel(int fmt, int ks, int cb) {
-    if (fmt == 0) return cb == 4 ? pick_lp<0, 4>(ks) : cb == 2 ? pick_lp<0, 2>(ks) : pick_lp<0, 1>(ks);
-    if (fmt == 1) return cb == 4 ? pick_lp<1, 4>(ks) : cb == 2 ? pick_lp<1, 2>(ks) : pick_lp<1, 1>(ks);
-    return cb == 4 ? pick_lp<2, 4>(ks) : cb == 2 ? pick_lp<2, 2>(ks) : pick_lp<2, 1>(ks);
+lp_fn lp_kernel(int fmt, int ks, int cb, bool pair) {
+    if (fmt == 0) return cb == 4 ? pick_lp<0, 4>(ks, pair) : cb == 2 ? pick_lp<0, 2>(ks, pair) : pick_lp<0, 1>(ks, pair);
+    if (fmt == 1) return cb == 4 ? pick_lp<1, 4>(ks, pair) : cb == 2 ? pick_lp<1, 2>(ks, pair) : pick_lp<1, 1>(ks, pair);
+    return cb == 4 ? pick_lp<2, 4>(ks, pair) : cb == 2 ? pick_lp<2, 2>(ks, pair) : pick_lp<2, 1>(ks, pair);
 }
 
 }  // namespace
@@ -319,8 +393,14 @@ dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_til
     return DG_OK;
 }
 
-static dg_status lp_occupancy(const LpPlan& P, int* per_cu) {
-    lp_fn fn = lp_kernel(P.fmt, P.ks, P.cb);
+// Paired stores (lp_panels) for rows of a multiple of 32 nodes written as
+// 16-byte vectors, with an even number of panels per group.
+static bool lp_pair_ok(const LpPlan& P, int nunit, bool vec_out) {
+    return vec_out && nunit % 32 == 0 && P.mblk % 2 == 0 && P.ppg % 2 == 0;
+}
+
+static dg_status lp_occupancy(const LpPlan& P, bool pair, int* per_cu) {
+    lp_fn fn = lp_kernel(P.fmt, P.ks, P.cb, pair);
     if (!fn) return fail(DG_EUNSUPPORTED, "no low-precision DG kernel instance");
     hipFuncAttributes fa;
     DG_HIP_CHECK(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(fn)));
@@ -346,7 +426,8 @@ dg_status resolve_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nunit
     tile->d_panels = P.ppg;
     if (tile->groups_per_cu == 0) {
         int per_cu = 0;
-        st = lp_occupancy(P, &per_cu);
+        // the kernel a launch into 16-byte aligned output would take
+        st = lp_occupancy(P, lp_pair_ok(P, nunit, nunit % 4 == 0), &per_cu);
         if (st != DG_OK) return st;
         tile->groups_per_cu = per_cu;
     }
@@ -362,14 +443,16 @@ dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nun
     LpPlan P;
     st = make_lp_plan(lp_format(in_t, tile), nmat, nelem, nunit, tile, 1, dev.num_cu, &P);
     if (st != DG_OK) return st;
+    const bool vec_out = (nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    const bool pair = lp_pair_ok(P, nunit, vec_out);
     int per_cu = (tile && tile->groups_per_cu > 0) ? tile->groups_per_cu : 0;
     if (per_cu == 0) {
-        st = lp_occupancy(P, &per_cu);
+        st = lp_occupancy(P, pair, &per_cu);
         if (st != DG_OK) return st;
     }
     st = make_lp_plan(P.fmt, nmat, nelem, nunit, tile, per_cu, dev.num_cu, &P);
     if (st != DG_OK) return st;
-    lp_fn fn = lp_kernel(P.fmt, P.ks, P.cb);
+    lp_fn fn = lp_kernel(P.fmt, P.ks, P.cb, pair);
     if (!fn) return fail(DG_EUNSUPPORTED, "no low-precision DG kernel instance");
     DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
@@ -388,7 +471,7 @@ dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nun
     a.ngroups = P.ngroups;
     a.nstreams = (int)(8 * P.slots);
     a.vec_in = (nunit % 8 == 0) && (reinterpret_cast<uintptr_t>(u) % 16 == 0);  // 8 values / load
-    a.vec_out = (nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    a.vec_out = vec_out;
     hipLaunchKernelGGL(fn, dim3((unsigned)P.grid), dim3(64 * P.waves), P.smem, s, a);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;

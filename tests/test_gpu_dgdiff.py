@@ -104,6 +104,35 @@ def test_unaligned_rows_staged_stores(orc, ops, dtype, nunit, tile):
             pytest.skip("launch shape not available for this problem")
 
 
+@pytest.mark.parametrize("nunit", [32, 64, 96, 512])
+@pytest.mark.parametrize("tile", [None, dict(elems_per_wave=32), dict(elems_per_wave=64), dict(d_panels=2),
+                                  dict(d_panels=3), dict(d_panels=4, waves=3)])
+def test_paired_stores(orc, ops, nunit, tile):
+    """FP32 rows of a multiple of 32 nodes take the paired-store variant (two
+    panels per step, halves traded between lanes c and c^8), also with several
+    panel groups; odd groups (d_panels=3) fall back to single panels.  Ragged
+    element counts leave the second store of a pair partly or wholly empty."""
+    D = I.random_dmats(nunit)
+    for nelem in (1, 9, 23, 1001):
+        u = I.uniform_u(nelem, nunit)
+        try:
+            _check(orc, ops, D, u, torch.float32, tile=tile)
+        except ops.DGError:
+            pytest.skip("launch shape not available for this problem")
+
+
+@pytest.mark.parametrize("nunit", [64, 512])
+def test_paired_matches_single_panels_bitwise(ops, nunit):
+    """Pairing reorders stores only: an even panel group (paired) and an odd
+    one (single panels) give bit-identical results."""
+    D = _dev(I.random_dmats(nunit), torch.float32)
+    u = _dev(I.uniform_u(1001, nunit), torch.float32)
+    a = ops.dgdiff_apply(D, u, tile=dict(d_panels=4))
+    b = ops.dgdiff_apply(D, u, tile=dict(d_panels=3))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_integer_data_bit_exact(orc, ops, dtype):
     rng = np.random.default_rng(12)

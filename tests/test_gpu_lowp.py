@@ -136,6 +136,50 @@ def test_lowp_tiles(orc, ops, tile):
     assert normwise_rel(got.double().cpu().numpy(), ref.double().cpu().numpy()) <= 1e-6
 
 
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+@pytest.mark.parametrize("nunit,tile", [(32, None), (64, None), (64, dict(d_panels=2)), (64, dict(d_panels=3)),
+                                        (64, dict(elems_per_wave=64)), (512, dict(d_panels=8)),
+                                        (512, None)])
+def test_lowp_paired_stores(orc, ops, to, nunit, tile):
+    """Rows of a multiple of 32 nodes take the paired-store variant when the
+    panel groups are even (scales applied per element before the exchange);
+    ragged element counts; odd groups fall back to single panels."""
+    D = I.gll_dmats(3) if nunit == 64 else I.random_dmats(nunit)
+    D32 = D.astype(np.float32)
+    for nelem in (1, 9, 300):
+        u32 = I.uniform_u(nelem, nunit).astype(np.float32)
+        qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), to)
+        qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), to)
+        sc = dict(inv_sD=isD, inv_su=isu) if to == "e4m3" else {}
+        got = ops.dgdiff_apply(qD.view(3, nunit, nunit), qu, tile=tile, **sc)
+        torch.cuda.synchronize()
+        # the oracle on the oracle's own dequantised operands
+        qDo, isDo = orc.quantize(D32.reshape(3, -1), to, True)
+        quo, isuo = orc.quantize(u32, to, True)
+        if to == "bf16":
+            Dd = orc.bf16_decode_array(qDo).astype(np.float64).reshape(3, nunit, nunit)
+            ud = orc.bf16_decode_array(quo).astype(np.float64)
+        else:
+            Dd = (orc.e4m3_decode_array(qDo) * isDo[:, None]).reshape(3, nunit, nunit)
+            ud = orc.e4m3_decode_array(quo) * isuo[:, None]
+        ref = orc.dg_forward(Dd, ud)
+        err = _dot_scaled(orc, got.double().cpu().numpy(), ref, Dd, ud) / (nunit * 2.0 ** -23)
+        assert err <= 1.0, (nelem, err)
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+def test_lowp_paired_matches_single_panels_bitwise(ops, to):
+    D32 = I.gll_dmats(3).astype(np.float32)
+    u32 = I.uniform_u(1001, 64).astype(np.float32)
+    qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), to)
+    qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), to)
+    sc = dict(inv_sD=isD, inv_su=isu) if to == "e4m3" else {}
+    a = ops.dgdiff_apply(qD.view(3, 64, 64), qu, tile=dict(d_panels=4), **sc)
+    b = ops.dgdiff_apply(qD.view(3, 64, 64), qu, tile=dict(d_panels=3), **sc)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_fp8_requires_scales(ops):
     q = torch.zeros(3, 64, 64, dtype=torch.float8_e4m3fn, device="cuda:0")
     u = torch.zeros(10, 64, dtype=torch.float8_e4m3fn, device="cuda:0")
