@@ -346,7 +346,7 @@ def main():
     roof = roofline(alg_bytes, alg_flops, t, "f32")
     src_hash = kernel_source_hash()
     roof["traffic"] = load_traffic("dg_kernel_f32:dg_fp32_p3_2e21", src_hash)
-    roof["kernel"] = "dg_kernel<float,16,1,1>"
+    roof["kernel"] = "dg_kernel<float,16,1,1,false,true> (paired stores)"
     log(f"headline: {t * 1e3:.3f} ms/step, {E / t:.3e} elements/s")
     del D, u, out
     torch.cuda.empty_cache()
