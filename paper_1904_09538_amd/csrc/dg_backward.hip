@@ -3,10 +3,16 @@
 //     grad_u[e][j]    = sum_m sum_i D[m][i][j] * g[m][e][i]
 //     grad_D[m][i][j] = sum_e g[m][e][i] * u[e][j]
 //
-// grad_u runs on the forward's contraction kernel (dg_kernel.hpp) with the
-// operator transposed and the g slabs as contraction segments.  When the
-// nmat segments do not fit the register budget, each operator is applied in
-// its own launch and the later launches accumulate (stream-ordered).
+// grad_u, FP32 rows of more than 96 nodes: a GEMM
+//     grad_u^T[j][e] = sum_(m,i) D[m][i][j] g[m][e][i]
+// on 128 x 128 tiles (output nodes x elements) whose contraction over (m, i)
+// streams through LDS in chunks of 16 nodes of one operator, so the operator
+// is not held resident (at p = 4 its panels for all three slabs leave room
+// for a single work-group of 4 waves per CU).  Otherwise grad_u runs on the
+// forward's contraction kernel (dg_kernel.hpp) with the operator transposed
+// and the g slabs as contraction segments; when the nmat segments do not fit
+// the register budget, each operator is applied in its own launch and the
+// later launches accumulate (stream-ordered).
 //
 // grad_D is a GEMM C[(m,i)][j] = sum_e G_m^T[i][e] U[e][j] with a very long
 // contraction (the element count).  It is split: work-group (tile, split)
@@ -258,9 +264,158 @@ dg_status launch_grad_d(int nmat, int64_t nelem, int nunit, const void* u, const
 
 // ------------------------------------------------------------------ grad_u
 
+constexpr int UT = 128;      // tile: output nodes j x elements
+constexpr int UK = 16;       // contraction nodes per chunk (one operator)
+constexpr int UA = UT + 4;   // LDS row stride of the operator chunk
+constexpr int UB = UK + 4;   // LDS row stride of the element chunk
+constexpr int kGradUGemmMin = 97;  // FP32 nunit from which grad_u runs as a GEMM
+
+struct GuArgs {
+    const float* D;   // [nmat][n][n]
+    const float* g;   // [nmat][nelem][n]
+    float* gu;        // [nelem][n]
+    int64_t nelem;
+    int64_t ntile_e;  // ceil(nelem / UT)
+    int nmat;
+    int n;
+    int ntile_j;      // ceil(n / UT)
+};
+
+// Work-group: 4 waves, 2 x 2 of 64 x 64 (4 x 4 MFMA tiles of 16 x 16).  The
+// chunk's operator rows D[m][i0 .. i0+15][j0 ..] are kept as they lie in
+// memory (row = contraction node, column = output node: lane group g reads
+// its four nodes 4g .. 4g+3 with one LDS load each); the element rows
+// g[m][e][i0 .. i0+15] are kept per element (one 16-byte LDS load per lane
+// per tile).  Chunks are double-buffered: the next is fetched into registers
+// while the current one is multiplied.  Blocks that share an element tile sit
+// on one XCD (block b on XCD b % 8), so the other output-node tiles re-read
+// it from that XCD's L2.
+__global__ void __launch_bounds__(256) grad_u_gemm_kernel(GuArgs a) {
+    __shared__ __attribute__((aligned(16))) float As[2][UK * UA];
+    __shared__ __attribute__((aligned(16))) float Bs[2][UT * UB];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int c = lane & 15;
+    const int g = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int xcd = blockIdx.x & 7;
+    const int kb = blockIdx.x >> 3;
+    const int64_t te = (int64_t)(kb / a.ntile_j) * 8 + xcd;
+    if (te >= a.ntile_e) return;  // whole block past the end: no barrier reached
+    const int j0 = (kb % a.ntile_j) * UT;
+    const int64_t e0 = te * UT;
+    const int n = a.n;
+    const int kpm = (n + UK - 1) / UK;  // chunks per operator
+    const int nchunk = a.nmat * kpm;
+
+    // staging: operator chunk row ka = t/32 (+8), output nodes ja .. ja+3;
+    // element eb = t/4 (+64), contraction nodes kq .. kq+3
+    const int ka = t >> 5, ja = (t & 31) * 4;
+    const int eb = t >> 2, kq = (t & 3) * 4;
+    const bool e_ok[2] = {e0 + eb < a.nelem, e0 + eb + 64 < a.nelem};
+    float ra[2][4], rb[2][4];
+    auto load = [&](int kc) {
+        const int m = kc / kpm;
+        const int i0 = (kc % kpm) * UK;
+        const float* Dm = a.D + (int64_t)m * n * n;
+        const float* gm = a.g + (int64_t)m * a.nelem * n;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = i0 + ka + 8 * h;
+            const int j = j0 + ja;
+            gd_load4<float>(Dm + (int64_t)(i < n ? i : 0) * n + j, i < n, n - j, ra[h]);
+            const int64_t e = e0 + eb + 64 * h;
+            gd_load4<float>(gm + (e_ok[h] ? e : 0) * n + i0 + kq, e_ok[h], n - (i0 + kq), rb[h]);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            __builtin_memcpy(&As[buf][(ka + 8 * h) * UA + ja], ra[h], 16);
+            __builtin_memcpy(&Bs[buf][(eb + 64 * h) * UB + kq], rb[h], 16);
+        }
+    };
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kc = 0; kc < nchunk; ++kc) {
+        const int buf = kc & 1;
+        const bool more = kc + 1 < nchunk;
+        if (more) load(kc + 1);
+        float av[4][4];  // [tile][node 4g + s]
+        f32x4 bv[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const float* Ar = &As[buf][(4 * g + s4) * UA + wm * 64 + c];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) av[p][s4] = Ar[p * 16];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            bv[q] = *reinterpret_cast<const f32x4*>(&Bs[buf][(wn * 64 + q * 16 + c) * UB + 4 * g]);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[p][s4], bv[q][s4], acc[p][q], 0, 0, 0);
+        if (more) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // lane holds output nodes j .. j+3 (j = j0 + wm*64 + p*16 + 4g) of
+    // element e0 + wn*64 + q*16 + c
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t e = e0 + wn * 64 + q * 16 + c;
+        if (e >= a.nelem) continue;
+        float* row = a.gu + e * n;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int j = j0 + wm * 64 + p * 16 + 4 * g;
+            if (j + 4 <= n) {
+                __builtin_memcpy(row + j, &acc[p][q], 16);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+                    if (j + r < n) row[j + r] = acc[p][q][r];
+            }
+        }
+    }
+}
+
+dg_status launch_grad_u_gemm(int nmat, int64_t nelem, int nunit, const void* D, const void* g,
+                             void* grad_u, hipStream_t s) {
+    GuArgs a;
+    a.D = static_cast<const float*>(D);
+    a.g = static_cast<const float*>(g);
+    a.gu = static_cast<float*>(grad_u);
+    a.nelem = nelem;
+    a.ntile_e = ceil_div(nelem, (int64_t)UT);
+    a.nmat = nmat;
+    a.n = nunit;
+    a.ntile_j = (int)ceil_div(nunit, UT);
+    const int64_t blocks = ceil_div(a.ntile_e, (int64_t)8) * 8 * a.ntile_j;
+    if (blocks > INT32_MAX) return fail(DG_EUNSUPPORTED, "grad_u: too many elements for one launch");
+    hipLaunchKernelGGL(grad_u_gemm_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    DG_HIP_CHECK(hipGetLastError());
+    return DG_OK;
+}
+
 template <typename T>
 dg_status launch_grad_u(int nmat, int64_t nelem, int nunit, const void* D, const void* g,
                         void* grad_u, const dg_tile* tile, hipStream_t s) {
+    if (sizeof(T) == 4 && nunit >= kGradUGemmMin)
+        return launch_grad_u_gemm(nmat, nelem, nunit, D, g, grad_u, s);
     const int kq = kq_for(nunit);
     if (kq < 0) return fail(DG_EUNSUPPORTED, "nunit too large for the DG kernel");
     const int waves = (tile && tile->waves) ? tile->waves : 4;

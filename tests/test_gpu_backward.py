@@ -45,6 +45,22 @@ def test_backward_vs_oracle(orc, ops, dtype, nunit):
         assert normwise_rel(gD.double().cpu().numpy(), rD) <= tol
 
 
+@pytest.mark.parametrize("nunit", [97, 128, 129, 256])
+def test_grad_u_gemm_edges(orc, ops, nunit):
+    """FP32 grad_u from 97 nodes on runs as a 128 x 128-tile GEMM: node counts
+    at and across the tile edge, element counts around the 128-element tile
+    and around the grouping of tiles by XCD (8 tiles)."""
+    for nmat, nelem in ((3, 127), (3, 129), (1, 128 * 9 + 5), (2, 1)):
+        D = _as(I.random_dmats(nunit, nmat=nmat), torch.float32)
+        u = _as(I.uniform_u(nelem, nunit), torch.float32)
+        g = _as(I.normal_g(nmat, nelem, nunit), torch.float32)
+        gu, _ = ops.dgdiff_backward(_t(D, torch.float32), _t(u, torch.float32), _t(g, torch.float32),
+                                    want_D=False)
+        torch.cuda.synchronize()
+        ru, _ = orc.dg_adjoint(D, u, g, want_D=False)
+        assert normwise_rel(gu.double().cpu().numpy(), ru) <= 1e-5, (nmat, nelem)
+
+
 def test_backward_partial_outputs_and_empty(orc, ops):
     D = I.random_dmats(64)
     u = I.uniform_u(100, 64)
