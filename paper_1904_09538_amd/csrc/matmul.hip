@@ -8,12 +8,16 @@
 //
 // Tiling.  A work-group of 4 waves owns a 128x128 block of c (2x2 waves of
 // 64x64 = 4x4 MFMA blocks each).  K advances in chunks of 16: the a chunk is
-// staged in LDS as [row][k] and the b chunk transposed as [col][k], so both
-// operands are read with 16-byte LDS loads (lane group g takes k = 4g..4g+3
-// of the chunk, k-step s = 0..3 — any order of the contraction is exact up to
-// rounding).  The next chunk is loaded from global memory into registers while
-// the current one is multiplied; LDS is double-buffered with one barrier per
-// chunk.
+// staged in LDS as [row][k] (read with one 16-byte load per tile) and the b
+// chunk as it lies in memory, [k][col] (read with one 4-byte load per tile and
+// k-step; consecutive lanes take consecutive columns and the row stride puts
+// lane groups g and g+1 sixteen banks apart).  Lane group g takes k = 4g..4g+3
+// of the chunk, k-step s = 0..3 (any order of the contraction is exact up to
+// rounding).  Both chunks are written with 16-byte LDS stores; transposing b
+// on the way in (16 columns of one k landing on one bank) cost a 16-way bank
+// conflict on every store.  The next chunk is loaded from global memory into
+// registers while the current one is multiplied; LDS is double-buffered with
+// one barrier per chunk.
 #include "common.hpp"
 
 namespace dg {
@@ -23,7 +27,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128;    // block rows / cols
 constexpr int BK = 16;     // k chunk
-constexpr int LDK = BK + 4;  // LDS row stride (floats): 16-byte pad against bank conflicts
+constexpr int LDK = BK + 4;  // a chunk row stride (floats): 16-byte pad against bank conflicts
+constexpr int LDB = BM + 4;  // b chunk row stride (floats)
 
 template <bool VEC>
 __device__ inline void load_chunk(const float* __restrict__ a, const float* __restrict__ b,
@@ -54,24 +59,22 @@ __device__ inline void load_chunk(const float* __restrict__ a, const float* __re
     }
 }
 
-__device__ inline void store_chunk(float* As, float* Bt, int t, const f32x4 (&ra)[2],
+__device__ inline void store_chunk(float* As, float* Bs, int t, const f32x4 (&ra)[2],
                                    const f32x4 (&rb)[2]) {
     float* arow = As + (t >> 1) * LDK + 8 * (t & 1);
     reinterpret_cast<f32x4*>(arow)[0] = ra[0];
     reinterpret_cast<f32x4*>(arow)[1] = ra[1];
-    const int k = t >> 4;
-    const int c0 = 8 * (t & 15);
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Bt[(c0 + 4 * h + q) * LDK + k] = rb[h][q];
+    float* brow = Bs + (t >> 4) * LDB + 8 * (t & 15);
+    reinterpret_cast<f32x4*>(brow)[0] = rb[0];
+    reinterpret_cast<f32x4*>(brow)[1] = rb[1];
 }
 
 template <bool VEC>
 __global__ void __launch_bounds__(256) matmul_kernel(const float* __restrict__ a,
                                                      const float* __restrict__ b,
                                                      float* __restrict__ c, int64_t n) {
-    __shared__ __attribute__((aligned(16))) float lds[2][2][BM * LDK];  // [buf][a|bt]
+    __shared__ __attribute__((aligned(16))) float As_[2][BM * LDK];  // [buf][row][k]
+    __shared__ __attribute__((aligned(16))) float Bs_[2][BK * LDB];  // [buf][k][col]
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -91,21 +94,23 @@ __global__ void __launch_bounds__(256) matmul_kernel(const float* __restrict__ a
 
     f32x4 ra[2], rb[2];
     load_chunk<VEC>(a, b, n, row0, col0, 0, t, ra, rb);
-    store_chunk(lds[0][0], lds[0][1], t, ra, rb);
+    store_chunk(As_[0], Bs_[0], t, ra, rb);
     __syncthreads();
 
     for (int64_t kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
         if (kc + 1 < nk) load_chunk<VEC>(a, b, n, row0, col0, (kc + 1) * BK, t, ra, rb);
-        const float* As = lds[buf][0];
-        const float* Bt = lds[buf][1];
-        f32x4 av[4], bv[4];
+        const float* As = As_[buf];
+        const float* Bs = Bs_[buf];
+        f32x4 av[4];
+        float bv[4][4];  // [col block][k-step]
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             av[i] = *reinterpret_cast<const f32x4*>(As + (wr * 64 + i * 16 + cl) * LDK + 4 * g);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            bv[j] = *reinterpret_cast<const f32x4*>(Bt + (wc * 64 + j * 16 + cl) * LDK + 4 * g);
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j][s] = Bs[(4 * g + s) * LDB + wc * 64 + j * 16 + cl];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -114,7 +119,7 @@ __global__ void __launch_bounds__(256) matmul_kernel(const float* __restrict__ a
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j][s], av[i][s], acc[i][j],
                                                                      0, 0, 0);
-        if (kc + 1 < nk) store_chunk(lds[buf ^ 1][0], lds[buf ^ 1][1], t, ra, rb);
+        if (kc + 1 < nk) store_chunk(As_[buf ^ 1], Bs_[buf ^ 1], t, ra, rb);
         __syncthreads();
     }
 
