@@ -19,8 +19,8 @@ of the kept samples.
 Measurement set: the DG forward in FP32 for hexahedral orders p = 1..7
 (nunit 8 .. 512) at 2^16..2^21 elements (2^15..2^19 for p = 6, 7) with five
 launch shapes each,
-the five-point stencil at nine n in 1024..16384, square matmul at nine n in
-512..8192, and empty kernels with 16..65536 work-groups (launch and
+the five-point stencil at fourteen n in 1024..16384, square matmul at twelve
+n in 512..8192, and empty kernels with 16..65536 work-groups (launch and
 work-group costs).  The fitted models use the linear form for the stencil and
 the overlap form for DG and matmul, as the paper does.
 20% of each family's variants are held out (seeded) and scored by MAPE and
@@ -58,7 +58,9 @@ MODELS = {
     "dg": ["launch", "workgroups", "wave_tiles", "serial_steps", "lat_steps", "gld_dg_u", "gld_dg_u_unal",
            "gld_dg_u_l2",
            "gld_dg_d", "gst_dg_out", "gst_dg_out_unal", "lds_bytes", "mfma_f32"],
-    "stencil": ["launch", "workgroups", "gld_st_u", "gst_st_res", "lds_bytes", "valu_f32"],
+    # serial_steps (rows of one strip): small grids are bound by the strip's
+    # chain of loads rather than by bandwidth
+    "stencil": ["launch", "workgroups", "serial_steps", "gld_st_u", "gst_st_res", "lds_bytes", "valu_f32"],
     "matmul": ["launch", "workgroups", "serial_steps", "barrier_x_wg", "gld_mm_ab", "gst_mm_c",
                "lds_bytes", "mfma_f32"],
 }
@@ -94,13 +96,14 @@ def dg_variants(quick=False):
 
 
 def stencil_variants(quick=False):
-    ns = ([1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384] if not quick
-          else [1024, 4096, 16384])
+    ns = ([1024, 1280, 1536, 2048, 2560, 3072, 4096, 5120, 6144, 8192, 10240, 12288, 14336, 16384]
+          if not quick else [1024, 4096, 16384])
     return [{"family": "stencil", "n": n} for n in ns]
 
 
 def matmul_variants(quick=False):
-    ns = [512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192] if not quick else [512, 2048, 8192]
+    ns = ([512, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096, 5120, 6144, 8192] if not quick
+          else [512, 2048, 8192])
     return [{"family": "matmul", "n": n} for n in ns]
 
 
