@@ -259,12 +259,23 @@ __device__ void gemm_tile(const BArgs& a, const BOrder& o, int64_t eb, int rb, f
         const int64_t eoff = a.off[a.perm[o.ids + kpos]];
 #pragma unroll
         for (int tm = 0; tm < 4; ++tm) {
+            const int row = r0 + wm * 64 + tm * 16 + 4 * g;
+            if (row >= R) continue;
+            const int m = row / n;
+            const int i = row - m * n;
+            if (i + 4 <= n) {
+                // four nodes of one operator slab: one 16-byte store (the
+                // stacked rows past R are zero padding: i + 4 <= n keeps them out)
+                store4(a.out + (int64_t)m * a.total + eoff + i, acc[tm][tn], 4);
+            } else {
+                // the four rows cross into the next slab (or past R)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = r0 + wm * 64 + tm * 16 + 4 * g + r;
-                if (row >= R) continue;
-                const int m = row / n;
-                a.out[(int64_t)m * a.total + eoff + (row - m * n)] = acc[tm][tn][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = row + r;
+                    if (rr >= R) break;
+                    const int mr = rr / n;
+                    a.out[(int64_t)mr * a.total + eoff + (rr - mr * n)] = acc[tm][tn][r];
+                }
             }
         }
     }
