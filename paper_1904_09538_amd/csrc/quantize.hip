@@ -120,6 +120,26 @@ __global__ void __launch_bounds__(256) quantize_rows_kernel(int to_fp8, int64_t 
 // first is reduced and encoded.
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// Four E4M3FN codes: the hardware FP32-to-FP8 conversion (round to nearest
+// even, subnormals included) for |y| < 448; the format's saturation (|y| >=
+// 448, infinities included) and the NaN code are set here rather than taken
+// from the instruction.  Bit-equal to the encoder by bit fields above (tests:
+// random FP32 bit patterns, special values).
+__device__ inline void e4m3_rne4(f4v y, uint8_t (&b)[4]) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], w, true);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        uint8_t code = (uint8_t)((uint32_t)w >> (8 * t));
+        if (!(fabsf(y[t]) < 448.0f)) {
+            const uint8_t sign = (uint8_t)((f32_bits(y[t]) >> 24) & 0x80u);
+            code = sign | (y[t] != y[t] ? 0x7F : 0x7E);
+        }
+        b[t] = code;
+    }
+}
+
+
 __device__ inline f4v load4_any(const float* p, int avail) {
     f4v v = {0.f, 0.f, 0.f, 0.f};
     if (avail >= 4) {
@@ -172,8 +192,7 @@ __device__ inline void quantize_short_row(int to_fp8, int64_t r, int64_t cols, c
         const int64_t avail = cols - c;
         if (avail <= 0) continue;
         uint8_t b[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) b[t] = e4m3_rne(v[k][t] * sc);
+        e4m3_rne4(v[k] * sc, b);
         if (avail >= 4) {
             __builtin_memcpy(qr + c, b, 4);
         } else {
@@ -224,8 +243,9 @@ dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, 
     }
     const int fp8 = to == DG_FP8E4M3 ? 1 : 0;
     if (cols <= 1024) {
-        // four rows per wave and step; 16384 waves fill the GPU several times
-        const int64_t waves = std::min<int64_t>(ceil_div(rows, 4), 16384);
+        // four rows per wave and step; measured at 2^20 rows of 216: BF16 is
+        // fastest with one step per wave, FP8 with four (65536 waves)
+        const int64_t waves = std::min<int64_t>(ceil_div(rows, 4), fp8 ? 65536 : 262144);
         const int64_t blocks = ceil_div(waves, 4);
         if (cols <= 256)
             hipLaunchKernelGGL(quantize_short_rows_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, fp8,
