@@ -85,6 +85,12 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
     const int vec_out = n % 4 == 0;
     /* unaligned rows that come through the wave slab leave through it too */
     const int stage_out = !lowp && use_slab && !vec_out;
+    /* FP32 rows of a multiple of 32 nodes in even panel groups are stored in
+       panel pairs; with small fragments (KQ * cb <= 32) their element loads are
+       issued a tile ahead, every lane of a wave-tile loading all its vectors
+       (rows past the end read the last element) */
+    const int piped = !lowp && sz == 4 && vec_in && vec_out && n % 32 == 0 && mblk % 2 == 0 &&
+                      ppg % 2 == 0 && KQ * cb <= 32;
 
     c[F_LAUNCH] += 1;
     c[F_WG] += G;
@@ -128,6 +134,10 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                                 }
                             }
                         }
+                } else if (piped) {
+                    for (int q = 0; q < cb; ++q)
+                        for (int lane = 0; lane < 64; ++lane)
+                            for (int s = 0; s < KQ; s += V) c[tag] += 16;
                 } else if (vec_in) {
                     for (int q = 0; q < cb; ++q)
                         for (int lane = 0; lane < 64; ++lane) {

@@ -23,7 +23,8 @@ dg_status launch_fwd(int nmat, int64_t nelem, int nunit, const void* D, const vo
     int cb;
     dg_status st = forward_cb(sizeof(T), kq, rows_aligned, tile ? tile->elems_per_wave : 0, &cb);
     if (st != DG_OK) return st;
-    const int waves = (tile && tile->waves) ? tile->waves : forward_waves(sizeof(T), kq, cb, rows_aligned);
+    const int waves =
+        (tile && tile->waves) ? tile->waves : forward_waves(sizeof(T), nunit, kq, cb, rows_aligned);
     if (waves < 1 || waves > 8) return fail(DG_EINVAL, "tile.waves must be in 1..8");
     KArgs a = {};
     a.D = D;
@@ -55,7 +56,7 @@ dg_status resolve_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_
     int cb;
     dg_status st = forward_cb(ts, kq, nunit % (int)(16 / ts) == 0, tile->elems_per_wave, &cb);
     if (st != DG_OK) return st;
-    if (tile->waves == 0) tile->waves = forward_waves(ts, kq, cb, nunit % (int)(16 / ts) == 0);
+    if (tile->waves == 0) tile->waves = forward_waves(ts, nunit, kq, cb, nunit % (int)(16 / ts) == 0);
     tile->elems_per_wave = 16 * cb;
     DeviceInfo dev;
     st = current_device(&dev);

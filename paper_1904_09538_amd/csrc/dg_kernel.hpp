@@ -248,6 +248,197 @@ __device__ inline void write_staged(const T* st, T* __restrict__ dst, int nel, i
     }
 }
 
+// Panel pairs of one tile (see "Paired stores"): returns the number of panels
+// done (np rounded down to even).  b: the lane's element fragments.
+template <int KQ, int CB>
+__device__ inline int paired_panels(const float (&b)[CB][KQ], int64_t e0, int p_lo, int np,
+                                    const float* dl, float* __restrict__ out, const KArgs& a, int c,
+                                    int g) {
+    constexpr int V = 4;
+    constexpr int KP = 4 * KQ;
+    constexpr int LD = KP + V;
+    const int nunit = a.nunit;
+    int pp = 0;
+    // panel pairs (pp, pp+1) start at even panels of a group whose first
+    // panel is even, and slabs hold an even number of panels, so a pair
+    // never straddles two output slabs
+    for (; pp + 1 < np; pp += 2) {
+        const int panel = p_lo + pp;
+        const int slab_o = panel / a.mblk;
+        const int i0 = (panel % a.mblk) * 16;
+        f32x4 accA[CB], accB[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            accA[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            accB[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        const float* arowA = dl + (pp * 16 + c) * LD + g * KQ;
+        const float* arowB = arowA + 16 * LD;
+#pragma unroll
+        for (int t = 0; t < KQ; t += V) {
+            const f32x4 avA = *reinterpret_cast<const f32x4*>(arowA + t);
+            const f32x4 avB = *reinterpret_cast<const f32x4*>(arowB + t);
+#pragma unroll
+            for (int q = 0; q < V; ++q)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    accA[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avA[q], b[cb][t + q], accA[cb], 0, 0, 0);
+                    accB[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(avB[q], b[cb][t + q], accB[cb], 0, 0, 0);
+                }
+        }
+        // lanes c < 8 keep panel A and take lane c+8's; lanes c >= 8 keep
+        // panel B and take lane c-8's: store 1 holds elements c&7 (nodes
+        // i0 .. i0+31), store 2 elements 8 + (c&7)
+        const bool lo = c < 8;
+        const int i = i0 + (lo ? 0 : 16) + 4 * g;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            f32x4 x1, x2;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float send = lo ? accB[cb][r] : accA[cb][r];
+                const float got = __builtin_bit_cast(
+                    float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, send),
+                                                       0x128 /* row_ror:8 */, 0xF, 0xF, false));
+                x1[r] = lo ? accA[cb][r] : got;
+                x2[r] = lo ? got : accB[cb][r];
+            }
+            const int64_t e1 = e0 + cb * 16 + (c & 7);
+            const int64_t e2 = e1 + 8;
+            if (i < nunit) {
+                if (e1 < a.nelem)
+                    *reinterpret_cast<f32x4*>(out + ((int64_t)slab_o * a.nelem + e1) * nunit + i) = x1;
+                if (e2 < a.nelem)
+                    *reinterpret_cast<f32x4*>(out + ((int64_t)slab_o * a.nelem + e2) * nunit + i) = x2;
+            }
+        }
+    }
+    return pp;
+}
+
+// One panel of a paired-store tile (the odd last panel of a group).
+template <int KQ, int CB>
+__device__ inline void single_panel_vec(const float (&b)[CB][KQ], int64_t e0, int p_lo, int pp,
+                                        const float* dl, float* __restrict__ out, const KArgs& a,
+                                        int c, int g) {
+    constexpr int KP = 4 * KQ;
+    constexpr int LD = KP + 4;
+    const int nunit = a.nunit;
+    const int panel = p_lo + pp;
+    const int slab_o = panel / a.mblk;
+    const int i = (panel % a.mblk) * 16 + 4 * g;
+    f32x4 acc[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float* arow = dl + (pp * 16 + c) * LD + g * KQ;
+#pragma unroll
+    for (int t = 0; t < KQ; t += 4) {
+        const f32x4 av = *reinterpret_cast<const f32x4*>(arow + t);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], b[cb][t + q], acc[cb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int64_t e = e0 + cb * 16 + c;
+        if (e < a.nelem && i < nunit)
+            *reinterpret_cast<f32x4*>(out + ((int64_t)slab_o * a.nelem + e) * nunit + i) = acc[cb];
+    }
+}
+
+// ------------------------------------------------- pipelined element loads
+// (paired-store kernels with 16-byte element rows)
+// One counter tracks a wave's outstanding vector loads and stores, and the
+// compiler's own wait before the first use of a loaded register counts every
+// store issued since as pending: a persistent loop that loads the next tile
+// and then stores the current one waits for all of its stores, and the load,
+// at each tile boundary.  Here the next tile's element data are issued as
+// loads the compiler does not track, before the current tile's stores, and the
+// wave waits for them with an explicit count that leaves the current tile's
+// stores in flight: waiting until at most m operations are outstanding, with
+// m no more than the stores issued after the loads, completes the loads.
+// Every lane loads from a valid address (rows past the end clamp to the last
+// element, columns past the end to column 0); values are masked after the
+// wait.
+__device__ inline void async_load4(f32x4& r, const float* p) {
+    asm volatile("global_load_dwordx4 %0, %1, off" : "=v"(r) : "v"(p) : "memory");
+}
+template <int N>
+__device__ inline void vm_wait() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+// wait until at most m vector memory operations are outstanding, for the
+// largest bucket m <= n (n wave-uniform)
+__device__ inline void vm_wait_below(int n) {
+    if (n >= 32) vm_wait<32>();
+    else if (n >= 16) vm_wait<16>();
+    else if (n >= 8) vm_wait<8>();
+    else if (n >= 4) vm_wait<4>();
+    else vm_wait<0>();
+}
+// the loaded registers pass through an empty statement ordered after the
+// wait, so that nothing reads them earlier
+__device__ inline void settle(f32x4& r) { asm volatile("" : "+v"(r)); }
+
+template <int KQ, int CB>
+struct TileBuf {
+    f32x4 v[CB][KQ / 4];
+};
+
+template <int KQ, int CB>
+__device__ inline void tile_issue(const float* __restrict__ src, int64_t e0, int c, int g,
+                                  const KArgs& a, TileBuf<KQ, CB>& t) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int64_t e = e0 + cb * 16 + c;
+        const int64_t ec = e < a.nelem ? e : a.nelem - 1;
+        const float* row = src + ec * a.nunit;
+#pragma unroll
+        for (int s4 = 0; s4 < KQ / 4; ++s4) {
+            const int col = g * KQ + 4 * s4;
+            async_load4(t.v[cb][s4], row + (col < a.nunit ? col : 0));
+        }
+    }
+}
+
+template <int KQ, int CB>
+__device__ inline void tile_settle(TileBuf<KQ, CB>& t) {
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int s4 = 0; s4 < KQ / 4; ++s4) settle(t.v[cb][s4]);
+}
+
+// Fewest store instructions one tile issues: all of them (two per pair, one
+// per single panel, per column block) when the tile's elements all exist, at
+// least one per pair or single otherwise (its first element's).
+template <int CB>
+__device__ inline int tile_stores_min(int np, bool full) {
+    const int pairs = np / 2, singles = np - 2 * pairs;
+    return full ? (2 * pairs + singles) * CB : pairs + singles;
+}
+
+template <int KQ, int CB>
+__device__ inline void tile_compute(const TileBuf<KQ, CB>& t, int64_t e0, int p_lo, int np,
+                                    const float* dl, float* __restrict__ out, const KArgs& a, int c,
+                                    int g) {
+    float b[CB][KQ];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const bool ev = e0 + cb * 16 + c < a.nelem;
+#pragma unroll
+        for (int s4 = 0; s4 < KQ / 4; ++s4) {
+            const bool ok = ev && g * KQ + 4 * s4 < a.nunit;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[cb][4 * s4 + q] = ok ? t.v[cb][s4][q] : 0.f;
+        }
+    }
+    const int pp = paired_panels<KQ, CB>(b, e0, p_lo, np, dl, out, a, c, g);
+    if (pp < np) single_panel_vec<KQ, CB>(b, e0, p_lo, pp, dl, out, a, c, g);
+}
+
 // ACC: out += result instead of out = result (a compile-time switch: as a
 // runtime branch it costs the FP32 kernels ~150 registers).
 // Work-groups of up to 8 waves for variants whose element operand takes at
@@ -295,6 +486,42 @@ __global__ void __launch_bounds__((dg_max_threads<T, KQ, CB, NSEG>())) dg_kernel
     __syncthreads();
 
     const int64_t tile_elems = (int64_t)nw * 16 * CB;
+    if constexpr (PAIR && KQ * CB <= 32) {
+        if (a.vec_in) {
+            // pipelined element loads (see above); no block-level sync below
+            const int64_t woff = (int64_t)__builtin_amdgcn_readfirstlane(wave) * 16 * CB;
+            TileBuf<KQ, CB> A, B;
+            int64_t t0 = stream;
+            if (t0 >= a.ntiles) return;
+            // a wave-tile whose first element is past the end loads nothing
+            // (and computes nothing)
+            if (t0 * tile_elems + woff < a.nelem) tile_issue<KQ, CB>(src, t0 * tile_elems + woff, c, g, a, A);
+            vm_wait<0>();
+            tile_settle(A);
+            for (;;) {
+                const int64_t t1 = t0 + a.nstreams;
+                const bool more1 = t1 < a.ntiles;
+                if (more1 && t1 * tile_elems + woff < a.nelem)
+                    tile_issue<KQ, CB>(src, t1 * tile_elems + woff, c, g, a, B);
+                const int64_t ea = t0 * tile_elems + woff;
+                if (ea < a.nelem) tile_compute<KQ, CB>(A, ea, p_lo, np, dl, out, a, c, g);
+                if (!more1) break;
+                vm_wait_below(ea < a.nelem ? tile_stores_min<CB>(np, ea + 16 * CB <= a.nelem) : 0);
+                tile_settle(B);
+                const int64_t t2 = t1 + a.nstreams;
+                const bool more2 = t2 < a.ntiles;
+                if (more2 && t2 * tile_elems + woff < a.nelem)
+                    tile_issue<KQ, CB>(src, t2 * tile_elems + woff, c, g, a, A);
+                const int64_t eb = t1 * tile_elems + woff;
+                if (eb < a.nelem) tile_compute<KQ, CB>(B, eb, p_lo, np, dl, out, a, c, g);
+                if (!more2) break;
+                vm_wait_below(eb < a.nelem ? tile_stores_min<CB>(np, eb + 16 * CB <= a.nelem) : 0);
+                tile_settle(A);
+                t0 = t2;
+            }
+            return;
+        }
+    }
     for (int64_t tile = stream; tile < a.ntiles; tile += a.nstreams) {
         const int64_t e0 = tile * tile_elems + (int64_t)wave * 16 * CB;
         if (e0 >= a.nelem) continue;  // whole wave past the end (no block-level sync below)
@@ -347,60 +574,7 @@ __global__ void __launch_bounds__((dg_max_threads<T, KQ, CB, NSEG>())) dg_kernel
         int pp_first = 0;
         if constexpr (PAIR) {
             static_assert(V == 4 && NSEG == 1 && !ACC, "paired stores: FP32 forward only");
-            // panel pairs (pp, pp+1) start at even panels of a group whose
-            // first panel is even, and slabs hold an even number of panels,
-            // so a pair never straddles two output slabs
-            for (; pp_first + 1 < np; pp_first += 2) {
-                const int panel = p_lo + pp_first;
-                const int slab_o = panel / a.mblk;
-                const int i0 = (panel % a.mblk) * 16;
-                acc_t accA[CB], accB[CB];
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    accA[cb] = acc_t(T(0));
-                    accB[cb] = acc_t(T(0));
-                }
-                const T* arowA = dl + (pp_first * 16 + c) * LD + g * KQ;
-                const T* arowB = arowA + 16 * LD;
-#pragma unroll
-                for (int t = 0; t < KQ; t += V) {
-                    const vec_t avA = *reinterpret_cast<const vec_t*>(arowA + t);
-                    const vec_t avB = *reinterpret_cast<const vec_t*>(arowB + t);
-#pragma unroll
-                    for (int q = 0; q < V; ++q)
-#pragma unroll
-                        for (int cb = 0; cb < CB; ++cb) {
-                            accA[cb] = Mma<T>::step(avA[q], b[0][cb][t + q], accA[cb]);
-                            accB[cb] = Mma<T>::step(avB[q], b[0][cb][t + q], accB[cb]);
-                        }
-                }
-                // lanes c < 8 keep panel A and take lane c+8's; lanes c >= 8
-                // keep panel B and take lane c-8's: store 1 holds elements
-                // c&7 (nodes i0 .. i0+31), store 2 elements 8 + (c&7)
-                const bool lo = c < 8;
-                const int i = i0 + (lo ? 0 : 16) + 4 * g;
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    f32x4 x1, x2;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float send = lo ? accB[cb][r] : accA[cb][r];
-                        const float got = __builtin_bit_cast(
-                            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, send),
-                                                               0x128 /* row_ror:8 */, 0xF, 0xF, false));
-                        x1[r] = lo ? accA[cb][r] : got;
-                        x2[r] = lo ? got : accB[cb][r];
-                    }
-                    const int64_t e1 = e0 + cb * 16 + (c & 7);
-                    const int64_t e2 = e1 + 8;
-                    if (i < nunit) {
-                        if (e1 < a.nelem)
-                            *reinterpret_cast<f32x4*>(out + ((int64_t)slab_o * a.nelem + e1) * nunit + i) = x1;
-                        if (e2 < a.nelem)
-                            *reinterpret_cast<f32x4*>(out + ((int64_t)slab_o * a.nelem + e2) * nunit + i) = x2;
-                    }
-                }
-            }
+            pp_first = paired_panels<KQ, CB>(b[0], e0, p_lo, np, dl, out, a, c, g);
         }
         for (int pp = pp_first; pp < np; ++pp) {
             const int panel = p_lo + pp;
@@ -602,6 +776,14 @@ inline bool pair_eligible(size_t tsize, int nunit, bool vec_out, const Plan& P) 
     return tsize == 4 && vec_out && nunit % 32 == 0 && P.mblk % 2 == 0 && P.ppg % 2 == 0;
 }
 
+// Paired-store launches whose element fragments are small (KQ * CB <= 32)
+// and come as 16-byte vectors take the pipelined element loads; these load
+// every row of a wave-tile that starts before the end (rows past it clamp to
+// the last element).
+inline bool pipelined_loads(size_t tsize, int nunit, int kq, int cb, bool vec_out, const Plan& P) {
+    return pair_eligible(tsize, nunit, vec_out, P) && kq * cb <= 32 && P.vec_in;
+}
+
 // Launch one contraction with the kernel fn (or fn_pair where the paired
 // stores apply); tile->groups_per_cu == 0 means "occupancy maximum" (queried
 // for the kernel launched).
@@ -691,11 +873,13 @@ inline dg_status forward_cb(size_t tsize, int kq, bool rows_aligned, int epw, in
 
 // Default waves per work-group: 8 (two copies' worth of waves sharing one
 // set of resident operator panels) where the variant allows 512 threads and
-// it measured faster -- FP32 rows off 16-byte boundaries, and FP32 rows of
-// 128 or more nodes per lane group -- else 4.
-inline int forward_waves(size_t tsize, int kq, int cb, bool rows_aligned) {
+// it measured faster -- FP32 rows off 16-byte boundaries, FP32 rows of 128 or
+// more nodes per lane group, and the pipelined paired-store shapes (rows of
+// a multiple of 32 nodes, KQ * CB <= 32) -- else 4.
+inline int forward_waves(size_t tsize, int nunit, int kq, int cb, bool rows_aligned) {
     const bool fits = cb * kq * (int)tsize <= 256;  // dg_max_threads() == 512
-    if (tsize == 4 && fits && (!rows_aligned || kq >= 32)) return 8;
+    const bool piped = rows_aligned && nunit % 32 == 0 && kq * cb <= 32;
+    if (tsize == 4 && fits && (!rows_aligned || kq >= 32 || piped)) return 8;
     return 4;
 }
 

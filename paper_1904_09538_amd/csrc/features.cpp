@@ -57,8 +57,11 @@ dg_status count_dg_fp(const perf_kernel_desc* d, int64_t* c) {
     c[PF_WORKGROUPS] = P.grid;
     c[PF_BARRIER_X_WG] = P.grid;  // one barrier after the operator staging
     c[PF_GLD_DG_D] = 8 * P.slots * (int64_t)M * n * n * (int64_t)sz;
-    c[P.vec_in ? PF_GLD_DG_U : PF_GLD_DG_U_UNAL] = E * n * (int64_t)sz;
-    c[PF_GLD_DG_U_L2] = (int64_t)(P.ngroups - 1) * E * n * (int64_t)sz;
+    // element rows read per operator group: the pipelined loads take whole
+    // wave-tiles (rows past the end clamp to the last element)
+    const int64_t urows = kern::pipelined_loads(sz, n, kq, cb, n % 4 == 0, P) ? nwt * 16 * cb : E;
+    c[P.vec_in ? PF_GLD_DG_U : PF_GLD_DG_U_UNAL] = urows * n * (int64_t)sz;
+    c[PF_GLD_DG_U_L2] = (int64_t)(P.ngroups - 1) * urows * n * (int64_t)sz;
     // unaligned rows read through the wave slab are also written through it:
     // contiguous stores (plus one LDS write and read per output value)
     const bool stage_out = P.use_slab && n % 4 != 0;

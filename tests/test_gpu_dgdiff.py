@@ -133,6 +133,23 @@ def test_paired_matches_single_panels_bitwise(ops, nunit):
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("nunit,tile", [(32, None), (64, None), (64, dict(elems_per_wave=32)),
+                                        (64, dict(waves=4)), (128, None)])
+def test_pipelined_loads_many_tiles(orc, ops, nunit, tile):
+    """Paired-store launches with small fragments load the next tile's element
+    data ahead of the current tile's stores: many tiles per stream, a ragged
+    end; equal to the oracle and bit-identical to a launch with an odd panel
+    group (single panels, loads not pipelined)."""
+    D = I.random_dmats(nunit)
+    u = I.uniform_u(300007, nunit)
+    _check(orc, ops, D, u, torch.float32, tile=tile)
+    Dg, ug = _dev(D, torch.float32), _dev(u, torch.float32)
+    a = ops.dgdiff_apply(Dg, ug, tile=tile)
+    b = ops.dgdiff_apply(Dg, ug, tile=dict(tile or {}, d_panels=3))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_integer_data_bit_exact(orc, ops, dtype):
     rng = np.random.default_rng(12)
