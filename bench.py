@@ -289,7 +289,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--rows", default="all",
                     help="comma list of extra rows (orders,lowp,batched,adjoint,companions,model) "
                          "or 'all' or 'none'")
