@@ -24,6 +24,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -295,13 +296,14 @@ def main():
                          "or 'all' or 'none'")
     ap.add_argument("--cpu-baseline", type=int, default=1 << 21,
                     help="elements of the workload the CPU oracle runs on (0: skip)")
+    ap.add_argument("--calib-out", default=os.path.join(tempfile.gettempdir(), "dgdiff_bench_calibration.jsonl"),
+                    help="where the model row writes its calibration measurements (JSON lines)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy three times: its FETCH_SIZE / "
                          "WRITE_SIZE counters calibrate the DG kernel's under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X; how the path would "
-              "shard over several GPUs is described in DESIGN.md, nothing is launched on more.",
+        print("bench.py measures one GPU (a single MI355X); nothing is launched on more than one.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -357,8 +359,8 @@ def main():
     small = max(5, args.steps // 5)
     model_summary = None
     if "model" in want:
-        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-        model_summary, rows["model"] = row_model(os.path.join(ROOT, "gpurun_out", "bench_calibration.jsonl"))
+        os.makedirs(os.path.dirname(os.path.abspath(args.calib_out)), exist_ok=True)
+        model_summary, rows["model"] = row_model(args.calib_out)
         log(f"model: held-out MAPE {100 * rows['model']['mape_heldout_all']:.1f}%")
     if "orders" in want:
         rows["dg_fp32_orders_2e21"] = row_dg_orders(L, I, np, torch, small)

@@ -10,7 +10,7 @@
  * or flops it moves.  No closed form is used anywhere in this file; the
  * library's closed forms must reproduce these counts exactly.
  *
- * Counting rules (the paper's granularities, read for this build):
+ * Counting rules (the paper's granularities, as read here):
  *   global and LDS traffic in bytes of the lanes that execute the access;
  *   matrix-core flops of every executed MFMA instruction (2*16*16*K);
  *   VALU flops per computing lane; barriers per work-item, times work-groups.
