@@ -252,8 +252,14 @@ def row_model(path):
                 "n_heldout": v["n_heldout"],
                 **({"ranking": v["ranking"]} if "ranking" in v else {})}
             for k, v in s["families"].items()}
+    x = s.get("cross")
+    cross = None if not x else {
+        "trained_on": x["train_families"], "predicts": x["target"], "n_target": x["n_target"],
+        "mape": x["nonneg"]["mape"], "geomean": x["nonneg"]["geomean"],
+        "ranking": x["nonneg"].get("ranking"), "unconstrained_mape": x["unconstrained"]["mape"]}
     return s, {"mape_heldout_all": s["mape_heldout_all"],
                "geomean_heldout_all": s["geomean_heldout_all"], "families": fams,
+               "cross_kernel": cross,
                "protocol": "cold cache, 60 event-timed trials per variant, 20% held out (seed 4); "
                            "unconstrained fit, non-negative fit beside"}
 

@@ -345,6 +345,59 @@ def fit_family(meta, rows, family, L, kind=None, with_overhead_rows=True):
     return out
 
 
+# ------------------------------------------------------------ cross-kernel
+# The paper calibrates on kernels other than the one predicted (Section
+# "Results": microbenchmarks, then the application kernels).  Here the model
+# is fitted on the companion and empty kernels only and predicts the DG
+# variants.  Their tagged counts are summed into kernel-independent features
+# (global bytes loaded and stored, whatever the array or pattern), so what the
+# tags distinguish -- aligned vs unaligned rows, L2 re-reads by other operator
+# groups -- is invisible to this model by construction.
+GENERIC = {"launch": ("launch",), "workgroups": ("workgroups",), "serial_steps": ("serial_steps",),
+           "gld": ("gld_",), "gst": ("gst_",), "lds_bytes": ("lds_bytes",), "mfma_f32": ("mfma_f32",),
+           "valu_f32": ("valu_f32",)}
+GENERIC_GROUP = {"launch": 0, "workgroups": 0, "serial_steps": 0, "gld": 1, "gst": 1, "lds_bytes": 2,
+                 "mfma_f32": 2, "valu_f32": 2}
+
+
+def generic_features(names, rows):
+    """[rows][len(GENERIC)] matrix: each generic feature the sum of the counted
+    features whose name equals one of its entries or, for entries ending in
+    '_', starts with it."""
+    idx = []
+    for keys in GENERIC.values():
+        idx.append([i for i, nm in enumerate(names)
+                    if any(nm == k or (k.endswith("_") and nm.startswith(k)) for k in keys)])
+    return np.array([[sum(r["features"][i] for i in ix) for ix in idx] for r in rows], dtype=np.float64)
+
+
+def fit_cross(meta, rows, L, train=("stencil", "matmul", "empty"), target="dg"):
+    """Overlap model on the generic features, fitted on the `train` families,
+    scored on every `target` row (non-negative fit, and the unconstrained one
+    beside it)."""
+    names = meta["feature_names"]
+    tr = [r for r in rows if r["family"] in train]
+    tg = [r for r in rows if r["family"] == target]
+    if not tr or not tg:
+        return None
+    Ftr, ttr = generic_features(names, tr), np.array([r["t"]["mean"] for r in tr])
+    Ftg, ttg = generic_features(names, tg), np.array([r["t"]["mean"] for r in tg])
+    group = [GENERIC_GROUP[k] for k in GENERIC]
+    out = {"train_families": list(train), "target": target, "features": list(GENERIC),
+           "n_train": len(tr), "n_target": len(tg)}
+    for label, nonneg in (("nonneg", True), ("unconstrained", False)):
+        lin = L.perf_model_fit(Ftr, ttr, relative=True, nonneg=nonneg)
+        fit = L.perf_model_fit_overlap(Ftr, ttr, group, relative=True, p0=lin["p"], nonneg=nonneg)
+        pred = L.perf_model_predict_overlap(Ftg, group, fit["p"], fit["edge"])
+        res = {"mape": mape(pred, ttg), "geomean": geomean(pred, ttg),
+               "mape_train": mape(L.perf_model_predict_overlap(Ftr, group, fit["p"], fit["edge"]), ttr),
+               "params": [float(x) for x in fit["p"]], "edge": fit["edge"]}
+        if target == "dg":
+            res["ranking"] = ranking([(r["p"], r["nelem"]) for r in tg], pred, ttg)
+        out[label] = res
+    return out
+
+
 def fit_all(path, kinds=None):
     from . import _lib
     meta, rows = load(path)
@@ -358,6 +411,7 @@ def fit_all(path, kinds=None):
         allm += [h["measured_s"] for h in f["heldout"]]
     out["mape_heldout_all"] = mape(allp, allm) if allm else None
     out["geomean_heldout_all"] = geomean(allp, allm) if allm else None
+    out["cross"] = fit_cross(meta, rows, _lib)
     return out
 
 

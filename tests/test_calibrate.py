@@ -86,3 +86,37 @@ def test_ranking_statistics():
     assert rev["regret_max"] == pytest.approx(2.0) and rev["regret_mean"] == pytest.approx(1.25)
     assert C.kendall_tau([1, 2, 3], [1, 3, 2]) == pytest.approx(1 / 3)
     assert C.ranking([1, 2], [1.0, 2.0], [1.0, 2.0]) is None
+
+
+def test_generic_features_sum_the_tags():
+    from paper_1904_09538_amd import _lib as L
+    names = L.feature_names()
+    tile = dict(elems_per_wave=16, waves=4, groups_per_cu=2, d_panels=12)
+    f = L.perf_features_count("dg", "f32", 5000, 64, 3, tile, 256).tolist()
+    g = C.generic_features(names, [{"features": f}])[0]
+    d = dict(zip(names, f))
+    assert g[list(C.GENERIC).index("gld")] == sum(v for k, v in d.items() if k.startswith("gld_"))
+    assert g[list(C.GENERIC).index("gst")] == sum(v for k, v in d.items() if k.startswith("gst_"))
+    assert g[list(C.GENERIC).index("mfma_f32")] == d["mfma_f32"]
+
+
+def test_cross_kernel_fit_recovers_a_shared_law(tmp_path):
+    """Times that follow one overlap law on the kernel-independent features
+    for every family: fitted on stencil, matmul and empty kernels, the model
+    predicts the DG variants it never saw.  The law switches sharply between
+    memory and on-chip cost (edge 1e3): the stencil and matmul rows lie far on
+    either side of the switch, so a soft switch would not be identifiable from
+    them."""
+    from paper_1904_09538_amd import _lib as L
+    meta, rows = _synthetic_rows(L, {})
+    names = meta["feature_names"]
+    group = [C.GENERIC_GROUP[k] for k in C.GENERIC]
+    p_true = np.array([4e-6, 2e-9, 5e-8, 1 / 5e12, 1 / 4e12, 1 / 60e12, 1 / 150e12, 1 / 50e12])
+    edge = 1e3
+    t = L.perf_model_predict_overlap(C.generic_features(names, rows), group, p_true, edge)
+    for r, tt in zip(rows, t):
+        r["t"] = {"mean": float(tt)}
+    x = C.fit_cross(meta, rows, L)
+    assert x["nonneg"]["mape_train"] < 1e-6
+    assert x["nonneg"]["mape"] < 1e-4, x["nonneg"]["mape"]
+    np.testing.assert_allclose(x["nonneg"]["params"], p_true, rtol=1e-3)
