@@ -188,10 +188,13 @@ def test_fp8_requires_scales(ops):
 
 
 @pytest.mark.parametrize("to", ["bf16", "e4m3"])
-def test_lowp_full_size_sampled(orc, ops, to):
-    """Hex p=5, 2^20 elements: the low-precision benchmark configuration."""
-    n, E = 216, 1 << 20
-    D32 = I.gll_dmats(5).astype(np.float32)
+@pytest.mark.parametrize("p,E", [(5, 1 << 20), (3, 1 << 21)])
+def test_lowp_full_size_sampled(orc, ops, to, p, E):
+    """Hex p=5, 2^20 elements (the low-precision benchmark configuration) and
+    hex p=3, 2^21 (paired stores): sampled outputs, and the sampled rows'
+    quantiser codes and scales bit-equal to the oracle's."""
+    n = (p + 1) ** 3
+    D32 = I.gll_dmats(p).astype(np.float32)
     u32 = np.asarray(I.uniform_u(E, n), dtype=np.float32)
     qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), to)
     qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), to)
@@ -204,6 +207,10 @@ def test_lowp_full_size_sampled(orc, ops, to):
     us = u32[sel]
     qDo, isDo = orc.quantize(D32.reshape(3, -1), to, True)
     quo, isuo = orc.quantize(us, to, True)
+    codes = qu[torch.from_numpy(sel).cuda()].view(torch.int16 if to == "bf16" else torch.uint8).cpu().numpy()
+    np.testing.assert_array_equal(codes.view(np.uint16) if to == "bf16" else codes, quo)
+    if to == "e4m3":
+        np.testing.assert_array_equal(isu[torch.from_numpy(sel).cuda()].cpu().numpy(), isuo)
     if to == "bf16":
         Dd = orc.bf16_decode_array(qDo).astype(np.float64).reshape(3, n, n)
         ud = orc.bf16_decode_array(quo).astype(np.float64)
