@@ -240,6 +240,19 @@ def row_companions(L, I, np, torch, steps):
     return {"stencil5": st, "matmul": mm}
 
 
+def achievable_hbm(torch):
+    """Measured reference rates of this GPU's memory system: a plain 1 GiB fill
+    (write only) and a 1 GiB device-to-device copy (read + write), steady
+    state (40 ms warm-up), GB/s."""
+    src = torch.ones(1 << 28, device="cuda")
+    dst = torch.empty_like(src)
+    tf = timed(lambda: dst.fill_(2.0), 20, 2)
+    tc = timed(lambda: dst.copy_(src), 20, 2)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"fill_GBps": (1 << 30) / tf / 1e9, "copy_GBps": 2 * (1 << 30) / tc / 1e9}
+
+
 def row_model(path):
     import contextlib
     from paper_1904_09538_amd import calibrate as C
@@ -380,6 +393,15 @@ def main():
     if "companions" in want:
         rows.update(row_companions(L, I, np, torch, small))
 
+    # the roofline against measured achievable rates beside the spec peaks:
+    # the FP32 matrix rate the matmul row reaches, the fill and copy rates
+    ach = achievable_hbm(torch)
+    mm = rows.get("matmul")
+    if mm:
+        ach["mfma_f32_TFLOPs_matmul"] = mm["roofline"]["achieved"]
+        roof["frac_vs_achievable"] = roof["achieved"] / mm["roofline"]["achieved"]
+    log(f"achievable: fill {ach['fill_GBps']:.0f} GB/s, copy {ach['copy_GBps']:.0f} GB/s")
+
     cpu = None
     if args.cpu_baseline:
         log(f"cpu baseline: FP64 oracle on {min(args.cpu_baseline, E)} elements")
@@ -395,6 +417,7 @@ def main():
                                f"operators, {E} elements, u~U(-1,1) seed 0",
                    "nelem": E, "nunit": n, "nmat": nmat},
         "roofline": roof,
+        "achievable": ach,
         "cpu_baseline": cpu,
         "rows": rows,
         "wall_s_timed": wall,
