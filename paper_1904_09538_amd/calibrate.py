@@ -102,7 +102,8 @@ def stencil_variants(quick=False):
 
 
 def matmul_variants(quick=False):
-    ns = ([512, 768, 1024, 1280, 1536, 2048, 2560, 3072, 4096, 5120, 6144, 8192] if not quick
+    ns = ([512, 640, 768, 896, 1024, 1280, 1536, 1792, 2048, 2304, 2560, 3072, 3584, 4096, 4608,
+           5120, 6144, 7168, 8192] if not quick
           else [512, 2048, 8192])
     return [{"family": "matmul", "n": n} for n in ns]
 
