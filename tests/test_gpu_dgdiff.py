@@ -191,6 +191,27 @@ def test_unaligned_pointers(orc, ops):
     assert normwise_rel(ov.double().cpu().numpy(), orc.dg_forward(_as(D, torch.float32), u)) <= 1e-5
 
 
+@pytest.mark.parametrize("nunit,nelem", [(5, 1), (10, 4099), (26, 513), (27, 37), (27, 300007), (30, 65)])
+def test_slab_rows_vector_and_scalar_loads_bitwise(orc, ops, nunit, nelem):
+    """Rows off 16-byte boundaries reach the wave's slab as 16-byte vectors
+    when the source is aligned and value by value when it starts one element
+    into a buffer: both give bit-identical results, equal to the oracle, over
+    many tiles and a run whose last values end inside a vector
+    (nelem * nunit not a multiple of 4)."""
+    D = _as(I.random_dmats(nunit), torch.float32)
+    u = _as(I.uniform_u(nelem, nunit), torch.float32)
+    Dg, ug = _dev(D, torch.float32), _dev(u, torch.float32)
+    ub = torch.zeros(nelem * nunit + 4, device="cuda:0")
+    uv = ub[1:1 + nelem * nunit].view(nelem, nunit)
+    uv.copy_(ug)
+    a = ops.dgdiff_apply(Dg, ug)
+    b = ops.dgdiff_apply(Dg, uv)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    from oracle.metrics import normwise_rel
+    assert normwise_rel(a.double().cpu().numpy(), orc.dg_forward(D, u)) <= 1e-5
+
+
 def test_nan_propagates_to_its_element_only(orc, ops):
     nunit, nelem = 27, 64
     D = I.random_dmats(nunit)
