@@ -209,7 +209,8 @@ typedef struct {
     int32_t nunit;     /* DG only */
     int32_t nmat;      /* DG only */
     dg_tile tile;      /* DG only: fully resolved launch shape (dgdiff_resolve_tile) */
-    int32_t num_cu;    /* DG only: compute units of the target device */
+    int32_t num_cu;    /* DG, matmul: compute units of the target device (matmul: 0
+                          counts one work-group's serial chain, not the busiest unit's) */
 } perf_kernel_desc;
 
 /* Feature indices of perf_features_count (counts are int64, exact):          */

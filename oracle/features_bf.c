@@ -20,6 +20,7 @@
  * kernels' documented interface, not shared code.
  */
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 /* feature slots, in the order of the library's interface */
@@ -288,9 +289,13 @@ static void stencil_walk(int dtype, int64_t n, int64_t* c) {
 
 /* ---------------------------------------------------------------- matmul */
 
-static void matmul_walk(int64_t n, int64_t* c) {
+/* num_cu > 0: the serial chain is that of the compute unit with the most
+   k-chunks when work-group w (in dispatch order) runs on unit w mod num_cu;
+   0: the chain of one work-group */
+static void matmul_walk(int64_t n, int num_cu, int64_t* c) {
     const int64_t g = cdiv(n, 128), nk = cdiv(n, 16);
     const int vec = n % 16 == 0;
+    int64_t* unit = num_cu > 0 ? calloc((size_t)num_cu, sizeof(int64_t)) : NULL;
     c[F_LAUNCH] += 1;
     c[F_WG] += g * g;
     for (int64_t by = 0; by < g; ++by)
@@ -300,6 +305,11 @@ static void matmul_walk(int64_t n, int64_t* c) {
             {
                 int64_t steps = 0;
                 for (int64_t kc = 0; kc < nk; ++kc) ++steps;
+                if (unit) {
+                    int64_t* u = &unit[(by * g + bx) % num_cu];
+                    *u += steps;
+                    steps = *u;
+                }
                 if (steps > c[F_SERIAL]) c[F_SERIAL] = steps;
             }
             for (int t = 0; t < 256; ++t) {
@@ -339,6 +349,7 @@ static void matmul_walk(int64_t n, int64_t* c) {
             }
             for (int w = 0; w < 4; ++w) c[F_MFMA_F32] += nk * 64 * 2048;
         }
+    free(unit);
 }
 
 /* counts[F_N] overwritten; returns 0 on success */
@@ -353,7 +364,7 @@ int orc_features(int kernel, int dtype, int64_t n0, int nunit, int nmat, int epw
             if (n0 > 0) stencil_walk(dtype, n0, counts);
             return 0;
         case K_MATMUL:
-            if (n0 > 0) matmul_walk(n0, counts);
+            if (n0 > 0) matmul_walk(n0, num_cu, counts);
             return 0;
         case K_EMPTY:
             counts[F_LAUNCH] = 1;

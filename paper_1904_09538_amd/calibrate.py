@@ -19,7 +19,7 @@ of the kept samples.
 Measurement set: the DG forward in FP32 for hexahedral orders p = 1..7
 (nunit 8 .. 512) at 2^16..2^21 elements (2^15..2^19 for p = 6, 7) with five
 launch shapes each,
-the five-point stencil at fourteen n in 1024..16384, square matmul at twelve
+the five-point stencil at fourteen n in 1024..16384, square matmul at nineteen
 n in 512..8192, and empty kernels with 16..65536 work-groups (launch and
 work-group costs).  The fitted models use the linear form for the stencil and
 the overlap form for DG and matmul, as the paper does.
@@ -196,7 +196,7 @@ def measure(path, quick=False, trials=60, families=("dg", "stencil", "matmul", "
             c = torch.empty((n, n), device=dev)
             tm = time_launch(lambda: _lib.matmul_apply(a, b, c), trials if n < 8192 else 20,
                              flush=flush)
-            emit({**v, "t": tm, "features": _lib.perf_features_count("matmul", "f32", n).tolist()})
+            emit({**v, "t": tm, "features": _lib.perf_features_count("matmul", "f32", n, num_cu=num_cu).tolist()})
             del a, b, c
     if "empty" in families:
         for v in empty_variants(quick):

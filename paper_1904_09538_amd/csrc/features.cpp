@@ -144,7 +144,11 @@ dg_status count_matmul(const perf_kernel_desc* d, int64_t* c) {
     c[PF_GST_MM_C] = 4 * n * n;
     c[PF_LDS_BYTES] = wg * nk * 256 * (64 + 128);  // chunk stores + operand reads
     c[PF_MFMA_F32] = wg * nk * 4 * 64 * 2048;
-    c[PF_SERIAL_STEPS] = nk;  // k-chunks of one work-group
+    // k-chunks walked by the busiest compute unit: the work-groups are dealt
+    // evenly over num_cu units (one work-group's chain when num_cu is 0).
+    // The tiles are MFMA-bound, so work-groups sharing a unit share its
+    // matrix cores and the busiest unit's chain sets the time.
+    c[PF_SERIAL_STEPS] = (d->num_cu > 0 ? ceil_div(wg, (int64_t)d->num_cu) : 1) * nk;
     return DG_OK;
 }
 

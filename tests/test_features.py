@@ -69,9 +69,22 @@ def test_stencil_counts_match_brute_force(orc, L, dtype, n):
 
 
 @pytest.mark.parametrize("n", [1, 7, 16, 100, 128, 130, 512, 1000, 2048])
-def test_matmul_counts_match_brute_force(orc, L, n):
-    np.testing.assert_array_equal(L.perf_features_count("matmul", "f32", n),
-                                  orc.features("matmul", "f32", n))
+@pytest.mark.parametrize("num_cu", [0, 7, 256])
+def test_matmul_counts_match_brute_force(orc, L, n, num_cu):
+    np.testing.assert_array_equal(L.perf_features_count("matmul", "f32", n, num_cu=num_cu),
+                                  orc.features("matmul", "f32", n, num_cu=num_cu))
+
+
+def test_matmul_serial_chain_is_the_busiest_unit():
+    """Hand counts: n = 2048 gives 16 x 16 = 256 work-groups of 128 k-chunks,
+    one per unit on 256 units; n = 2560 gives 400, two on the busiest unit
+    (320 chunks); on 7 units 256 work-groups put 37 on the busiest."""
+    from paper_1904_09538_amd import _lib as L
+    k = L.feature_names().index("serial_steps")
+    assert L.perf_features_count("matmul", "f32", 2048, num_cu=256)[k] == 128
+    assert L.perf_features_count("matmul", "f32", 2560, num_cu=256)[k] == 2 * 160
+    assert L.perf_features_count("matmul", "f32", 2048, num_cu=7)[k] == 37 * 128
+    assert L.perf_features_count("matmul", "f32", 2048)[k] == 128
 
 
 def test_empty_counts(orc, L):
