@@ -21,8 +21,9 @@ Measurement set: the DG forward in FP32 for hexahedral orders p = 1..7
 launch shapes each,
 the five-point stencil at fourteen n in 1024..16384, square matmul at nineteen
 n in 512..8192, and empty kernels with 16..65536 work-groups (launch and
-work-group costs).  The fitted models use the linear form for the stencil and
-the overlap form for DG and matmul, as the paper does.
+work-group costs).  The paper's model forms are the defaults (linear for the
+stencil, overlap for DG and matmul); a family takes the linear form instead
+when its cross-validation error on the training rows is lower.
 20% of each family's variants are held out (seeded) and scored by MAPE and
 by the geometric mean of relative error.
 
