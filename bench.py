@@ -12,10 +12,20 @@ seven plain launches, with the model's predicted time; forward + adjoint at
 p = 4; the five-point stencil and matmul companions; and a live calibration
 of the performance model (held-out MAPE).
 
-Timing: HIP events on the launch stream over the timed steps (warm-up steps
-first); roofline positions use the algorithmic bytes and flops of one launch
+Timing: HIP events on the launch stream over the timed steps.  Before
+them every measurement runs its warm-up launches and then keeps launching for
+at least WARM_S seconds, whatever --warmup says: after idle the GPU clock
+needs about 20 ms of load to settle, and the numbers reported are the steady
+rate.  Roofline positions use the algorithmic bytes and flops of one launch
 and the MI355X peaks (HBM 8 TB/s, FP32 matrix 157.3 TFLOP/s, BF16 2.5
 PFLOP/s, FP8 5.0 PFLOP/s, FP64 78.6 TFLOP/s).
+
+Accuracy: every row keeps the GPU's outputs on a seeded sample of its
+elements (the first and last 64 and 2048 drawn at random; the headline keeps
+all of them), and the CPU-oracle leg at the end compares them with the FP64
+oracle on the same inputs ("err_vs_oracle": normwise max |y - y_ref| /
+max |y_ref|).  That leg is the only place this script calls the oracle; it
+also times it ("cpu_baseline").
 """
 from __future__ import annotations
 
@@ -37,6 +47,8 @@ METRIC = "DG-diff elems/s & %roofline, BF16/FP8/batched vs FP32; perf-model MAPE
 PEAK = {"hbm": 8000.0, "f32": 157.3, "f64": 78.6, "bf16": 2500.0, "fp8": 5000.0}
 KERNEL_SOURCES = ["paper_1904_09538_amd/csrc/dg_kernel.hpp",
                   "paper_1904_09538_amd/csrc/dg_forward.hip"]
+WARM_S = 0.1          # seconds of launches before any timed region
+SAMPLE_RANDOM = 2048  # elements drawn (seed 99) for the accuracy check of a row
 
 
 def log(*a):
@@ -64,13 +76,10 @@ def load_traffic(key: str, src_hash: str):
     return ent.get("hbm_bytes_per_launch")
 
 
-def timed(fn, steps, warmup, warm_s=0.04):
-    """Average seconds per call, HIP events on the current stream.
-
-    Warm-up runs at least `warmup` calls and at least `warm_s` seconds of
-    them: the first milliseconds of sustained load after idle run at a
-    transient clock (a few launches fast, then a dip, then a slow climb to
-    the steady rate), and the rows report the steady rate."""
+def warm(fn, warmup, warm_s=WARM_S):
+    """`warmup` calls, then more until at least warm_s seconds have passed: the
+    first milliseconds of sustained load after idle run at a transient clock
+    (a few launches fast, then a dip, then a slow climb to the steady rate)."""
     import torch
     for _ in range(warmup):
         fn()
@@ -80,6 +89,12 @@ def timed(fn, steps, warmup, warm_s=0.04):
         for _ in range(8):
             fn()
         torch.cuda.synchronize()
+
+
+def timed(fn, steps, warmup, warm_s=WARM_S):
+    """Average seconds per call, HIP events on the current stream, after warm()."""
+    import torch
+    warm(fn, warmup, warm_s)
     s = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -106,69 +121,141 @@ def dg_bytes_flops(E, n, in_bytes, out_bytes, nmat=3):
     return E * n * in_bytes + nmat * E * n * out_bytes + nmat * n * n * in_bytes, 2 * nmat * n * n * E
 
 
-# ------------------------------------------------------------------ rows
+def sample_elements(E, k=SAMPLE_RANDOM, seed=99):
+    """First and last 64 elements and k drawn at random (sorted, unique)."""
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([np.arange(min(64, E)), np.arange(max(0, E - 64), E),
+                                     rng.integers(0, E, k)])).astype(np.int64)
 
-def row_dg_orders(L, I, np, torch, steps):
+
+def gather_out(torch, o, sel):
+    """out[:, sel, :] of a [nmat][E][n] device tensor as FP64 [nsel][nmat][n] on the host."""
+    idx = torch.from_numpy(sel).to(o.device)
+    return o.index_select(1, idx).permute(1, 0, 2).double().cpu().numpy()
+
+
+# ------------------------------------------------------------------ rows
+# Each row returns its measurements and appends accuracy checks to `checks`:
+# dicts with the row's place ("at"), the kind of reference and the arrays the
+# CPU-oracle leg needs (inputs as FP64 values of what the GPU read, and the
+# GPU's outputs on the sample).
+
+def row_dg_orders(L, I, torch, steps, checks):
     out = {}
     for p in (2, 3, 4, 5):
         n, E = (p + 1) ** 3, 1 << 21
-        D = torch.from_numpy(I.gll_dmats(p)).float().cuda()
-        u = torch.from_numpy(I.uniform_u(E, n).astype(np.float32)).cuda()
+        D64 = I.gll_dmats(p).astype(np.float32).astype(np.float64)
+        u32 = I.uniform_u(E, n).astype(np.float32)
+        D = torch.from_numpy(D64).float().cuda()
+        u = torch.from_numpy(u32).cuda()
         o = torch.empty((3, E, n), device="cuda")
         t = timed(lambda: L.dgdiff_apply(D, u, out=o), steps, 2)
         b, f = dg_bytes_flops(E, n, 4, 4)
-        out[f"p{p}"] = {"nunit": n, "nelem": E, "ms": t * 1e3, "elements_per_s": E / t,
-                        "roofline": roofline(b, f, t, "f32")}
+        key = f"p{p}"
+        out[key] = {"nunit": n, "nelem": E, "ms": t * 1e3, "elements_per_s": E / t,
+                    "roofline": roofline(b, f, t, "f32")}
+        sel = sample_elements(E)
+        checks.append({"at": ("dg_fp32_orders_2e21", key), "kind": "dg", "D": D64,
+                       "u": u32[sel].astype(np.float64), "got": gather_out(torch, o, sel)})
         log(f"dg fp32 p={p}: {t * 1e3:.3f} ms")
-        del D, u, o
+        del D, u, o, u32
         torch.cuda.empty_cache()
     return out
 
 
-def row_lowp(L, I, np, torch, steps):
+def _codes_to_host(torch, q, sel=None):
+    """Raw codes of a BF16 / FP8 tensor (rows `sel` only, if given) as uint16 / uint8."""
+    bf = q.dtype == torch.bfloat16
+    raw = q.view(torch.int16 if bf else torch.uint8)
+    if sel is not None:
+        raw = raw.index_select(0, sel)
+    h = raw.cpu().numpy()
+    return h.view(np.uint16) if bf else h
+
+
+def row_lowp(L, I, torch, steps, checks):
     p, n, E = 5, 216, 1 << 20
-    D32 = I.gll_dmats(p).astype(np.float32)
-    u32 = torch.from_numpy(I.uniform_u(E, n).astype(np.float32)).cuda()
-    Dg = torch.from_numpy(D32).cuda()
+    D64 = I.gll_dmats(p).astype(np.float32).astype(np.float64)
+    u32h = I.uniform_u(E, n).astype(np.float32)
+    u32 = torch.from_numpy(u32h).cuda()
+    Dg = torch.from_numpy(D64).float().cuda()
     o = torch.empty((3, E, n), device="cuda")
+    sel = sample_elements(E)
+    usel = u32h[sel].astype(np.float64)
+    selg = torch.from_numpy(sel).cuda()
     res = {}
     t32 = timed(lambda: L.dgdiff_apply(Dg, u32, out=o), steps, 2)
     b, f = dg_bytes_flops(E, n, 4, 4)
     res["fp32"] = {"ms": t32 * 1e3, "elements_per_s": E / t32, "roofline": roofline(b, f, t32, "f32")}
-    ref = o.clone()
+    checks.append({"at": ("precision_p5_2e20", "fp32"), "kind": "dg", "D": D64, "u": usel,
+                   "got": gather_out(torch, o, sel)})
     for name, to, flags in (("bf16", "bf16", 0), ("fp8", "e4m3", 0), ("fp8_native", "e4m3", 2)):
         qD, isD = L.dgdiff_quantize(Dg.reshape(3, -1), to)
         qu, isu = L.dgdiff_quantize(u32, to)
         sc = dict(inv_sD=isD, inv_su=isu) if to == "e4m3" else {}
         tile = dict(flags=flags) if flags else None
         t = timed(lambda: L.dgdiff_apply(qD.view(3, n, n), qu, out=o, tile=tile, **sc), steps, 2)
+
+        # end to end: quantise the element data, then apply (the operator
+        # stack is quantised once per operator, outside the loop)
+        def e2e():
+            q, s = L.dgdiff_quantize(u32, to)
+            L.dgdiff_apply(qD.view(3, n, n), q, out=o, tile=tile,
+                           **(dict(inv_sD=isD, inv_su=s) if to == "e4m3" else {}))
+        te = timed(e2e, steps, 2)
         eb = 2 if to == "bf16" else 1
         b, f = dg_bytes_flops(E, n, eb, 4)
-        err = float(torch.linalg.vector_norm((o - ref).double()) / torch.linalg.vector_norm(ref.double()))
         res[name] = {"ms": t * 1e3, "elements_per_s": E / t, "speedup_vs_fp32": t32 / t,
-                     "normwise_rel_err_vs_fp32": err,
+                     "quantize_u_and_apply_ms": te * 1e3, "quantize_u_and_apply_speedup_vs_fp32": t32 / te,
                      "roofline": roofline(b, f, t, "bf16" if name != "fp8_native" else "fp8")}
-        log(f"dg {name} p=5 2^20: {t * 1e3:.3f} ms ({t32 / t:.2f}x fp32)")
+        # the last e2e call wrote o with freshly quantised (identical) codes
+        checks.append({"at": ("precision_p5_2e20", name), "kind": "dg_lowp", "fmt": to, "D": D64,
+                       "u": usel, "qD": _codes_to_host(torch, qD).reshape(3, n, n),
+                       "qu": _codes_to_host(torch, qu, selg),
+                       "isD": isD.cpu().numpy().astype(np.float64) if to == "e4m3" else None,
+                       "isu": isu.index_select(0, selg).cpu().numpy().astype(np.float64)
+                       if to == "e4m3" else None,
+                       "got": gather_out(torch, o, sel)})
+        log(f"dg {name} p=5 2^20: {t * 1e3:.3f} ms ({t32 / t:.2f}x fp32); "
+            f"quantise+apply {te * 1e3:.3f} ms ({t32 / te:.2f}x)")
+        del qD, qu, isD, isu
     # the quantiser itself (element data, per-element power-of-two scales)
     tq = timed(lambda: L.dgdiff_quantize(u32, "e4m3"), steps, 2)
-    res["quantize_u_fp8"] = {"ms": tq * 1e3, "GB_per_s": E * n * (4 + 1) / tq / 1e9,
+    res["quantize_u_fp8"] = {"ms": tq * 1e3, "GB_per_s": (E * n * (4 + 1) + E * 4) / tq / 1e9,
                              "roofline": roofline(E * n * 5 + E * 4, 0, tq, "f32")}
-    del u32, o, ref
+    qu, isu = L.dgdiff_quantize(u32, "e4m3")
+    checks.append({"at": ("precision_p5_2e20", "quantize_u_fp8"), "kind": "quant", "x": u32h[sel],
+                   "q": _codes_to_host(torch, qu, selg),
+                   "inv": isu.index_select(0, selg).cpu().numpy()})
+    del u32, o, qu, isu
     torch.cuda.empty_cache()
     return {"config": "hex p=5, 2^20 elements, FP32 output and accumulation", **res}
 
 
-def row_batched(L, I, np, torch, steps, model):
+def row_batched(L, I, torch, steps, model, checks):
     E = 1 << 20
     order = I.batched_orders(E)
     off = I.batched_offsets(order)
     total = int(off[-1])
-    u = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, total).astype(np.float32)).cuda()
-    Ds = {p: torch.from_numpy(I.gll_dmats(p).astype(np.float32)).cuda() for p in range(1, 8)}
+    uh = np.random.default_rng(0).uniform(-1, 1, total).astype(np.float32)
+    u = torch.from_numpy(uh).cuda()
+    Dh = {p: I.gll_dmats(p).astype(np.float32) for p in range(1, 8)}
+    Ds = {p: torch.from_numpy(Dh[p]).cuda() for p in range(1, 8)}
     plan = L.BatchedPlan(order, model=model)
     o = torch.empty((3, total), device="cuda")
     tb = timed(lambda: plan.apply(Ds, u, out=o), steps, 2)
     pred = sum(plan.info(p)["predicted_s"] for p in range(1, 8))
+    sel = sample_elements(E)
+    for p in range(1, 8):
+        sp = sel[order[sel] == p]
+        if sp.size == 0:
+            continue
+        n = (p + 1) ** 3
+        rows = (off[sp][:, None] + np.arange(n)[None, :]).reshape(-1)
+        got = o[:, torch.from_numpy(rows).cuda()].view(3, sp.size, n).permute(1, 0, 2).double().cpu().numpy()
+        checks.append({"at": ("batched_mixed_p1_7_2e20", f"order{p}"), "kind": "dg",
+                       "D": Dh[p].astype(np.float64), "u": uh[rows].reshape(sp.size, n).astype(np.float64),
+                       "got": got})
     # baseline: seven plain launches on pre-grouped copies (grouping not timed)
     groups = {}
     for p in range(1, 8):
@@ -200,40 +287,65 @@ def row_batched(L, I, np, torch, steps, model):
     return res
 
 
-def row_adjoint(L, I, np, torch, steps):
+def row_adjoint(L, I, torch, steps, checks):
     p, n, E = 4, 125, 1 << 19
-    D = torch.from_numpy(I.gll_dmats(p).astype(np.float32)).cuda()
-    u = torch.from_numpy(I.uniform_u(E, n).astype(np.float32)).cuda()
-    g = torch.from_numpy(I.normal_g(3, E, n).astype(np.float32)).cuda()
+    D64 = I.gll_dmats(p).astype(np.float32).astype(np.float64)
+    u32 = I.uniform_u(E, n).astype(np.float32)
+    g32 = I.normal_g(3, E, n).astype(np.float32)
+    D = torch.from_numpy(D64).float().cuda()
+    u = torch.from_numpy(u32).cuda()
+    g = torch.from_numpy(g32).cuda()
     o = torch.empty((3, E, n), device="cuda")
     tf = timed(lambda: L.dgdiff_apply(D, u, out=o), steps, 2)
     tbw = timed(lambda: L.dgdiff_backward(D, u, g), steps, 2)
+    gu, gD = L.dgdiff_backward(D, u, g)
+    sel = sample_elements(E)
+    rng = np.random.default_rng(98)
+    ent = (rng.integers(0, 3, 256), rng.integers(0, n, 256), rng.integers(0, n, 256))
+    checks.append({"at": ("adjoint_p4_2e19", "forward"), "kind": "dg", "D": D64,
+                   "u": u32[sel].astype(np.float64), "got": gather_out(torch, o, sel)})
+    checks.append({"at": ("adjoint_p4_2e19", "grad_u"), "kind": "grad_u", "D": D64,
+                   "g": g32[:, sel, :].astype(np.float64),
+                   "got": gu.index_select(0, torch.from_numpy(sel).cuda()).double().cpu().numpy()})
+    checks.append({"at": ("adjoint_p4_2e19", "grad_D"), "kind": "grad_D", "u": u32, "g": g32, "ent": ent,
+                   "got": gD.double().cpu().numpy()[ent]})
     flops_f = 2 * 3 * n * n * E
     res = {"config": "hex p=4, 2^19 elements, FP32", "forward_ms": tf * 1e3, "backward_ms": tbw * 1e3,
            "forward_roofline": roofline(E * n * 16, flops_f, tf, "f32"),
            "backward_roofline": roofline(E * n * 4 * 5, 2 * flops_f, tbw, "f32")}
     log(f"adjoint p=4: fwd {tf * 1e3:.3f} ms, bwd {tbw * 1e3:.3f} ms")
-    del D, u, g, o
+    del D, u, g, o, gu, gD
     torch.cuda.empty_cache()
     return res
 
 
-def row_companions(L, I, np, torch, steps):
+def row_companions(L, I, torch, steps, checks):
     n = 16384
+    grid = I.stencil_grid(n).astype(np.float32)
     ug = torch.zeros((n + 2, n + 64), device="cuda")
-    ug[:, :n + 2] = torch.from_numpy(I.stencil_grid(n).astype(np.float32)).cuda()
+    ug[:, :n + 2] = torch.from_numpy(grid).cuda()
     r = torch.empty((n, n), device="cuda")
     ts = timed(lambda: L.stencil5_apply(ug, res=r, n=n), steps, 2)
     st = {"n": n, "ms": ts * 1e3, "points_per_s": n * n / ts,
           "roofline": roofline(((n + 2) ** 2 + n * n) * 4, 5 * n * n, ts, "f32")}
+    rng = np.random.default_rng(97)
+    ii = np.concatenate([[0, 0, n - 1, n - 1], rng.integers(0, n, 4092)])
+    jj = np.concatenate([[0, n - 1, 0, n - 1], rng.integers(0, n, 4092)])
+    checks.append({"at": ("stencil5",), "kind": "stencil", "u": grid, "ii": ii, "jj": jj,
+                   "got": r[torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()].double().cpu().numpy()})
     del ug, r
     m = 8192
     a, b = I.matmul_operands(m)
-    a = torch.from_numpy(a.astype(np.float32)).cuda()
-    b = torch.from_numpy(b.astype(np.float32)).cuda()
+    a32, b32 = a.astype(np.float32), b.astype(np.float32)
+    a = torch.from_numpy(a32).cuda()
+    b = torch.from_numpy(b32).cuda()
     c = torch.empty((m, m), device="cuda")
     tm = timed(lambda: L.matmul_apply(a, b, c), max(3, steps // 5), 1)
     mm = {"n": m, "ms": tm * 1e3, "roofline": roofline(12 * m * m, 2 * m ** 3, tm, "f32")}
+    ii = np.concatenate([[0, 0, m - 1, m - 1], rng.integers(0, m, 1020)])
+    jj = np.concatenate([[0, m - 1, 0, m - 1], rng.integers(0, m, 1020)])
+    checks.append({"at": ("matmul",), "kind": "matmul", "a": a32, "b": b32, "ii": ii, "jj": jj,
+                   "got": c[torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()].double().cpu().numpy()})
     log(f"stencil n={n}: {ts * 1e3:.3f} ms; matmul n={m}: {tm * 1e3:.3f} ms")
     del a, b, c
     torch.cuda.empty_cache()
@@ -243,7 +355,7 @@ def row_companions(L, I, np, torch, steps):
 def achievable_hbm(torch):
     """Measured reference rates of this GPU's memory system: a plain 1 GiB fill
     (write only) and a 1 GiB device-to-device copy (read + write), steady
-    state (40 ms warm-up), GB/s."""
+    state, GB/s."""
     src = torch.ones(1 << 28, device="cuda")
     dst = torch.empty_like(src)
     tf = timed(lambda: dst.fill_(2.0), 20, 2)
@@ -293,16 +405,69 @@ def model_vector(summary, names):
     return {"cost": cost, "group": group, "edge": f["edge"]}
 
 
-def cpu_baseline(D64, u64, nsample):
-    """The FP64 C oracle (single-threaded) on the first nsample elements."""
+# ------------------------------------------------------------------ CPU-oracle leg
+
+def _err(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = float(np.max(np.abs(ref))) if ref.size else 0.0
+    num = float(np.max(np.abs(got - ref))) if ref.size else 0.0
+    return num / den if den else num
+
+
+def oracle_leg(D64, u64, nsample, headline_out, checks, rows):
+    """The only use of the FP64 C oracle here: time it on the headline workload
+    (single-threaded, the first nsample elements) and compare the headline's
+    outputs on those elements and every row's sampled outputs with it."""
     import oracle
     us = np.ascontiguousarray(u64[:nsample])
     t0 = time.perf_counter()
-    oracle.dg_forward(D64, us)
+    ref = oracle.dg_forward(D64, us)
     dt = time.perf_counter() - t0
-    return {"value": nsample / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {nsample} of the {u64.shape[0]} elements, FP64 single-threaded C "
-                      f"oracle, {dt:.1f} s"}
+    cpu = {"value": nsample / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {nsample} of the {u64.shape[0]} elements, FP64 single-threaded C "
+                     f"oracle, {dt:.1f} s"}
+    head_err = _err(headline_out, ref) if headline_out is not None else None
+    del ref
+    for c in checks:
+        k = c["kind"]
+        e = {}
+        if k == "dg":
+            ref = oracle.dg_forward(c["D"], c["u"]).transpose(1, 0, 2)
+            e["err_vs_oracle"] = _err(c["got"], ref)
+        elif k == "dg_lowp":
+            ref = oracle.dg_forward(c["D"], c["u"]).transpose(1, 0, 2)
+            e["err_vs_oracle"] = _err(c["got"], ref)     # method: vs the unquantised FP32 inputs
+            if c["fmt"] == "bf16":
+                Dq = oracle.bf16_decode_array(c["qD"]).astype(np.float64)
+                uq = oracle.bf16_decode_array(c["qu"]).astype(np.float64)
+            else:
+                Dq = oracle.e4m3_decode_array(c["qD"]) * c["isD"][:, None, None]
+                uq = oracle.e4m3_decode_array(c["qu"]) * c["isu"][:, None]
+            refq = oracle.dg_forward(Dq, uq).transpose(1, 0, 2)
+            e["err_vs_oracle_dequantised"] = _err(c["got"], refq)   # kernel alone
+        elif k == "quant":
+            q, inv = oracle.quantize(c["x"], "e4m3", per_row=True)
+            e["codes_equal_oracle"] = bool(np.array_equal(q, c["q"]) and np.array_equal(inv, c["inv"]))
+        elif k == "grad_u":
+            gu, _ = oracle.dg_adjoint(c["D"], np.zeros((c["g"].shape[1], c["D"].shape[1])), c["g"],
+                                      want_u=True, want_D=False)
+            e["err_vs_oracle"] = _err(c["got"], gu)
+        elif k == "grad_D":
+            mm, ii, jj = c["ent"]
+            ref = oracle.dg_adjoint_D_select(c["u"], c["g"], mm, ii, jj)
+            e["err_vs_oracle_sampled_entries"] = _err(c["got"], ref)
+        elif k == "stencil":
+            e["err_vs_oracle"] = _err(c["got"], oracle.stencil5_select(c["u"], c["ii"], c["jj"]))
+        elif k == "matmul":
+            e["err_vs_oracle"] = _err(c["got"], oracle.matmul_select(c["a"], c["b"], c["ii"], c["jj"]))
+        node = rows
+        for key in c["at"]:
+            node = node[key]
+        node.update(e)
+        node["oracle_sample"] = ("first/last 64 + 2048 seeded elements" if k in ("dg", "dg_lowp", "grad_u", "quant")
+                                 else "256 seeded entries" if k == "grad_D" else "4096/1024 seeded points")
+    return cpu, head_err
 
 
 def main():
@@ -314,7 +479,7 @@ def main():
                     help="comma list of extra rows (orders,lowp,batched,adjoint,companions,model) "
                          "or 'all' or 'none'")
     ap.add_argument("--cpu-baseline", type=int, default=1 << 21,
-                    help="elements of the workload the CPU oracle runs on (0: skip)")
+                    help="elements of the workload the CPU oracle runs on (0: skip the oracle leg)")
     ap.add_argument("--calib-out", default=os.path.join(tempfile.gettempdir(), "dgdiff_bench_calibration.jsonl"),
                     help="where the model row writes its calibration measurements (JSON lines)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -326,7 +491,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1904_09538_amd import _lib as L, inputs as I
@@ -344,21 +508,20 @@ def main():
     p, E, nmat = 3, 1 << 21, 3
     n = I.nunit_of_order(p)
     log(f"headline: DG FP32 p={p} nunit={n} nelem={E}")
-    D64 = I.gll_dmats(p)
-    u64 = I.uniform_u(E, n)
+    D64 = I.gll_dmats(p).astype(np.float32).astype(np.float64)
+    u32 = I.uniform_u(E, n).astype(np.float32)
     D = torch.from_numpy(D64).float().to(dev)
-    u = torch.from_numpy(u64.astype(np.float32)).to(dev)
+    u = torch.from_numpy(u32).to(dev)
     out = torch.empty((nmat, E, n), device=dev)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        L.dgdiff_apply(D, u, out=out, stream=stream)
-    torch.cuda.synchronize()
+    step = lambda: L.dgdiff_apply(D, u, out=out, stream=stream)  # noqa: E731
+    warm(step, args.warmup)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        L.dgdiff_apply(D, u, out=out, stream=stream)
+        step()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -369,10 +532,12 @@ def main():
     roof["traffic"] = load_traffic("dg_kernel_f32:dg_fp32_p3_2e21", src_hash)
     roof["kernel"] = "dg_kernel<float,16,1,1,false,true> (paired stores)"
     log(f"headline: {t * 1e3:.3f} ms/step, {E / t:.3e} elements/s")
+    nsample = min(args.cpu_baseline, E)
+    head_out = out[:, :nsample, :].double().cpu().numpy() if nsample else None
     del D, u, out
     torch.cuda.empty_cache()
 
-    rows = {}
+    rows, checks = {}, []
     want = ["orders", "lowp", "batched", "adjoint", "companions", "model"] if args.rows == "all" else \
         ([] if args.rows == "none" else args.rows.split(","))
     small = max(5, args.steps // 5)
@@ -382,16 +547,16 @@ def main():
         model_summary, rows["model"] = row_model(args.calib_out)
         log(f"model: held-out MAPE {100 * rows['model']['mape_heldout_all']:.1f}%")
     if "orders" in want:
-        rows["dg_fp32_orders_2e21"] = row_dg_orders(L, I, np, torch, small)
+        rows["dg_fp32_orders_2e21"] = row_dg_orders(L, I, torch, small, checks)
     if "lowp" in want:
-        rows["precision_p5_2e20"] = row_lowp(L, I, np, torch, small)
+        rows["precision_p5_2e20"] = row_lowp(L, I, torch, small, checks)
     if "batched" in want:
         mv = model_vector(model_summary, L.feature_names()) if model_summary else None
-        rows["batched_mixed_p1_7_2e20"] = row_batched(L, I, np, torch, small, mv)
+        rows["batched_mixed_p1_7_2e20"] = row_batched(L, I, torch, small, mv, checks)
     if "adjoint" in want:
-        rows["adjoint_p4_2e19"] = row_adjoint(L, I, np, torch, small)
+        rows["adjoint_p4_2e19"] = row_adjoint(L, I, torch, small, checks)
     if "companions" in want:
-        rows.update(row_companions(L, I, np, torch, small))
+        rows.update(row_companions(L, I, torch, small, checks))
 
     # the roofline against measured achievable rates beside the spec peaks:
     # the FP32 matrix rate the matmul row reaches, the fill and copy rates
@@ -402,11 +567,10 @@ def main():
         roof["frac_vs_achievable"] = roof["achieved"] / mm["roofline"]["achieved"]
     log(f"achievable: fill {ach['fill_GBps']:.0f} GB/s, copy {ach['copy_GBps']:.0f} GB/s")
 
-    cpu = None
-    if args.cpu_baseline:
-        log(f"cpu baseline: FP64 oracle on {min(args.cpu_baseline, E)} elements")
-        cpu = cpu_baseline(D64.astype(np.float32).astype(np.float64),
-                           u64.astype(np.float32).astype(np.float64), min(args.cpu_baseline, E))
+    cpu, head_err = None, None
+    if nsample:
+        log(f"cpu-oracle leg: FP64 oracle on {nsample} headline elements and {len(checks)} row samples")
+        cpu, head_err = oracle_leg(D64, u32.astype(np.float64), nsample, head_out, checks, rows)
 
     rec = {
         "metric": METRIC, "value": E / t, "unit": "elements/s", "n_gpus": 1,
@@ -417,10 +581,13 @@ def main():
                                f"operators, {E} elements, u~U(-1,1) seed 0",
                    "nelem": E, "nunit": n, "nmat": nmat},
         "roofline": roof,
+        "err_vs_oracle": head_err,
+        "err_vs_oracle_sample": f"first {nsample} elements (normwise, FP64 oracle)" if nsample else None,
         "achievable": ach,
         "cpu_baseline": cpu,
         "rows": rows,
         "wall_s_timed": wall,
+        "warm_s": WARM_S,
         "kernel_source_hash": src_hash,
     }
     print(json.dumps(rec), flush=True)

@@ -65,6 +65,15 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
         KP = 4 * KQ;
         V = (int)(16 / sz);
     }
+    /* launch shapes the library documents as unavailable: an element tile
+       of 64 per wave needs the wave's element fragments within 128 bytes per
+       lane (FP32 nunit <= 128, FP64 nunit <= 64; low precision nunit <= 256),
+       waves per work-group 1..8, and the staged operator panels (plus a wave
+       slab) within the 160 KB LDS */
+    if (waves < 1 || waves > 8) return 1;
+    if (epw != 16 && epw != 32 && epw != 64) return 1;
+    if (epw == 64 && (lowp ? KS > 8 : KQ * sz > 128)) return 1;
+    if (lowp && KS > 16) return 1;
     const int mblk = (int)cdiv(n, 16);
     const int P = M * mblk;
     const int ppg = (int)mini(d_panels, P);
@@ -82,6 +91,11 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
         int64_t panel_bytes = 16 * (4LL * KQ + V) * sz;
         int64_t slab = (int64_t)waves * cdiv(16LL * cb * n, V) * V * sz;
         use_slab = slab + panel_bytes <= 80 * 1024;
+    }
+    {
+        const int64_t panel = lowp ? 16 * (32LL * KS * el + 16) : 16 * (4LL * KQ + V) * sz;
+        const int64_t slab = use_slab ? (int64_t)waves * cdiv(16LL * cb * n, V) * V * sz : 0;
+        if (ppg * panel + slab > 160 * 1024) return 1;
     }
     const int vec_out = n % 4 == 0;
     /* unaligned rows that come through the wave slab leave through it too */

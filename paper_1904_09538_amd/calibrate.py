@@ -9,10 +9,13 @@ unconstrained, as in the paper; a second fit with non-negative weights (the
 paper's interpretability criterion) is reported beside it.
 
 Timing protocol (the paper's wall-time feature): warm-up launches, then 60
-timed trials, each bracketed by HIP events on the launch stream (host-device
-transfer excluded).  Between trials a 512 MB scratch buffer is rewritten so
-that inputs do not stay resident in the 256 MB last-level cache ("cold"
-protocol).  Samples above 10x the median are dropped (the paper drops
+timed trials for every variant, each bracketed by HIP events on the launch
+stream (host-device transfer excluded).  Before each trial a 512 MB scratch
+buffer is rewritten on the same stream, so that inputs do not stay resident
+in the 256 MB last-level cache ("cold" protocol) and so that the first event
+is queued behind GPU work: the pair then measures GPU time, never the host's
+launch latency (this matters for the empty kernels, whose run time is a few
+microseconds).  Samples above 10x the median are dropped (the paper drops
 occasional ~10x anomalies seen on AMD hardware); the model input is the mean
 of the kept samples.
 
@@ -195,13 +198,14 @@ def measure(path, quick=False, trials=60, families=("dg", "stencil", "matmul", "
             a = torch.from_numpy(a.astype(np.float32)).to(dev)
             b = torch.from_numpy(b.astype(np.float32)).to(dev)
             c = torch.empty((n, n), device=dev)
-            tm = time_launch(lambda: _lib.matmul_apply(a, b, c), trials if n < 8192 else 20,
-                             flush=flush)
+            tm = time_launch(lambda: _lib.matmul_apply(a, b, c), trials, flush=flush)
             emit({**v, "t": tm, "features": _lib.perf_features_count("matmul", "f32", n, num_cu=num_cu).tolist()})
             del a, b, c
     if "empty" in families:
         for v in empty_variants(quick):
-            tm = time_launch(lambda: _lib.dg_empty_launch(v["wgs"]), trials, flush=None)
+            # the flush is queued ahead of the first event here too: the event
+            # pair then brackets GPU time only, not the host's launch latency
+            tm = time_launch(lambda: _lib.dg_empty_launch(v["wgs"]), trials, flush=flush)
             emit({**v, "t": tm, "features": _lib.perf_features_count("empty", "f32", v["wgs"]).tolist()})
     meta = {"meta": True, "device": torch.cuda.get_device_name(0), "num_cu": num_cu,
             "feature_names": _lib.feature_names(), "trials": trials, "protocol": "cold",

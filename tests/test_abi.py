@@ -16,6 +16,7 @@ def _declared_functions():
         text = open(h).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"^\s*#[^\n]*", "", text, flags=re.M)   # preprocessor lines
         text = re.sub(r"typedef[^;]*;", "", text, flags=re.S)
         for m in re.finditer(r"\b([A-Za-z_]\w*)\s*\(", text):
             name = m.group(1)

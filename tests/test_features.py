@@ -55,9 +55,16 @@ def test_dg_counts_match_brute_force(orc, L, case):
     try:
         got = L.perf_features_count("dg", dtype, E, nunit, nmat, tile, num_cu=256)
     except L.DGError:
-        pytest.skip("launch shape not available for this problem (rejected by the library)")
-    ref = orc.features("dg", dtype, E, nunit, nmat, epw, waves, per_cu, ppg, flags, 256)
-    np.testing.assert_array_equal(got, ref)
+        got = None
+    try:
+        ref = orc.features("dg", dtype, E, nunit, nmat, epw, waves, per_cu, ppg, flags, 256)
+    except ValueError:
+        ref = None
+    # a shape the library documents as unavailable (element tile of 64 with
+    # large rows, operator panels beyond the LDS) is refused by both sides
+    assert (got is None) == (ref is None), (got is None, ref is None)
+    if got is not None:
+        np.testing.assert_array_equal(got, ref)
 
 
 @pytest.mark.parametrize("dtype,n", list(itertools.product(["f32"], [4, 8, 100, 1000, 1024, 2048, 4096,

@@ -142,7 +142,8 @@ def test_autograd_function_and_gradcheck(orc, ops):
 
 def test_full_size_fp32_p4(orc, ops):
     """Forward + backward through the autograd Function at hex p=4, 2^19
-    elements, FP32, g ~ N(0,1); grad_u and grad_D checked on samples."""
+    elements, FP32, g ~ N(0,1): all of grad_u and all 46,875 entries of
+    grad_D against the FP64 oracle adjoint."""
     from paper_1904_09538_amd.autograd import DGDiffFn
     n, E = 125, 1 << 19
     D32 = I.gll_dmats(4).astype(np.float32)
@@ -153,17 +154,10 @@ def test_full_size_fp32_p4(orc, ops):
     out = DGDiffFn.apply(D, u)
     out.backward(torch.from_numpy(g32).cuda())
     torch.cuda.synchronize()
-    rng = np.random.default_rng(41)
-    sel = np.unique(np.concatenate([np.arange(16), np.arange(E - 16, E), rng.integers(0, E, 256)]))
-    ru, _ = orc.dg_adjoint(D32.astype(np.float64), u32[sel].astype(np.float64),
-                           g32[:, sel, :].astype(np.float64), want_D=False)
-    assert normwise_rel(u.grad[torch.from_numpy(sel).cuda()].double().cpu().numpy(), ru) <= 1e-5
-    mm = rng.integers(0, 3, 96)
-    ii = rng.integers(0, n, 96)
-    jj = rng.integers(0, n, 96)
-    rD = orc.dg_adjoint_D_select(u32.astype(np.float64), g32.astype(np.float64), mm, ii, jj)
-    gD = D.grad.double().cpu().numpy()[mm, ii, jj]
-    assert normwise_rel(gD, rD) <= 1e-5
+    # every entry of grad_u and of grad_D against the oracle adjoint
+    ru, rD = orc.dg_adjoint(D32.astype(np.float64), u32.astype(np.float64), g32.astype(np.float64))
+    assert normwise_rel(u.grad.double().cpu().numpy(), ru) <= 1e-5
+    assert normwise_rel(D.grad.double().cpu().numpy(), rD) <= 1e-5
 
 
 def test_backward_deterministic(ops):

@@ -36,6 +36,22 @@ def _as(x, dtype):
     return x.astype(np.float32).astype(np.float64) if dtype == torch.float32 else x
 
 
+def _epw64_unavailable(dtype, nunit):
+    """The documented limit of an element tile of 64 per wave: nunit <= 128 in
+    FP32, nunit <= 64 in FP64 (the wave's element fragments in registers)."""
+    return nunit > (128 if dtype == torch.float32 else 64)
+
+
+def _check_or_refused(orc, ops, D, u, dtype, tile):
+    """Shapes the header documents as unavailable raise DGError; every other
+    shape runs and matches the oracle."""
+    if tile and tile.get("elems_per_wave") == 64 and _epw64_unavailable(dtype, u.shape[1]):
+        with pytest.raises(ops.DGError):
+            _run(ops, _as(D, dtype), _as(u, dtype), dtype, tile)
+        return
+    _check(orc, ops, D, u, dtype, tile=tile)
+
+
 def _check(orc, ops, D, u, dtype, tile=None):
     D, u = _as(D, dtype), _as(u, dtype)
     got = _run(ops, D, u, dtype, tile)
@@ -98,10 +114,7 @@ def test_unaligned_rows_staged_stores(orc, ops, dtype, nunit, tile):
     D = I.random_dmats(nunit)
     for nelem in (1, 63, 1001):
         u = I.uniform_u(nelem, nunit)
-        try:
-            _check(orc, ops, D, u, dtype, tile=tile)
-        except ops.DGError:
-            pytest.skip("launch shape not available for this problem")
+        _check_or_refused(orc, ops, D, u, dtype, tile)
 
 
 @pytest.mark.parametrize("nunit", [32, 64, 96, 512])
@@ -115,10 +128,7 @@ def test_paired_stores(orc, ops, nunit, tile):
     D = I.random_dmats(nunit)
     for nelem in (1, 9, 23, 1001):
         u = I.uniform_u(nelem, nunit)
-        try:
-            _check(orc, ops, D, u, torch.float32, tile=tile)
-        except ops.DGError:
-            pytest.skip("launch shape not available for this problem")
+        _check_or_refused(orc, ops, D, u, torch.float32, tile)
 
 
 @pytest.mark.parametrize("nunit", [64, 512])
@@ -233,18 +243,35 @@ def test_empty_is_noop(ops):
     assert out.shape == (3, 0, 64)
 
 
-@pytest.mark.parametrize("nunit,nelem", [(64, 1 << 21), (216, 1 << 20)])
-def test_full_size_sampled(orc, ops, nunit, nelem):
-    """Full-size launch (the benchmark's configuration), checked on a seeded
-    sample of elements including the first and last 64."""
-    p = round(nunit ** (1 / 3)) - 1
-    D = _as(I.gll_dmats(p), torch.float32)
+def test_full_size_p3_every_element(orc, ops):
+    """The benchmark's headline launch (hex p=3, 2^21 elements, GLL operators,
+    FP32): every output against the FP64 oracle."""
+    nunit, nelem = 64, 1 << 21
+    D = _as(I.gll_dmats(3), torch.float32)
     u32 = np.asarray(I.uniform_u(nelem, nunit), dtype=np.float32)
+    print(f"full size: FP32 nunit={nunit} nelem={nelem}, all outputs", flush=True)
     out = ops.dgdiff_apply(_dev(D, torch.float32), torch.from_numpy(u32).cuda())
     torch.cuda.synchronize()
-    rng = np.random.default_rng(99)
-    sel = np.unique(np.concatenate([np.arange(64), np.arange(nelem - 64, nelem),
-                                    rng.integers(0, nelem, 1024)]))
+    got = out.double().cpu().numpy()
+    del out
+    ref = orc.dg_forward(D, u32.astype(np.float64))
+    from oracle.metrics import normwise_rel
+    assert normwise_rel(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("p,nelem", [(2, 1 << 21), (4, 1 << 21), (5, 1 << 21), (5, 1 << 20)])
+def test_full_size_every_wave_tile(orc, ops, p, nelem):
+    """The benchmark's other FP32 launches at full size: one element from
+    every 16-element wave-tile and the whole first and last 512 elements
+    against the FP64 oracle."""
+    from sample_sets import every_tile
+    nunit = (p + 1) ** 3
+    D = _as(I.gll_dmats(p), torch.float32)
+    u32 = np.asarray(I.uniform_u(nelem, nunit), dtype=np.float32)
+    print(f"full size: FP32 nunit={nunit} nelem={nelem}, every wave-tile", flush=True)
+    out = ops.dgdiff_apply(_dev(D, torch.float32), torch.from_numpy(u32).cuda())
+    torch.cuda.synchronize()
+    sel = every_tile(nelem, seed=p)
     ref = orc.dg_forward_select(D, u32.astype(np.float64), sel)        # [nsel][3][n]
     got = out[:, torch.from_numpy(sel).cuda(), :].permute(1, 0, 2).double().cpu().numpy()
     from oracle.metrics import normwise_rel

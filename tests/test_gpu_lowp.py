@@ -123,17 +123,42 @@ def test_lowp_random_operators(orc, ops, to):
     assert k_err <= 1.0 and m_err <= TOL_METHOD[to]
 
 
-@pytest.mark.parametrize("tile", [dict(elems_per_wave=16), dict(elems_per_wave=64),
-                                  dict(d_panels=5), dict(waves=2)])
-def test_lowp_tiles(orc, ops, tile):
-    D32 = I.gll_dmats(3).astype(np.float32)
-    u32 = I.uniform_u(333, 64).astype(np.float32)
-    qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), "e4m3")
-    qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), "e4m3")
-    ref = ops.dgdiff_apply(qD.view(3, 64, 64), qu, inv_sD=isD, inv_su=isu)
-    got = ops.dgdiff_apply(qD.view(3, 64, 64), qu, inv_sD=isD, inv_su=isu, tile=tile)
-    torch.cuda.synchronize()
-    assert normwise_rel(got.double().cpu().numpy(), ref.double().cpu().numpy()) <= 1e-6
+def _oracle_dequantised(orc, D32, u32, to):
+    """The oracle's own quantisation and decoding of the FP32 inputs."""
+    nmat, n, _ = D32.shape
+    qDo, isDo = orc.quantize(D32.reshape(nmat, -1), to, True)
+    quo, isuo = orc.quantize(u32, to, True)
+    if to == "bf16":
+        Dd = orc.bf16_decode_array(qDo).astype(np.float64).reshape(nmat, n, n)
+        ud = orc.bf16_decode_array(quo).astype(np.float64)
+    else:
+        Dd = (orc.e4m3_decode_array(qDo) * isDo[:, None]).reshape(nmat, n, n)
+        ud = orc.e4m3_decode_array(quo) * isuo[:, None]
+    return Dd, ud
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+@pytest.mark.parametrize("nunit", [64, 216])
+@pytest.mark.parametrize("tile", [dict(elems_per_wave=16), dict(elems_per_wave=32),
+                                  dict(elems_per_wave=64), dict(d_panels=5), dict(d_panels=1),
+                                  dict(waves=2), dict(waves=3, elems_per_wave=32),
+                                  dict(groups_per_cu=1)])
+def test_lowp_tiles(orc, ops, to, nunit, tile):
+    """Launch shapes of the low-precision forward against the FP64 oracle on
+    the oracle's dequantised inputs (the FP32 accumulation bound), ragged
+    element counts."""
+    p = round(nunit ** (1 / 3)) - 1
+    D32 = I.gll_dmats(p).astype(np.float32)
+    for nelem in (1, 333):
+        u32 = I.uniform_u(nelem, nunit).astype(np.float32)
+        qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), to)
+        qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), to)
+        sc = dict(inv_sD=isD, inv_su=isu) if to == "e4m3" else {}
+        got = ops.dgdiff_apply(qD.view(3, nunit, nunit), qu, tile=tile, **sc)
+        torch.cuda.synchronize()
+        Dd, ud = _oracle_dequantised(orc, D32, u32, to)
+        err = _dot_scaled(orc, got.double().cpu().numpy(), orc.dg_forward(Dd, ud), Dd, ud)
+        assert err <= nunit * 2.0 ** -23, (nelem, err)
 
 
 @pytest.mark.parametrize("to", ["bf16", "e4m3"])
@@ -191,8 +216,10 @@ def test_fp8_requires_scales(ops):
 @pytest.mark.parametrize("p,E", [(5, 1 << 20), (3, 1 << 21)])
 def test_lowp_full_size_sampled(orc, ops, to, p, E):
     """Hex p=5, 2^20 elements (the low-precision benchmark configuration) and
-    hex p=3, 2^21 (paired stores): sampled outputs, and the sampled rows'
-    quantiser codes and scales bit-equal to the oracle's."""
+    hex p=3, 2^21 (paired stores): one element of every 16-element wave-tile
+    and the whole first and last 512, and the sampled rows' quantiser codes
+    and scales bit-equal to the oracle's."""
+    print(f"full size: {to} p={p} nelem={E}", flush=True)
     n = (p + 1) ** 3
     D32 = I.gll_dmats(p).astype(np.float32)
     u32 = np.asarray(I.uniform_u(E, n), dtype=np.float32)
@@ -201,8 +228,8 @@ def test_lowp_full_size_sampled(orc, ops, to, p, E):
     out = ops.dgdiff_apply(qD.view(3, n, n), qu, inv_sD=isD if to == "e4m3" else None,
                            inv_su=isu if to == "e4m3" else None)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(31)
-    sel = np.unique(np.concatenate([np.arange(32), np.arange(E - 32, E), rng.integers(0, E, 512)]))
+    from sample_sets import every_tile
+    sel = every_tile(E, seed=31)
     got = out[:, torch.from_numpy(sel).cuda(), :].permute(1, 0, 2).double().cpu().numpy()
     us = u32[sel]
     qDo, isDo = orc.quantize(D32.reshape(3, -1), to, True)
