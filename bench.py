@@ -244,7 +244,11 @@ def row_batched(L, I, torch, steps, model, checks):
     plan = L.BatchedPlan(order, model=model)
     o = torch.empty((3, total), device="cuda")
     tb = timed(lambda: plan.apply(Ds, u, out=o), steps, 2)
-    pred = sum(plan.info(p)["predicted_s"] for p in range(1, 8))
+    # the model's prediction of the launch that ran: the counted features of
+    # every order's share (its body, its work-groups) under the batched model
+    info = {p: plan.info(p) for p in range(1, 8)}
+    feats = L.batched_counts(info, torch.cuda.get_device_properties(0).multi_processor_count)
+    pred = model_predict(model, feats) if model else None
     sel = sample_elements(E)
     for p in range(1, 8):
         sp = sel[order[sel] == p]
@@ -280,8 +284,10 @@ def row_batched(L, I, torch, steps, model, checks):
            "seven_plain_launches_ms": t7 * 1e3, "speedup_vs_plain": t7 / tb,
            "predicted_ms": pred * 1e3 if pred else None,
            "model_rel_error": (pred - tb) / tb if pred else None,
+           "predicted_by": "batched-family model on the counts of every order's share (the bodies that ran)",
            "shapes": {p: plan.info(p)["tile"] for p in range(1, 8)}}
-    log(f"batched: {tb * 1e3:.3f} ms vs 7 launches {t7 * 1e3:.3f} ms, predicted {pred * 1e3:.3f} ms")
+    log(f"batched: {tb * 1e3:.3f} ms vs 7 launches {t7 * 1e3:.3f} ms, predicted "
+        f"{pred * 1e3 if pred else float('nan'):.3f} ms")
     del u, o, groups
     torch.cuda.empty_cache()
     return res
@@ -368,13 +374,16 @@ def achievable_hbm(torch):
 def row_model(path):
     import contextlib
     from paper_1904_09538_amd import calibrate as C
+    fresh = os.path.splitext(path)[0] + "_fresh.jsonl"
     with contextlib.redirect_stdout(sys.stderr):      # keep stdout to the one JSON line
         C.measure(path, quick=False, trials=60)
-    s = C.fit_all(path)
+        C.measure_fresh(fresh, trials=60)
+    s = C.fit_all(path, fresh_path=fresh)
     fams = {k: {"kind": v["kind"], "mape_heldout": v["mape_heldout"],
-                "geomean_heldout": v["geomean_heldout"], "negative_params": v["negative_params"],
-                "nonneg_mape_heldout": v["nonneg"]["mape_heldout"], "n_train": v["n_train"],
-                "n_heldout": v["n_heldout"],
+                "geomean_heldout": v["geomean_heldout"],
+                "unconstrained_mape_heldout": v["unconstrained"]["mape_heldout"],
+                "unconstrained_negative_params": v["unconstrained"]["negative_params"],
+                "n_train": v["n_train"], "n_heldout": v["n_heldout"],
                 **({"ranking": v["ranking"]} if "ranking" in v else {})}
             for k, v in s["families"].items()}
     x = s.get("cross")
@@ -382,18 +391,36 @@ def row_model(path):
         "trained_on": x["train_families"], "predicts": x["target"], "n_target": x["n_target"],
         "mape": x["nonneg"]["mape"], "geomean": x["nonneg"]["geomean"],
         "ranking": x["nonneg"].get("ranking"), "unconstrained_mape": x["unconstrained"]["mape"]}
+    fr = s.get("fresh")
+    fresh_row = None if not fr else {
+        "seed": fr["seed"], "mape_all": fr["mape_all"], "geomean_all": fr["geomean_all"],
+        "families": {k: {"n": v["n"], "mape": v["mape"], "geomean": v["geomean"],
+                         **({"ranking": v["ranking"]} if v.get("ranking") else {})}
+                     for k, v in fr["families"].items()},
+        "protocol": "sizes off the calibration grids, inputs from a fresh seed, scored once by the "
+                    "models (forms chosen on the calibration rows) fitted on every calibration row"}
+    micro = {t: None if not m else {
+        "mape": m["mape"], "geomean": m["geomean"], "linear_mape": m["linear_mape"], "n_target": m["n_target"],
+        "n_train": m["n_train"], "trained_on": m["train_kinds"],
+        **({"ranking": m["ranking"]} if m.get("ranking") else {})} for t, m in (s.get("micro") or {}).items()}
+    ov = s.get("overlap")
+    overlap = None if not ov else {
+        "overlap_median_per_order": ov["overlap_median_per_order"],
+        "reading": "(gmem twin + on-chip from microbenchmark rates - kernel time) / min of the two: "
+                   "1 = complete overlap, 0 = none"}
     return s, {"mape_heldout_all": s["mape_heldout_all"],
                "geomean_heldout_all": s["geomean_heldout_all"], "families": fams,
-               "cross_kernel": cross,
+               "cross_kernel": cross, "fresh_heldout": fresh_row,
+               "microbenchmark_calibrated": micro, "overlap_diagnosis": overlap,
                "protocol": "cold cache, 60 event-timed trials per variant, 20% held out (seed 4); "
-                           "unconstrained fit, non-negative fit beside"}
+                           "non-negative fit primary, unconstrained fit beside"}
 
 
-def model_vector(summary, names):
-    """DG model of a calibration summary as a per-feature cost vector: the
-    non-negative fit, whose costs stay positive for the batch's orders and
-    sizes wherever they fall relative to the calibration set."""
-    f = {**summary["families"]["dg"], **summary["families"]["dg"]["nonneg"]}
+def model_vector(summary, names, family="dg"):
+    """A family's model of a calibration summary as a per-feature cost vector
+    (the non-negative fit, whose costs stay positive wherever the batch's
+    orders and sizes fall relative to the calibration set)."""
+    f = summary["families"][family]
     cost = [0.0] * len(names)
     group = [0] * len(names)
     from paper_1904_09538_amd import calibrate as C
@@ -403,6 +430,18 @@ def model_vector(summary, names):
     if f["kind"] == "linear":
         return {"cost": cost, "group": None}
     return {"cost": cost, "group": group, "edge": f["edge"]}
+
+
+def model_predict(model, feats):
+    """Time of a feature vector under a model_vector (linear or overlap form)."""
+    import math
+    c = [0.0, 0.0, 0.0]
+    for k, (p, f) in enumerate(zip(model["cost"], feats)):
+        c[model["group"][k] if model["group"] else 0] += p * float(f)
+    if not model["group"]:
+        return c[0]
+    d = c[1] - c[2]
+    return c[0] + c[2] + d * 0.5 * (math.tanh(model["edge"] * d) + 1.0)
 
 
 # ------------------------------------------------------------------ CPU-oracle leg
@@ -463,7 +502,7 @@ def oracle_leg(D64, u64, nsample, headline_out, checks, rows):
             e["err_vs_oracle"] = _err(c["got"], oracle.matmul_select(c["a"], c["b"], c["ii"], c["jj"]))
         node = rows
         for key in c["at"]:
-            node = node[key]
+            node = node.setdefault(key, {})
         node.update(e)
         node["oracle_sample"] = ("first/last 64 + 2048 seeded elements" if k in ("dg", "dg_lowp", "grad_u", "quant")
                                  else "256 seeded entries" if k == "grad_D" else "4096/1024 seeded points")
@@ -551,7 +590,8 @@ def main():
     if "lowp" in want:
         rows["precision_p5_2e20"] = row_lowp(L, I, torch, small, checks)
     if "batched" in want:
-        mv = model_vector(model_summary, L.feature_names()) if model_summary else None
+        mv = (model_vector(model_summary, L.feature_names(), "batched")
+              if model_summary and "batched" in model_summary["families"] else None)
         rows["batched_mixed_p1_7_2e20"] = row_batched(L, I, torch, small, mv, checks)
     if "adjoint" in want:
         rows["adjoint_p4_2e19"] = row_adjoint(L, I, torch, small, checks)

@@ -101,19 +101,21 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
 
    dgdiff_plan_create: order [nelem] is a HOST array; nmat must be 3.
      tiles [8] (HOST, indexed by order; NULL = choose): launch shape per order.
-     Three kernel bodies serve the orders: one element per thread (orders 1
-     and 2 by default; reported as elems_per_wave 256), resident operator
+     Three kernel bodies serve the orders: one element per thread (order 1,
+     nunit 8, by default; reported as elems_per_wave 256), resident operator
      panels with the elements streamed through (elems_per_wave 16 or 32,
-     d_panels; used when a tile gives elems_per_wave for an order below 3), and a
-     GEMM tiling of 128 stacked operator rows x 128 elements, used for orders
-     with nunit >= 64 and for any order whose tile sets DG_TILE_BATCH_GEMM
-     (its other tile fields are then ignored).
+     d_panels; orders 2..5 by default, and order 1 when its tile gives
+     elems_per_wave), and a GEMM tiling of 128 stacked operator rows x 128
+     elements (orders 6 and 7, nunit >= 343, always, and any order whose
+     tile sets DG_TILE_BATCH_GEMM; its other tile fields are then ignored).
      When tiles is NULL and model_cost [PF_COUNT] (HOST, seconds per feature
-     unit) is given, every candidate shape of every order is priced with the
-     model -- linear (model_group NULL) or the overlap form (model_group
-     [PF_COUNT] cost groups 0/1/2, model_edge) -- and the cheapest is taken;
-     the persistent grid is split across orders in proportion to predicted
-     time; GEMM-body orders are drained from a shared tile pool that every
+     unit; a model of DG_K_BATCHED counts) is given, every candidate shape of
+     every order is priced with the model as the body that runs it
+     (DG_K_BATCHED counts of the share the order would have alone on the
+     GPU, plus DG_K_BATCHED_POOL's for GEMM tiles) -- linear (model_group
+     NULL) or the overlap form (model_group [PF_COUNT] cost groups 0/1/2,
+     model_edge) -- and the cheapest is taken; the persistent grid is split
+     across orders in proportion to predicted time; GEMM-body orders are drained from a shared tile pool that every
      work-group joins after its own share, which absorbs estimate errors.
      The plan owns device copies of the sorted element ids and the offsets
      and the pool's cursors: calls that use one plan must not overlap in time
@@ -149,6 +151,7 @@ size_t dgdiff_backward_workspace(dg_dtype t, int32_t nmat, int64_t nelem, int32_
 dg_status dgdiff_backward(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit, const void* D,
                           const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
                           size_t ws_bytes, dg_stream_t stream);
+
 
 /* Quantise an FP32 [rows][cols] array for the low-precision DG path.
      to = DG_BF16:     q (uint16 [rows][cols]) = round-to-nearest-even BF16 of x;
@@ -199,7 +202,21 @@ typedef enum {
     DG_K_DGDIFF = 0,   /* dgdiff_apply forward (dtype = in_t) */
     DG_K_STENCIL5 = 1, /* stencil5_apply (fast path: FP32, n % 4 == 0, padded pitches) */
     DG_K_MATMUL = 2,   /* matmul_apply */
-    DG_K_EMPTY = 3     /* dg_empty_launch */
+    DG_K_EMPTY = 3,    /* dg_empty_launch */
+    DG_K_BWD_U = 4,    /* dgdiff_backward's grad_u step (dtype F32/F64; tile from
+                          dgdiff_resolve_backward: flags DG_TILE_BATCH_GEMM = the
+                          128 x 128 GEMM body, else the contraction kernel) */
+    DG_K_BWD_D = 5,    /* dgdiff_backward's grad_D step: split partials and the two
+                          fixed-order reductions (tile.groups_per_cu from
+                          dgdiff_resolve_backward) */
+    DG_K_QUANT = 6,    /* dgdiff_quantize: dtype = target (BF16/FP8), n0 = rows,
+                          nunit = cols, nmat = per_row_scale (0/1) */
+    DG_K_BATCHED = 7,  /* one order's share of a dgdiff_apply_batched launch: n0 = its
+                          elements, nunit = (p+1)^3, nmat = 3, tile and workgroups as
+                          dgdiff_plan_info reports them (elems_per_wave 256 = one
+                          element per thread; DG_TILE_BATCH_GEMM = GEMM tiles) */
+    DG_K_BATCHED_POOL = 8 /* the GEMM tile pool's fixed cost in a batched launch with
+                          GEMM orders: n0 = the launch's work-groups */
 } dg_kernel;
 
 typedef struct {
@@ -211,6 +228,7 @@ typedef struct {
     dg_tile tile;      /* DG only: fully resolved launch shape (dgdiff_resolve_tile) */
     int32_t num_cu;    /* DG, matmul: compute units of the target device (matmul: 0
                           counts one work-group's serial chain, not the busiest unit's) */
+    int64_t workgroups; /* DG_K_BATCHED: work-groups of the order's share */
 } perf_kernel_desc;
 
 /* Feature indices of perf_features_count (counts are int64, exact):          */
@@ -239,6 +257,12 @@ enum {
     PF_SERIAL_STEPS,     /* longest chain of loop iterations one work-group walks (latency) */
     PF_LAT_STEPS,        /* DG: 64 x serial steps / resident waves per SIMD (per_cu x waves / 4):
                             the tile latency left unhidden by other waves (launch configuration) */
+    PF_GLD_WS,           /* partial-result (workspace) loads, bytes */
+    PF_GST_WS,           /* partial-result (workspace) stores, bytes */
+    PF_GLD_IDX,          /* index and offset loads (batched element lists), bytes */
+    PF_GLD_UB,           /* measurement kernels: 16-byte vector loads, consecutive lanes, bytes */
+    PF_GST_UB,           /* measurement kernels: stores, bytes */
+    PF_GLD_UB_STRIDED,   /* measurement kernels: 4-byte loads, lanes S floats apart, bytes */
     PF_COUNT
 };
 
@@ -260,6 +284,63 @@ dg_status perf_features_count(const perf_kernel_desc* d, int64_t* counts);
    of the chosen kernel; needs a GPU).                                       */
 dg_status dgdiff_resolve_tile(dg_dtype in_t, int32_t nmat, int64_t nelem, int32_t nunit,
                               dg_tile* tile);
+
+/* The launch shapes dgdiff_backward uses for this problem on the current
+   device (needs a GPU): *tile_u for the grad_u step (DG_TILE_BATCH_GEMM in
+   flags when it runs as the 128 x 128 GEMM), *tile_d for grad_D
+   (groups_per_cu = resident work-groups per CU of the split-partial
+   kernel, which sets the split count).  Either pointer may be NULL.         */
+dg_status dgdiff_resolve_backward(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit,
+                                  dg_tile* tile_u, dg_tile* tile_d);
+
+/* ------------------------------------------------------------------------
+   Measurement kernels (Sections "Measurement Kernel Design", "Measurement
+   Kernel Sets for Evaluation" and "Measurement Workload Synthesis by Work
+   Removal Transformation"): microbenchmarks that each exercise one feature
+   of the model, and work-removed twins that keep a kernel's global-memory
+   accesses and drop its on-chip work.  All FP32; arrays are device arrays,
+   `in` a HOST array of device pointers.
+     kind                n              a              b         in / out
+     DG_UB_STREAM        4-float vectors inputs 1..4     -        in[0..a-1] [4n], out [4n] = sum of inputs
+     DG_UB_STRIDED       threads        stride S >= 1    -        in[0] [n*S], out[t] = in[0][t*S]
+     DG_UB_FMA           work-groups    loop trips       -        out [256n]: the fma recurrence's sum
+     DG_UB_MFMA          work-groups    loop trips       -        out [1024n]: eight chains of products
+                                                                  (dtype DG_F32 or DG_BF16 operands)
+     DG_UB_LDS           work-groups    trips            1 or 4   in[0], out [256n*b]: rotated by a lanes
+     DG_UB_BARRIER       work-groups    barriers         -        out [256n] = a
+     DG_UB_OVERLAP       4-float vectors LDS pairs m     -        in[0], out [4n]: rotated by m lanes
+     DG_UB_TWIN_DG       nelem          nunit            nmat     in[0] = D, in[1] = u, out as dgdiff_apply
+                                                                  (tile: a resolved FP32 forward tile)
+     DG_UB_TWIN_STENCIL  n              ld_u             ld_res   in[0] = u, out = res (vector path layout)
+     DG_UB_TWIN_MATMUL   n              -                -        in[0] = a, in[1] = b, out = c
+   The twins' outputs carry no meaning beyond covering every element the
+   original writes.  perf_ubench_count gives the launch's counts (as
+   perf_features_count; twins count the original's global accesses, with the
+   adds of the loaded values as VALU flops).                                */
+typedef enum {
+    DG_UB_STREAM = 0,
+    DG_UB_STRIDED = 1,
+    DG_UB_FMA = 2,
+    DG_UB_MFMA = 3,
+    DG_UB_LDS = 4,
+    DG_UB_BARRIER = 5,
+    DG_UB_OVERLAP = 6,
+    DG_UB_TWIN_DG = 7,
+    DG_UB_TWIN_STENCIL = 8,
+    DG_UB_TWIN_MATMUL = 9
+} dg_ubench;
+
+typedef struct {
+    dg_ubench kind;
+    dg_dtype dtype;
+    int64_t n;
+    int32_t a, b;
+    dg_tile tile;      /* DG_UB_TWIN_DG only */
+    int32_t num_cu;    /* DG_UB_TWIN_DG only (counts) */
+} dg_ubench_desc;
+
+dg_status dg_ubench_run(const dg_ubench_desc* d, const void* const* in, void* out, dg_stream_t stream);
+dg_status perf_ubench_count(const dg_ubench_desc* d, int64_t* counts);
 
 /* Flags of the model fits.  DG_FIT_RELATIVE: minimise the relative error
    (the paper's scale_features_by_output, Section "Computing Model

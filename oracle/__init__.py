@@ -64,8 +64,10 @@ def _declare(L):
     L.orc_pow2_scale.argtypes = [ctypes.c_double, ctypes.c_double]
     L.orc_pow2_scale.restype = ctypes.c_double
     L.orc_quantize.argtypes = [_i32, _i64, _i64, _i32, _fp, ctypes.c_void_p, _fp]
-    L.orc_features.argtypes = [_i32, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i64p]
+    L.orc_features.argtypes = [_i32, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i64, _i64p]
     L.orc_features.restype = _i32
+    L.orc_ubench_features.argtypes = [_i32, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i64p]
+    L.orc_ubench_features.restype = _i32
     L.orc_count_triangle.argtypes = [_i64, _i64]
     L.orc_count_triangle.restype = _i64
 
@@ -195,17 +197,38 @@ def matmul_select(a, b, ii, jj):
 FEATURES = ["launch", "workgroups", "barrier_x_wg", "gld_dg_u", "gld_dg_u_l2", "gld_dg_d",
             "gst_dg_out", "gld_st_u", "gst_st_res", "gld_mm_ab", "gst_mm_c", "lds_bytes",
             "mfma_f64", "mfma_f32", "mfma_bf16", "mfma_fp8", "valu_f32", "valu_f64",
-            "gld_dg_u_unal", "gst_dg_out_unal", "wave_tiles", "serial_steps", "lat_steps"]
-KERNELS = {"dg": 0, "stencil": 1, "matmul": 2, "empty": 3}
+            "gld_dg_u_unal", "gst_dg_out_unal", "wave_tiles", "serial_steps", "lat_steps",
+            "gld_ws", "gst_ws", "gld_idx", "gld_ub", "gst_ub", "gld_ub_strided"]
+KERNELS = {"dg": 0, "stencil": 1, "matmul": 2, "empty": 3, "bwd_u": 4, "bwd_d": 5, "quant": 6,
+           "batched": 7, "batched_pool": 8}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}
 
 
 def features(kernel, dtype, n0, nunit=0, nmat=0, elems_per_wave=0, waves=0, groups_per_cu=0,
-             d_panels=0, flags=0, num_cu=0):
-    """Brute-force enumeration of one launch's operation counts (int64 array)."""
+             d_panels=0, flags=0, num_cu=0, workgroups=0):
+    """Brute-force enumeration of one launch's operation counts (int64 array).
+    quant: nunit = cols, nmat = per-row scales (0/1); batched: one order's
+    share of workgroups work-groups."""
     out = np.zeros(len(FEATURES), dtype=np.int64)
     rc = lib().orc_features(KERNELS[kernel], DTYPES[dtype], int(n0), nunit, nmat, elems_per_wave,
-                            waves, groups_per_cu, d_panels, flags, num_cu, _ptr(out, _i64p))
+                            waves, groups_per_cu, d_panels, flags, num_cu, int(workgroups),
+                            _ptr(out, _i64p))
+    if rc != 0:
+        raise ValueError("unsupported descriptor")
+    return out
+
+
+UBENCH = {"stream": 0, "strided": 1, "fma": 2, "mfma": 3, "lds": 4, "barrier": 5, "overlap": 6,
+          "twin_dg": 7, "twin_stencil": 8, "twin_matmul": 9}
+
+
+def ubench_features(kind, n, a=0, b=0, dtype="f32", tile=None, num_cu=0):
+    """Brute-force enumeration of one measurement-kernel launch's counts."""
+    t = tile or {}
+    out = np.zeros(len(FEATURES), dtype=np.int64)
+    rc = lib().orc_ubench_features(UBENCH[kind], DTYPES[dtype], int(n), int(a), int(b),
+                                   t.get("elems_per_wave", 0), t.get("waves", 0), t.get("groups_per_cu", 0),
+                                   t.get("d_panels", 0), t.get("flags", 0), int(num_cu), _ptr(out, _i64p))
     if rc != 0:
         raise ValueError("unsupported descriptor")
     return out

@@ -26,9 +26,10 @@
 /* feature slots, in the order of the library's interface */
 enum { F_LAUNCH, F_WG, F_BAR, F_U, F_U_L2, F_D, F_OUT, F_ST_U, F_ST_RES, F_MM_AB, F_MM_C, F_LDS,
        F_MFMA_F64, F_MFMA_F32, F_MFMA_BF16, F_MFMA_FP8, F_VALU_F32, F_VALU_F64, F_U_UNAL, F_OUT_UNAL,
-       F_WAVE_TILES, F_SERIAL, F_LAT, F_N };
+       F_WAVE_TILES, F_SERIAL, F_LAT, F_WS_LD, F_WS_ST, F_IDX, F_UB_LD, F_UB_ST, F_UB_LD_STRIDED, F_N };
 
-enum { K_DG = 0, K_STENCIL = 1, K_MATMUL = 2, K_EMPTY = 3 };
+enum { K_DG = 0, K_STENCIL = 1, K_MATMUL = 2, K_EMPTY = 3, K_BWD_U = 4, K_BWD_D = 5, K_QUANT = 6,
+       K_BATCHED = 7, K_BATCHED_POOL = 8 };
 enum { T_F64 = 0, T_F32 = 1, T_BF16 = 2, T_FP8 = 3 };
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -46,8 +47,12 @@ static int kq_of(int n) {
 
 /* ---------------------------------------------------------------- DG forward */
 
-static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int per_cu, int d_panels,
-                   int flags, int num_cu, int64_t* c) {
+/* One launch of the contraction kernel.  nseg contraction segments (grad_u:
+   the nmat slabs of g, operator transposed), M output slabs; allow_pipe: the
+   forward's paired-store launch (pipelined element loads may apply); acc:
+   the launch adds to its output (reads each value it writes). */
+static int dg_walk(int dtype, int64_t E, int n, int nseg, int M, int epw, int waves, int per_cu,
+                   int d_panels, int flags, int num_cu, int allow_pipe, int acc, int64_t* c) {
     const int lowp = dtype == T_BF16 || dtype == T_FP8;
     const int native = dtype == T_FP8 && (flags & 2);
     const int64_t sz = dtype == T_F64 ? 8 : 4;      /* FP element size */
@@ -88,13 +93,13 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
     const int vec_in = lowp ? (n % 8 == 0) : (n % V == 0);
     int use_slab = 0;
     if (!lowp && !vec_in) {
-        int64_t panel_bytes = 16 * (4LL * KQ + V) * sz;
-        int64_t slab = (int64_t)waves * cdiv(16LL * cb * n, V) * V * sz;
+        int64_t panel_bytes = 16 * (nseg * 4LL * KQ + V) * sz;
+        int64_t slab = (int64_t)waves * nseg * cdiv(16LL * cb * n, V) * V * sz;
         use_slab = slab + panel_bytes <= 80 * 1024;
     }
     {
-        const int64_t panel = lowp ? 16 * (32LL * KS * el + 16) : 16 * (4LL * KQ + V) * sz;
-        const int64_t slab = use_slab ? (int64_t)waves * cdiv(16LL * cb * n, V) * V * sz : 0;
+        const int64_t panel = lowp ? 16 * (32LL * KS * el + 16) : 16 * (nseg * 4LL * KQ + V) * sz;
+        const int64_t slab = use_slab ? (int64_t)waves * nseg * cdiv(16LL * cb * n, V) * V * sz : 0;
         if (ppg * panel + slab > 160 * 1024) return 1;
     }
     const int vec_out = n % 4 == 0;
@@ -104,11 +109,12 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
        panel pairs; with small fragments (KQ * cb <= 32) their element loads are
        issued a tile ahead, every lane of a wave-tile loading all its vectors
        (rows past the end read the last element) */
-    const int piped = !lowp && sz == 4 && vec_in && vec_out && n % 32 == 0 && mblk % 2 == 0 &&
-                      ppg % 2 == 0 && KQ * cb <= 32;
+    const int piped = allow_pipe && !lowp && sz == 4 && vec_in && vec_out && n % 32 == 0 &&
+                      mblk % 2 == 0 && ppg % 2 == 0 && KQ * cb <= 32;
 
     c[F_LAUNCH] += 1;
     c[F_WG] += G;
+    int64_t serial = 0;
     for (int64_t b = 0; b < G; ++b) {
         const int64_t xcd = b % 8, kb = b / 8;
         const int pg = (int)(kb % NG);
@@ -116,13 +122,22 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
         const int p_lo = pg * ppg;
         const int np = (int)mini(ppg, P - p_lo);
         /* operator staging: one lane-iteration per LDS slot */
-        for (int64_t idx = 0; idx < (int64_t)np * 16 * KP; ++idx) {
-            const int k = (int)(idx % KP);
-            const int rr = (int)(idx / KP);
+        const int KS2 = lowp ? KP : nseg * KP;   /* staged columns per row */
+        for (int64_t idx = 0; idx < (int64_t)np * 16 * KS2; ++idx) {
+            const int k = (int)(idx % KS2) % KP;
+            const int rr = (int)(idx / KS2);
             const int panel = p_lo + rr / 16;
             const int o = (panel % mblk) * 16 + rr % 16;
             if (o < n && k < n) c[F_D] += lowp ? eg : sz;
             c[F_LDS] += lowp ? el : sz;
+        }
+        if (lowp) {
+            /* threads 0..7 stage the operator scales (1 where none are given):
+               FP8 reads the nmat given ones */
+            for (int t = 0; t < 8; ++t) {
+                c[F_LDS] += 4;
+                if (dtype == T_FP8 && t < M) c[F_D] += 4;
+            }
         }
         c[F_BAR] += 1;
         /* element-data tag: re-reads by groups > 0, else by access path */
@@ -140,6 +155,7 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                         for (int lane = 0; lane < 64; ++lane) {
                             const int cc = lane & 15, g = lane >> 4;
                             const int64_t e = e0 + q * 16 + cc;
+                            if (dtype == T_FP8 && e < E) c[F_U_UNAL] += 4;   /* the element's scale */
                             for (int s = 0; s < KS; ++s) {
                                 if (vec_in) {
                                     if (e < E && g * KQ + 8 * s < n) c[tag] += 8 * eg;
@@ -149,41 +165,45 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                                 }
                             }
                         }
-                } else if (piped) {
-                    for (int q = 0; q < cb; ++q)
-                        for (int lane = 0; lane < 64; ++lane)
-                            for (int s = 0; s < KQ; s += V) c[tag] += 16;
-                } else if (vec_in) {
-                    for (int q = 0; q < cb; ++q)
-                        for (int lane = 0; lane < 64; ++lane) {
-                            const int cc = lane & 15, g = lane >> 4;
-                            const int64_t e = e0 + q * 16 + cc;
-                            if (e >= E) continue;
-                            for (int s = 0; s < KQ; s += V)
-                                if (g * KQ + s < n) c[tag] += 16;
-                        }
-                } else if (!use_slab) {
-                    for (int q = 0; q < cb; ++q)
-                        for (int lane = 0; lane < 64; ++lane) {
-                            const int cc = lane & 15, g = lane >> 4;
-                            const int64_t e = e0 + q * 16 + cc;
-                            for (int t = 0; t < KQ; ++t)
-                                if (e < E && g * KQ + t < n) c[tag] += sz;
-                        }
                 } else {
-                    const int64_t nel = mini(16LL * cb, E - e0);
-                    const int64_t len = nel * n;
-                    for (int64_t f = 0; f < len; ++f) {   /* slab copy: load + LDS store */
-                        c[tag] += sz;
-                        c[F_LDS] += sz;
-                    }
-                    for (int q = 0; q < cb; ++q)
-                        for (int lane = 0; lane < 64; ++lane) {
-                            const int cc = lane & 15, g = lane >> 4;
-                            const int elx = q * 16 + cc;
-                            for (int t = 0; t < KQ; ++t)
-                                if (elx < nel && g * KQ + t < n) c[F_LDS] += sz;
+                    for (int sg = 0; sg < nseg; ++sg) {   /* each contraction segment's rows */
+                        if (piped) {
+                            for (int q = 0; q < cb; ++q)
+                                for (int lane = 0; lane < 64; ++lane)
+                                    for (int s = 0; s < KQ; s += V) c[tag] += 16;
+                        } else if (vec_in) {
+                            for (int q = 0; q < cb; ++q)
+                                for (int lane = 0; lane < 64; ++lane) {
+                                    const int cc = lane & 15, g = lane >> 4;
+                                    const int64_t e = e0 + q * 16 + cc;
+                                    if (e >= E) continue;
+                                    for (int s = 0; s < KQ; s += V)
+                                        if (g * KQ + s < n) c[tag] += 16;
+                                }
+                        } else if (!use_slab) {
+                            for (int q = 0; q < cb; ++q)
+                                for (int lane = 0; lane < 64; ++lane) {
+                                    const int cc = lane & 15, g = lane >> 4;
+                                    const int64_t e = e0 + q * 16 + cc;
+                                    for (int t = 0; t < KQ; ++t)
+                                        if (e < E && g * KQ + t < n) c[tag] += sz;
+                                }
+                        } else {
+                            const int64_t nel = mini(16LL * cb, E - e0);
+                            const int64_t len = nel * n;
+                            for (int64_t f = 0; f < len; ++f) {   /* slab copy: load + LDS store */
+                                c[tag] += sz;
+                                c[F_LDS] += sz;
+                            }
+                            for (int q = 0; q < cb; ++q)
+                                for (int lane = 0; lane < 64; ++lane) {
+                                    const int cc = lane & 15, g = lane >> 4;
+                                    const int elx = q * 16 + cc;
+                                    for (int t = 0; t < KQ; ++t)
+                                        if (elx < nel && g * KQ + t < n) c[F_LDS] += sz;
+                                }
                         }
+                    }
                 }
                 const int64_t nel_w = mini(16LL * cb, E - e0);
                 /* panels */
@@ -195,12 +215,28 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                             c[F_LDS] += 64 * 8 * el;                    /* operand read */
                             for (int q = 0; q < cb; ++q) c[native ? F_MFMA_FP8 : F_MFMA_BF16] += 16384;
                         }
-                    } else {
-                        for (int s = 0; s < KQ; s += V) {
-                            c[F_LDS] += 64 * 16;                        /* 16-byte operand read */
-                            for (int t = 0; t < V; ++t)
-                                for (int q = 0; q < cb; ++q) c[sz == 8 ? F_MFMA_F64 : F_MFMA_F32] += 2048;
+                        /* de-scaling: panel pairs (rows of a multiple of 32 nodes,
+                           even panel groups) read the operator scale once and scale
+                           both panels on every lane; single panels on lanes whose
+                           element exists (one product of scales, four multiplies) */
+                        const int lp_pair = vec_out && n % 32 == 0 && mblk % 2 == 0 && ppg % 2 == 0;
+                        if (lp_pair && pp % 2 == 0 && pp + 1 < np) {
+                            c[F_LDS] += 64 * 4;
+                            for (int q = 0; q < cb; ++q) c[F_VALU_F32] += 64 * 9;
+                        } else if (!(lp_pair && pp % 2 == 1)) {
+                            c[F_LDS] += 64 * 4;
+                            for (int q = 0; q < cb; ++q)
+                                for (int lane = 0; lane < 64; ++lane)
+                                    if (e0 + q * 16 + (lane & 15) < E) c[F_VALU_F32] += 5;
                         }
+                    } else {
+                        for (int sg = 0; sg < nseg; ++sg)
+                            for (int s = 0; s < KQ; s += V) {
+                                c[F_LDS] += 64 * 16;                    /* 16-byte operand read */
+                                for (int t = 0; t < V; ++t)
+                                    for (int q = 0; q < cb; ++q)
+                                        c[sz == 8 ? F_MFMA_F64 : F_MFMA_F32] += 2048;
+                            }
                     }
                     if (stage_out) {
                         /* each lane puts its four results into the slab ... */
@@ -221,6 +257,7 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                             for (int64_t f = 0; f < nel_w * rows; ++f) {
                                 c[F_LDS] += sz;
                                 c[F_OUT] += sz;
+                                if (acc) c[F_WS_LD] += sz;   /* the value added to */
                             }
                         }
                         continue;
@@ -232,6 +269,9 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                             if (e >= E) continue;
                             const int i = i0 + 4 * g;
                             const int64_t osz = lowp ? 4 : sz;
+                            if (acc)
+                                for (int r = 0; r < 4; ++r)
+                                    if (i + r < n) c[F_WS_LD] += osz;   /* the value added to */
                             if (vec_out) {
                                 if (i < n) c[F_OUT] += 4 * osz;
                             } else {
@@ -242,11 +282,12 @@ static int dg_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int p
                 }
             }
         }
-        if (steps > c[F_SERIAL]) c[F_SERIAL] = steps;
+        if (steps > serial) serial = steps;
     }
     /* latency left unhidden: the busiest stream's steps over resident waves
        per SIMD (per_cu work-groups of `waves` waves on 4 SIMDs), x 64 */
-    c[F_LAT] = c[F_SERIAL] * 64 / ((int64_t)per_cu * waves);
+    c[F_SERIAL] += serial;
+    c[F_LAT] += serial * 64 / ((int64_t)per_cu * waves);
     return 0;
 }
 
@@ -273,11 +314,11 @@ static void stencil_walk(int dtype, int64_t n, int64_t* c) {
                     const int self_halo = lane == 63 || j0 + 4 >= n;
                     const int64_t i_lo = by * R, i_hi = mini(n, i_lo + R);
                     if (i_hi - i_lo > c[F_SERIAL]) c[F_SERIAL] = i_hi - i_lo;
-                    /* rows i_lo .. i_hi+1 are loaded once each */
+                    /* rows i_lo .. i_hi+1 are loaded once each (the other lanes'
+                       right halo comes by a wave shuffle, which moves no LDS bytes) */
                     for (int64_t r = i_lo; r < i_hi + 2; ++r) {
                         if (active) c[F_ST_U] += 16;
                         if (active && self_halo) c[F_ST_U] += 8;
-                        c[F_LDS] += 2 * 4;   /* two shuffles */
                     }
                     for (int64_t i = i_lo; i < i_hi; ++i) {
                         c[F_VALU_F32] += 4 * 5;
@@ -366,14 +407,477 @@ static void matmul_walk(int64_t n, int num_cu, int64_t* c) {
     free(unit);
 }
 
+/* ---------------------------------------------------------------- adjoint */
+
+static int64_t clamp04(int64_t a) { return a < 0 ? 0 : a > 4 ? 4 : a; }
+
+/* grad_D: kernel 1, work-group (m, tile row ti, tile column tj, split) multiplies
+   its 128 x 128 tile over the split's elements in chunks of 16 (thread t
+   stages element t/16 of a chunk, nodes 8(t%16) .. +7 of its g and u rows,
+   four at a time); kernel 2 sums the partials of every entry in groups of 16
+   splits; kernel 3 sums the group sums.  The split plan (one round of
+   resident work-groups, at most one split per 256 elements, splits a
+   multiple of 16 elements long) is the documented schedule. */
+static int bwdd_walk(int dtype, int64_t E, int n, int M, int per_cu, int num_cu, int64_t* c) {
+    const int64_t sz = dtype == T_F64 ? 8 : 4;
+    const int V = (int)(16 / sz);
+    const int64_t count = (int64_t)M * n * n;
+    const int fl = sz == 8 ? F_VALU_F64 : F_VALU_F32;
+    if (per_cu < 1 || num_cu < 1) return 1;
+    if (E == 0) {
+        c[F_LAUNCH] += 1;
+        c[F_WG] += cdiv(count, 256);
+        for (int64_t idx = 0; idx < count; ++idx) c[F_OUT_UNAL] += sz;
+        return 0;
+    }
+    const int ntile = (int)cdiv(n, 128);
+    const int64_t tiles = (int64_t)M * ntile * ntile;
+    int64_t ns = maxi(1, (int64_t)per_cu * num_cu / tiles);
+    ns = mini(ns, maxi(1, cdiv(E, 256)));
+    const int64_t len = cdiv(cdiv(E, ns), 16) * 16;
+    const int64_t nsplit = maxi(1, cdiv(E, len)), ngroups = cdiv(nsplit, 16);
+    const int tag = n % V == 0 ? F_U : F_U_UNAL;
+    c[F_LAUNCH] += 3;
+    int64_t serial = 0;
+    for (int m = 0; m < M; ++m)
+        for (int ti = 0; ti < ntile; ++ti)
+            for (int tj = 0; tj < ntile; ++tj)
+                for (int64_t sp = 0; sp < nsplit; ++sp) {
+                    const int i0 = ti * 128, j0 = tj * 128;
+                    const int64_t e_lo = sp * len, e_hi = mini(E, e_lo + len);
+                    const int64_t nchunk = e_hi > e_lo ? cdiv(e_hi - e_lo, 16) : 0;
+                    c[F_WG] += 1;
+                    c[F_BAR] += 1 + nchunk;
+                    if (nchunk > serial) serial = nchunk;
+                    for (int t = 0; t < 256; ++t) {
+                        const int el = t >> 4, xs = (t & 15) * 8;
+                        for (int64_t kc = 0; kc < nchunk; ++kc) {
+                            const int64_t e = e_lo + kc * 16 + el;
+                            if (e < e_hi)
+                                for (int h = 0; h < 2; ++h) {
+                                    c[tag] += sz * clamp04(n - (i0 + xs + 4 * h));   /* g row */
+                                    c[tag] += sz * clamp04(n - (j0 + xs + 4 * h));   /* u row */
+                                }
+                            c[F_LDS] += 2 * 8 * sz;   /* the chunk's two rows into LDS */
+                        }
+                    }
+                    for (int w = 0; w < 4; ++w)
+                        for (int64_t kc = 0; kc < nchunk; ++kc) {
+                            c[F_LDS] += 64 * 32 * sz;     /* 16 g and 16 u values per lane */
+                            for (int k = 0; k < 64; ++k) c[sz == 8 ? F_MFMA_F64 : F_MFMA_F32] += 2048;
+                        }
+                    for (int t = 0; t < 256; ++t) {
+                        const int lane = t & 63, wave = t >> 6, wr = wave >> 1, wc = wave & 1;
+                        const int cc = lane & 15, g = lane >> 4;
+                        for (int pi = 0; pi < 4; ++pi)
+                            for (int qj = 0; qj < 4; ++qj)
+                                for (int r = 0; r < 4; ++r) {
+                                    const int row = sz == 8 ? g + 4 * r : 4 * g + r;
+                                    const int i = i0 + wr * 64 + pi * 16 + row;
+                                    const int j = j0 + wc * 64 + qj * 16 + cc;
+                                    if (i < n && j < n) c[F_WS_ST] += sz;
+                                }
+                    }
+                }
+    c[F_WG] += cdiv(count, 256) * ngroups + cdiv(count, 256);
+    for (int64_t idx = 0; idx < count; ++idx) {
+        for (int64_t y = 0; y < ngroups; ++y) {
+            for (int64_t k = 16 * y; k < mini(nsplit, 16 * y + 16); ++k) {
+                c[F_WS_LD] += sz;
+                c[fl] += 1;
+            }
+            c[F_WS_ST] += sz;
+        }
+        for (int64_t y = 0; y < ngroups; ++y) {
+            c[F_WS_LD] += sz;
+            c[fl] += 1;
+        }
+        c[F_OUT_UNAL] += sz;
+    }
+    c[F_SERIAL] += serial;
+    return 0;
+}
+
+/* grad_u as a GEMM (FP32): block b sits on XCD b % 8 and takes element tile
+   (b / 8 / ntile_j) * 8 + b % 8 and output-node tile (b / 8) % ntile_j; the
+   contraction over (m, i) runs in chunks of 16 nodes of one operator (thread t
+   stages operator rows t/32 and t/32 + 8 at output nodes 4(t%32) .. +3, and
+   elements t/4 and t/4 + 64 at contraction nodes 4(t%4) .. +3). */
+static void bwdu_gemm_walk(int64_t E, int n, int M, int64_t* c) {
+    const int64_t ntile_e = cdiv(E, 128), ntile_j = cdiv(n, 128);
+    const int64_t blocks = cdiv(ntile_e, 8) * 8 * ntile_j;
+    const int kpm = (int)cdiv(n, 16);
+    const int nchunk = M * kpm;
+    int any = 0;
+    c[F_LAUNCH] += 1;
+    c[F_WG] += blocks;
+    for (int64_t b = 0; b < blocks; ++b) {
+        const int64_t xcd = b & 7, kb = b >> 3;
+        const int64_t te = (kb / ntile_j) * 8 + xcd;
+        if (te >= ntile_e) continue;
+        any = 1;
+        const int j0 = (int)(kb % ntile_j) * 128;
+        const int64_t e0 = te * 128;
+        const int gtag = j0 > 0 ? F_U_L2 : n % 4 == 0 ? F_U : F_U_UNAL;
+        const int otag = n % 4 == 0 ? F_OUT : F_OUT_UNAL;
+        c[F_BAR] += 1 + nchunk;
+        for (int t = 0; t < 256; ++t) {
+            const int ka = t >> 5, ja = (t & 31) * 4, eb = t >> 2, kq = (t & 3) * 4;
+            for (int kc = 0; kc < nchunk; ++kc) {
+                const int i0 = (kc % kpm) * 16;
+                for (int h = 0; h < 2; ++h) {
+                    const int i = i0 + ka + 8 * h, j = j0 + ja;
+                    if (i < n) c[F_D] += 4 * clamp04(n - j);
+                    const int64_t e = e0 + eb + 64 * h;
+                    if (e < E) c[gtag] += 4 * clamp04(n - (i0 + kq));
+                }
+                c[F_LDS] += 4 * 16;   /* two operator and two element vectors into LDS */
+            }
+        }
+        for (int w = 0; w < 4; ++w)
+            for (int kc = 0; kc < nchunk; ++kc) {
+                c[F_LDS] += 64 * (16 * 4 + 4 * 16);   /* operand reads */
+                for (int k = 0; k < 64; ++k) c[F_MFMA_F32] += 2048;
+            }
+        for (int t = 0; t < 256; ++t) {
+            const int lane = t & 63, wave = t >> 6, wm = wave >> 1, wn = wave & 1;
+            const int cc = lane & 15, g = lane >> 4;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t e = e0 + wn * 64 + q * 16 + cc;
+                if (e >= E) continue;
+                for (int p = 0; p < 4; ++p) {
+                    const int j = j0 + wm * 64 + p * 16 + 4 * g;
+                    if (j + 4 <= n) {
+                        c[otag] += 16;
+                    } else {
+                        for (int r = 0; r < 3; ++r)
+                            if (j + r < n) c[otag] += 4;
+                    }
+                }
+            }
+        }
+    }
+    if (any) c[F_SERIAL] += nchunk;
+}
+
+/* grad_u: the GEMM for FP32 rows of 97 nodes or more (flags bit 4 set by the
+   resolver), else the contraction kernel with the operator transposed: the
+   nmat slabs of g as segments of one launch where such an instance exists
+   (nmat <= 3 and nmat * KQ * size <= 768 bytes of fragments), else one
+   launch per operator, the later ones adding to grad_u. */
+static int bwdu_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int per_cu, int d_panels,
+                     int flags, int num_cu, int64_t* c) {
+    const int64_t sz = dtype == T_F64 ? 8 : 4;
+    if (flags & 4) {
+        if (sz != 4 || n < 97) return 1;
+        bwdu_gemm_walk(E, n, M, c);
+        return 0;
+    }
+    if (epw != 16) return 1;
+    const int KQ = kq_of(n);
+    if (KQ < 0) return 1;
+    const int one = M <= 3 && (M == 1 || M * KQ * sz <= 768);
+    if (one) return dg_walk(dtype, E, n, M, 1, 16, waves, per_cu, d_panels, 0, num_cu, 0, 0, c);
+    for (int m = 0; m < M; ++m)
+        if (dg_walk(dtype, E, n, 1, 1, 16, waves, per_cu, d_panels, 0, num_cu, 0, m > 0, c)) return 1;
+    return 0;
+}
+
+/* ---------------------------------------------------------------- quantiser */
+
+/* dgdiff_quantize.  Rows of at most 1024 values: the short-row kernel (lane
+   l holds 4-value vectors 4(l + 64k), k < NV; four rows per wave and step,
+   rows r0, r0 + W, r0 + 2W, r0 + 3W for W launched waves); longer rows: one
+   wave per row, value by value (FP8 reads the row twice: maximum, then
+   encode); FP8 with one scale for the whole array: clear, grid-wide
+   maximum, encode (16-byte vectors while they fit, then the tail value by
+   value), final.  BF16 without per-row scales writes its single scale
+   (1) in a launch of its own.  Inverse scales are always requested. */
+static int quant_walk(int dtype, int64_t rows, int64_t cols, int per_row, int64_t* c) {
+    const int fp8 = dtype == T_FP8;
+    const int64_t esz = fp8 ? 1 : 2;
+    if (dtype != T_FP8 && dtype != T_BF16) return 1;
+    if (rows == 0 || cols == 0) return 0;
+    if (!per_row && fp8) {
+        const int64_t N = rows * cols;
+        const int64_t blocks = maxi(1, mini(cdiv(N, 1024), 2048)), T = blocks * 256;
+        const int64_t nv = N / 4;
+        c[F_LAUNCH] += 4;
+        c[F_WG] += 1 + blocks + blocks + 1;
+        c[F_WS_ST] += 4;                                   /* clear the maximum */
+        for (int pass = 0; pass < 2; ++pass) {             /* maximum, encode */
+            for (int64_t w = 0; w < T / 64; ++w) {
+                if (pass == 0) {
+                    c[F_WS_ST] += 4;                           /* atomic maximum */
+                } else {
+                    c[F_WS_LD] += 4;                           /* the maximum, wave-uniform */
+                }
+            }
+            for (int64_t gid = 0; gid < T; ++gid) {
+                for (int64_t v = gid; v < nv; v += T) {
+                    c[F_U] += 16;
+                    if (pass) {
+                        c[F_VALU_F32] += 4;
+                        c[F_OUT] += 4;
+                    }
+                }
+                for (int64_t i = 4 * nv + gid; i < N; i += T) {
+                    c[F_U_UNAL] += 4;
+                    if (pass) {
+                        c[F_VALU_F32] += 1;
+                        c[F_OUT_UNAL] += 1;
+                    }
+                }
+            }
+        }
+        c[F_WS_LD] += 4;                                   /* final: read the maximum ... */
+        c[F_OUT_UNAL] += 4;                                /* ... write 1/s */
+        c[F_SERIAL] += cdiv(nv, T);
+        return 0;
+    }
+    int64_t serial = 0;
+    if (cols <= 1024) {
+        const int NV = cols <= 256 ? 1 : cols <= 512 ? 2 : 4;
+        const int64_t waves = mini(cdiv(rows, 4), fp8 ? 65536 : 262144);
+        const int64_t blocks = cdiv(waves, 4), W = blocks * 4;
+        const int vec = cols % 4 == 0;
+        c[F_LAUNCH] += 1;
+        c[F_WG] += blocks;
+        for (int64_t w = 0; w < W; ++w) {
+            int64_t steps = 0;
+            for (int64_t r0 = w; r0 < rows; r0 += 4 * W) {
+                ++steps;
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t r = r0 + j * W;
+                    if (r >= rows) continue;
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int k = 0; k < NV; ++k) {
+                            const int64_t avail = cols - 4 * (lane + 64 * k);
+                            if (avail >= 4) c[vec ? F_U : F_U_UNAL] += 16;
+                            else if (avail > 0) c[vec ? F_U : F_U_UNAL] += 4 * avail;
+                        }
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int k = 0; k < NV; ++k) {
+                            const int64_t avail = cols - 4 * (lane + 64 * k);
+                            if (avail <= 0) continue;
+                            if (fp8) c[F_VALU_F32] += 4;
+                            c[vec ? F_OUT : F_OUT_UNAL] += (avail >= 4 ? 4 : avail) * esz;
+                        }
+                    if (per_row) c[F_OUT_UNAL] += 4;
+                }
+            }
+            if (steps > serial) serial = steps;
+        }
+    } else {
+        const int64_t waves = mini(rows, 65536);
+        const int64_t blocks = cdiv(waves, 4), W = blocks * 4;
+        c[F_LAUNCH] += 1;
+        c[F_WG] += blocks;
+        for (int64_t w = 0; w < W; ++w) {
+            int64_t steps = 0;
+            for (int64_t r = w; r < rows; r += W) {
+                ++steps;
+                for (int lane = 0; lane < 64; ++lane) {
+                    for (int64_t cc = lane; cc < cols; cc += 64) {
+                        c[F_U_UNAL] += 4;
+                        if (fp8) {   /* encode pass */
+                            c[F_U_UNAL] += 4;
+                            c[F_VALU_F32] += 1;
+                        }
+                        c[F_OUT_UNAL] += esz;
+                    }
+                }
+                if (per_row) c[F_OUT_UNAL] += 4;
+            }
+            if (steps > serial) serial = steps;
+        }
+    }
+    if (!per_row) {   /* BF16's single scale */
+        c[F_LAUNCH] += 1;
+        c[F_WG] += 1;
+        c[F_OUT_UNAL] += 4;
+    }
+    c[F_SERIAL] += serial;
+    return 0;
+}
+
+/* ---------------------------------------------------------------- batched */
+
+/* One order's share of the batched launch: G work-groups of 4 waves; element
+   ids and offsets (8 + 8 bytes) loaded by every lane that uses them. */
+static int batched_walk(int64_t cnt, int n, int M, int epw, int ppg_in, int per_cu, int flags, int64_t G,
+                        int64_t* c) {
+    if (G < 1 || M != 3) return 1;
+    c[F_LAUNCH] += 1;
+    c[F_WG] += G;
+    if (cnt == 0) return 0;
+    if (flags & 4) {
+        /* GEMM tiles: pool x holds element blocks eb = x (mod 8), each with
+           every row block of the 3n stacked operator rows */
+        const int64_t R = (int64_t)M * n, RB = cdiv(R, 128), EB = cdiv(cnt, 128), nk = cdiv(n, 16);
+        for (int x = 0; x < 8; ++x) {
+            const int64_t nt = EB > x ? cdiv(EB - x, 8) * RB : 0;
+            for (int64_t t = 0; t < nt; ++t) {
+                const int64_t eb = x + 8 * (t / RB), rb = t % RB;
+                const int64_t e0 = eb * 128, r0 = rb * 128;
+                c[F_BAR] += 2 + 1 + nk;   /* the claim; after the first chunk; one per chunk */
+                c[F_LDS] += 8 + 256 * 8;  /* the claimed index: thread 0 stores it, every thread reads it */
+                for (int tid = 0; tid < 256; ++tid) {
+                    const int ar = tid >> 1, ah = (tid & 1) * 8, be = tid >> 2, bq = (tid & 3) * 4;
+                    const int a_ok = r0 + ar < R;
+                    int b_ok[2];
+                    for (int h = 0; h < 2; ++h) {
+                        b_ok[h] = e0 + be + 64 * h < cnt;
+                        if (b_ok[h]) c[F_IDX] += 16;
+                    }
+                    for (int64_t kc = 0; kc < nk; ++kc) {
+                        const int64_t k0 = kc * 16;
+                        for (int h = 0; h < 2; ++h)
+                            if (a_ok) c[F_D] += 4 * clamp04(n - (k0 + ah + 4 * h));
+                        for (int h = 0; h < 2; ++h)
+                            if (b_ok[h]) c[rb == 0 ? F_U_UNAL : F_U_L2] += 4 * clamp04(n - k0 - bq);
+                        c[F_LDS] += 4 * 16;
+                    }
+                }
+                for (int w = 0; w < 4; ++w)
+                    for (int64_t kc = 0; kc < nk; ++kc) {
+                        c[F_LDS] += 64 * (4 * 16 + 4 * 16);
+                        for (int k = 0; k < 64; ++k) c[F_MFMA_F32] += 2048;
+                    }
+                for (int tid = 0; tid < 256; ++tid) {
+                    const int lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+                    const int cc = lane & 15, g = lane >> 4;
+                    for (int tn = 0; tn < 4; ++tn) {
+                        const int64_t kpos = e0 + wn * 64 + tn * 16 + cc;
+                        if (kpos >= cnt) continue;
+                        c[F_IDX] += 16;
+                        for (int tm = 0; tm < 4; ++tm) {
+                            const int64_t row = r0 + wm * 64 + tm * 16 + 4 * g;
+                            if (row >= R) continue;
+                            const int64_t i = row % n;
+                            if (i + 4 <= n) {
+                                c[F_OUT_UNAL] += 16;
+                            } else {
+                                for (int r = 0; r < 4; ++r) {
+                                    if (row + r >= R) break;
+                                    c[F_OUT_UNAL] += 4;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        c[F_SERIAL] += nk;
+        return 0;
+    }
+    if (epw == 256) {
+        /* one element per thread (nunit 8): block lb sweeps 256-element blocks
+           lb, lb + G, ...; operator entries are wave-uniform loads */
+        if (n != 8) return 1;
+        int64_t serial = 0;
+        for (int64_t lb = 0; lb < G; ++lb) {
+            int64_t steps = 0;
+            for (int64_t blk = lb; blk * 256 < cnt; blk += G) {
+                ++steps;
+                for (int w = 0; w < 4; ++w) {
+                    int any = 0;
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int64_t k = blk * 256 + w * 64 + lane;
+                        if (k >= cnt) continue;
+                        any = 1;
+                        c[F_IDX] += 16;
+                        for (int v = 0; v < 2; ++v) c[F_U_UNAL] += 16;
+                        for (int m = 0; m < 3; ++m) {
+                            for (int i = 0; i < 8; ++i)
+                                for (int j = 0; j < 8; ++j) c[F_VALU_F32] += 2;
+                            for (int v = 0; v < 2; ++v) c[F_OUT_UNAL] += 16;
+                        }
+                    }
+                    if (any) c[F_D] += 3 * 8 * 8 * 4;
+                }
+            }
+            if (steps > serial) serial = steps;
+        }
+        c[F_SERIAL] += serial;
+        return 0;
+    }
+    /* resident operator panels (elems_per_wave 16 or 32) */
+    const int cb = epw / 16;
+    if (cb != 1 && cb != 2) return 1;
+    const int KQ = kq_of(n);
+    if (KQ < 0) return 1;
+    const int KP = 4 * KQ;
+    const int mblk = (int)cdiv(n, 16), P = M * mblk;
+    const int ppg = (int)maxi(1, mini(ppg_in, P));
+    const int NG = (int)cdiv(P, ppg);
+    if (G % (8 * NG)) return 1;
+    const int64_t nstreams = 8 * (G / (8 * NG));
+    const int64_t ntiles = cdiv(cnt, 16LL * cb * 4);
+    int64_t serial = 0;
+    for (int64_t lb = 0; lb < G; ++lb) {
+        const int64_t xcd = lb & 7, kb = lb >> 3;
+        const int pg = (int)(kb % NG);
+        const int64_t stream = (kb / NG) * 8 + xcd;
+        const int p_lo = pg * ppg;
+        const int np = (int)mini(ppg, P - p_lo);
+        for (int64_t idx = 0; idx < (int64_t)np * 16 * KP; ++idx) {
+            const int j = (int)(idx % KP), rr = (int)(idx / KP);
+            const int panel = p_lo + rr / 16;
+            const int i = (panel % mblk) * 16 + rr % 16;
+            if (i < n && j < n) c[F_D] += 4;
+            c[F_LDS] += 4;
+        }
+        c[F_BAR] += 1;
+        int64_t steps = 0;
+        for (int64_t tile = stream; tile < ntiles; tile += nstreams) {
+            ++steps;
+            for (int w = 0; w < 4; ++w) {
+                const int64_t k0 = tile * 64 * cb + (int64_t)w * 16 * cb;
+                if (k0 >= cnt) continue;
+                c[F_WAVE_TILES] += 1;
+                for (int q = 0; q < cb; ++q)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int cc = lane & 15, g = lane >> 4;
+                        const int64_t k = k0 + q * 16 + cc;
+                        if (k >= cnt) continue;
+                        c[F_IDX] += 16;
+                        for (int t = 0; t < KQ; t += 4)
+                            c[pg ? F_U_L2 : F_U_UNAL] += 4 * clamp04(n - g * KQ - t);
+                    }
+                for (int pp = 0; pp < np; ++pp) {
+                    const int panel = p_lo + pp;
+                    const int i = (panel % mblk) * 16;
+                    for (int t = 0; t < KQ; t += 4) {
+                        c[F_LDS] += 64 * 16;
+                        for (int s4 = 0; s4 < 4; ++s4)
+                            for (int q = 0; q < cb; ++q) c[F_MFMA_F32] += 2048;
+                    }
+                    for (int q = 0; q < cb; ++q)
+                        for (int lane = 0; lane < 64; ++lane) {
+                            const int cc = lane & 15, g = lane >> 4;
+                            const int64_t k = k0 + q * 16 + cc;
+                            if (k < cnt && i + 4 * g < n) c[F_OUT_UNAL] += 4 * clamp04(n - i - 4 * g);
+                        }
+                }
+            }
+        }
+        if (steps > serial) serial = steps;
+    }
+    c[F_SERIAL] += serial;
+    c[F_LAT] += serial * 64 / ((int64_t)(per_cu < 1 ? 1 : per_cu) * 4);
+    return 0;
+}
+
 /* counts[F_N] overwritten; returns 0 on success */
 int orc_features(int kernel, int dtype, int64_t n0, int nunit, int nmat, int epw, int waves,
-                 int per_cu, int d_panels, int flags, int num_cu, int64_t* counts) {
+                 int per_cu, int d_panels, int flags, int num_cu, int64_t workgroups, int64_t* counts) {
     memset(counts, 0, sizeof(int64_t) * F_N);
     switch (kernel) {
         case K_DG:
             if (n0 == 0) return 0;
-            return dg_walk(dtype, n0, nunit, nmat, epw, waves, per_cu, d_panels, flags, num_cu, counts);
+            return dg_walk(dtype, n0, nunit, 1, nmat, epw, waves, per_cu, d_panels, flags, num_cu, 1, 0,
+                           counts);
         case K_STENCIL:
             if (n0 > 0) stencil_walk(dtype, n0, counts);
             return 0;
@@ -383,6 +887,142 @@ int orc_features(int kernel, int dtype, int64_t n0, int nunit, int nmat, int epw
         case K_EMPTY:
             counts[F_LAUNCH] = 1;
             counts[F_WG] = n0;
+            return 0;
+        case K_BWD_U:
+            if (n0 == 0) return 0;
+            return bwdu_walk(dtype, n0, nunit, nmat, epw, waves, per_cu, d_panels, flags, num_cu, counts);
+        case K_BWD_D:
+            return bwdd_walk(dtype, n0, nunit, nmat, per_cu, num_cu, counts);
+        case K_QUANT:
+            return quant_walk(dtype, n0, nunit, nmat ? 1 : 0, counts);
+        case K_BATCHED:
+            return batched_walk(n0, nunit, nmat, epw, d_panels, per_cu, flags, workgroups, counts);
+        case K_BATCHED_POOL:
+            /* each work-group: one barrier before the pool, then per pool of the
+               eight the claim that finds it drained (two barriers) */
+            for (int64_t b = 0; b < n0; ++b) {
+                counts[F_BAR] += 1;
+                for (int x = 0; x < 8; ++x) {
+                    counts[F_BAR] += 2;
+                    counts[F_LDS] += 8 + 256 * 8;
+                }
+            }
+            return 0;
+    }
+    return 1;
+}
+
+/* ---------------------------------------------------------------- measurement kernels */
+
+enum { UB_STREAM, UB_STRIDED, UB_FMA, UB_MFMA, UB_LDS, UB_BARRIER, UB_OVERLAP, UB_TWIN_DG, UB_TWIN_STENCIL,
+       UB_TWIN_MATMUL };
+
+/* a twin: the original's global accesses and schedule, no on-chip work, one
+   add per loaded value */
+static void twin_of(int64_t* c) {
+    c[F_LDS] = c[F_BAR] = 0;
+    c[F_MFMA_F64] = c[F_MFMA_F32] = c[F_MFMA_BF16] = c[F_MFMA_FP8] = 0;
+    c[F_VALU_F64] = 0;
+    c[F_VALU_F32] = (c[F_U] + c[F_U_L2] + c[F_D] + c[F_ST_U] + c[F_MM_AB] + c[F_U_UNAL]) / 4;
+}
+
+int orc_ubench_features(int kind, int dtype, int64_t n, int a, int b, int epw, int waves, int per_cu,
+                        int d_panels, int flags, int num_cu, int64_t* c) {
+    memset(c, 0, sizeof(int64_t) * F_N);
+    if (n == 0) return 0;
+    c[F_LAUNCH] = 1;
+    switch (kind) {
+        case UB_STREAM: {
+            /* grid-stride over 4-float vectors, at most 8192 work-groups of 256 */
+            const int64_t blocks = maxi(1, mini(cdiv(n, 256), 8192)), T = blocks * 256;
+            int64_t serial = 0;
+            c[F_WG] = blocks;
+            for (int64_t t = 0; t < T; ++t) {
+                int64_t trips = 0;
+                for (int64_t v = t; v < n; v += T) {
+                    ++trips;
+                    for (int k = 0; k < a; ++k) c[F_UB_LD] += 16;
+                    c[F_VALU_F32] += 4 * (a - 1);
+                    c[F_UB_ST] += 16;
+                }
+                if (trips > serial) serial = trips;
+            }
+            c[F_SERIAL] = serial;
+            return 0;
+        }
+        case UB_STRIDED:
+            c[F_WG] = cdiv(n, 256);
+            for (int64_t t = 0; t < n; ++t) {
+                c[F_UB_LD_STRIDED] += 4;
+                c[F_UB_ST] += 4;
+            }
+            c[F_SERIAL] = 1;
+            return 0;
+        case UB_FMA:
+            c[F_WG] = n;
+            for (int64_t t = 0; t < 256 * n; ++t) {
+                c[F_VALU_F32] += 1 + 32;                       /* (t % 256) * 2^-8, then + v * 2^-5 */
+                for (int it = 0; it < a; ++it)
+                    for (int k = 0; k < 64; ++k) c[F_VALU_F32] += 2;
+                c[F_VALU_F32] += 31;                           /* the sum */
+                c[F_UB_ST] += 4;
+            }
+            c[F_SERIAL] = a;
+            return 0;
+        case UB_MFMA:
+            c[F_WG] = n;
+            for (int64_t w = 0; w < 4 * n; ++w)
+                for (int it = 0; it < a; ++it)
+                    for (int k = 0; k < 8; ++k) c[dtype == T_BF16 ? F_MFMA_BF16 : F_MFMA_F32] += dtype == T_BF16 ? 16384 : 2048;
+            for (int64_t t = 0; t < 256 * n; ++t) {
+                c[F_VALU_F32] += 7 * 4;
+                c[F_UB_ST] += 16;
+            }
+            c[F_SERIAL] = a;
+            return 0;
+        case UB_LDS:
+            if (b != 1 && b != 4) return 1;
+            c[F_WG] = n;
+            for (int64_t t = 0; t < 256 * n; ++t) {
+                c[F_UB_LD] += 4 * b;
+                c[F_LDS] += 4 * b;                             /* initial store */
+                for (int k = 0; k < a; ++k) c[F_LDS] += 2 * 4 * b;
+                c[F_LDS] += 4 * b;                             /* final load */
+                c[F_UB_ST] += 4 * b;
+            }
+            c[F_SERIAL] = a;
+            return 0;
+        case UB_BARRIER:
+            c[F_WG] = n;
+            for (int64_t g = 0; g < n; ++g) c[F_BAR] += a;
+            for (int64_t t = 0; t < 256 * n; ++t) c[F_UB_ST] += 4;
+            c[F_SERIAL] = a;
+            return 0;
+        case UB_OVERLAP: {
+            const int64_t blocks = cdiv(n, 256);
+            c[F_WG] = blocks;
+            for (int64_t g = 0; g < 256 * blocks; ++g) {
+                if (g < n) c[F_UB_LD] += 16;
+                for (int k = 0; k < a; ++k) c[F_LDS] += 16 + 16;
+                if (g < n) c[F_UB_ST] += 16;
+            }
+            c[F_SERIAL] = a;
+            return 0;
+        }
+        case UB_TWIN_DG:
+            c[F_LAUNCH] = 0;
+            if (dg_walk(T_F32, n, a, 1, b, epw, waves, per_cu, d_panels, flags, num_cu, 1, 0, c)) return 1;
+            twin_of(c);
+            return 0;
+        case UB_TWIN_STENCIL:
+            memset(c, 0, sizeof(int64_t) * F_N);
+            stencil_walk(T_F32, n, c);
+            twin_of(c);
+            return 0;
+        case UB_TWIN_MATMUL:
+            memset(c, 0, sizeof(int64_t) * F_N);
+            matmul_walk(n, num_cu, c);
+            twin_of(c);
             return 0;
     }
     return 1;

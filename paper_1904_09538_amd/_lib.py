@@ -36,14 +36,26 @@ DG_TILE_NT_STORE = 1
 DG_TILE_FP8_NATIVE = 2
 DG_TILE_BATCH_GEMM = 4
 
-DG_K_DGDIFF, DG_K_STENCIL5, DG_K_MATMUL, DG_K_EMPTY = range(4)
+(DG_K_DGDIFF, DG_K_STENCIL5, DG_K_MATMUL, DG_K_EMPTY, DG_K_BWD_U, DG_K_BWD_D, DG_K_QUANT,
+ DG_K_BATCHED, DG_K_BATCHED_POOL) = range(9)
+_KERNELS = {"dg": DG_K_DGDIFF, "stencil": DG_K_STENCIL5, "matmul": DG_K_MATMUL, "empty": DG_K_EMPTY,
+            "bwd_u": DG_K_BWD_U, "bwd_d": DG_K_BWD_D, "quant": DG_K_QUANT, "batched": DG_K_BATCHED,
+            "batched_pool": DG_K_BATCHED_POOL}
 
 
 class perf_kernel_desc(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n0", ctypes.c_int64),
                 ("nunit", ctypes.c_int32), ("nmat", ctypes.c_int32), ("tile", dg_tile),
-                ("num_cu", ctypes.c_int32)]
+                ("num_cu", ctypes.c_int32), ("workgroups", ctypes.c_int64)]
 
+
+class dg_ubench_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("tile", dg_tile), ("num_cu", ctypes.c_int32)]
+
+
+UBENCH = {"stream": 0, "strided": 1, "fma": 2, "mfma": 3, "lds": 4, "barrier": 5, "overlap": 6,
+          "twin_dg": 7, "twin_stencil": 8, "twin_matmul": 9}
 
 _lib = None
 
@@ -99,6 +111,13 @@ def _declare(L):
     L.perf_features_count.argtypes = [ctypes.POINTER(perf_kernel_desc), ctypes.POINTER(ctypes.c_int64)]
     L.dgdiff_resolve_tile.restype = _i32
     L.dgdiff_resolve_tile.argtypes = [_i32, _i32, _i64, _i32, ctypes.POINTER(dg_tile)]
+    L.dg_ubench_run.restype = _i32
+    L.dg_ubench_run.argtypes = [ctypes.POINTER(dg_ubench_desc), ctypes.POINTER(ctypes.c_void_p), _vp, _vp]
+    L.perf_ubench_count.restype = _i32
+    L.perf_ubench_count.argtypes = [ctypes.POINTER(dg_ubench_desc), ctypes.POINTER(ctypes.c_int64)]
+    L.dgdiff_resolve_backward.restype = _i32
+    L.dgdiff_resolve_backward.argtypes = [_i32, _i32, _i64, _i32, ctypes.POINTER(dg_tile),
+                                          ctypes.POINTER(dg_tile)]
     _dp = ctypes.POINTER(ctypes.c_double)
     L.perf_model_fit.restype = _i32
     L.perf_model_fit.argtypes = [_i32, _i32, _dp, _dp, _i32, _dp, _dp, ctypes.POINTER(_i32), _dp]
@@ -255,13 +274,13 @@ def feature_names():
     return [L.perf_feature_name(k).decode() for k in range(L.perf_feature_count())]
 
 
-def perf_features_count(kernel, dtype, n0, nunit=0, nmat=0, tile=None, num_cu=0):
-    """Exact operation counts of one launch (numpy int64 array, feature_names() order)."""
+def perf_features_count(kernel, dtype, n0, nunit=0, nmat=0, tile=None, num_cu=0, workgroups=0):
+    """Exact operation counts of one launch (numpy int64 array, feature_names() order).
+    kernel: dg, stencil, matmul, empty, bwd_u, bwd_d, quant, batched, batched_pool."""
     import numpy as np
     L = lib()
     d = perf_kernel_desc()
-    d.kernel = {"dg": DG_K_DGDIFF, "stencil": DG_K_STENCIL5, "matmul": DG_K_MATMUL,
-                "empty": DG_K_EMPTY}[kernel]
+    d.kernel = _KERNELS[kernel]
     d.dtype = _DT[dtype]
     d.n0 = int(n0)
     d.nunit = int(nunit)
@@ -271,9 +290,76 @@ def perf_features_count(kernel, dtype, n0, nunit=0, nmat=0, tile=None, num_cu=0)
             *[int(tile.get(k, 0)) for k in ("elems_per_wave", "waves", "groups_per_cu", "d_panels", "flags")])
         d.tile = t
     d.num_cu = int(num_cu)
+    d.workgroups = int(workgroups)
     out = np.zeros(L.perf_feature_count(), dtype=np.int64)
     check(L.perf_features_count(ctypes.byref(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
     return out
+
+
+def _ub_desc(kind, n, a=0, b=0, dtype="f32", tile=None, num_cu=0):
+    d = dg_ubench_desc()
+    d.kind = UBENCH[kind]
+    d.dtype = _DT[dtype]
+    d.n = int(n)
+    d.a = int(a)
+    d.b = int(b)
+    if tile is not None:
+        d.tile = dg_tile(*[int(tile.get(k, 0)) for k in ("elems_per_wave", "waves", "groups_per_cu", "d_panels",
+                                                       "flags")])
+    d.num_cu = int(num_cu)
+    return d
+
+
+def dg_ubench_run(kind, n, inputs, out, a=0, b=0, dtype="f32", tile=None, stream=None):
+    """Launch a measurement kernel (dg_ubench_run): inputs a list of device
+    tensors, out a device tensor."""
+    d = _ub_desc(kind, n, a, b, dtype, tile)
+    arr = (ctypes.c_void_p * max(1, len(inputs)))(*[t.data_ptr() for t in inputs])
+    check(lib().dg_ubench_run(ctypes.byref(d), arr, _ptr(out), _stream(stream)))
+    return out
+
+
+def perf_ubench_count(kind, n, a=0, b=0, dtype="f32", tile=None, num_cu=0):
+    """Counted features of one measurement-kernel launch (feature_names() order)."""
+    import numpy as np
+    d = _ub_desc(kind, n, a, b, dtype, tile, num_cu)
+    out = np.zeros(lib().perf_feature_count(), dtype=np.int64)
+    check(lib().perf_ubench_count(ctypes.byref(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return out
+
+
+def _tile_dict(t):
+    return {k: getattr(t, k) for k in ("elems_per_wave", "waves", "groups_per_cu", "d_panels", "flags")}
+
+
+def resolve_backward(dtype, nmat, nelem, nunit):
+    """Launch shapes of dgdiff_backward's grad_u and grad_D steps (GPU)."""
+    tu, td = dg_tile(), dg_tile()
+    check(lib().dgdiff_resolve_backward(_DT[dtype], nmat, nelem, nunit, ctypes.byref(tu), ctypes.byref(td)))
+    return _tile_dict(tu), _tile_dict(td)
+
+
+def batched_counts(plan_info, num_cu=0):
+    """Counted features of a whole batched launch from dgdiff_plan_info's
+    per-order report ({p: info}): the orders' shares summed, the GEMM pool's
+    fixed cost added when an order runs GEMM tiles, one launch."""
+    import numpy as np
+    tot = None
+    grid = sum(int(i["workgroups"]) for i in plan_info.values() if int(i["count"]) > 0)
+    pool = False
+    for p, i in plan_info.items():
+        if int(i["count"]) == 0:
+            continue
+        c = perf_features_count("batched", "f32", int(i["count"]), (int(p) + 1) ** 3, 3, i["tile"], num_cu,
+                                int(i["workgroups"]))
+        pool = pool or bool(int(i["tile"]["flags"]) & DG_TILE_BATCH_GEMM)
+        tot = c if tot is None else tot + c
+    if tot is None:
+        return None
+    if pool:
+        tot = tot + perf_features_count("batched_pool", "f32", grid)
+    tot[0] = 1
+    return np.asarray(tot)
 
 
 def resolve_tile(dtype, nmat, nelem, nunit, tile=None):

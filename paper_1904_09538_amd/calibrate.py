@@ -54,10 +54,14 @@ GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0, "seri
          "gst_dg_out_unal": 1,
          "gld_st_u": 1, "gst_st_res": 1, "gld_mm_ab": 1, "gst_mm_c": 1,
          "lds_bytes": 2, "mfma_f64": 2, "mfma_f32": 2, "mfma_bf16": 2, "mfma_fp8": 2,
-         "valu_f32": 2, "valu_f64": 2}
+         "valu_f32": 2, "valu_f64": 2, "gld_ws": 1, "gst_ws": 1, "gld_idx": 1, "gld_ub": 1, "gst_ub": 1,
+         "gld_ub_strided": 1}
 # the paper's choice: the overlap model for DG and matmul, the linear model for
-# the stencil (little overlap observed there)
-KIND = {"dg": "overlap", "stencil": "linear", "matmul": "overlap"}
+# the stencil (little overlap observed there); the batched launch and the
+# adjoint are contractions like DG (overlap), the quantiser a streaming pass
+# like the stencil (linear)
+KIND = {"dg": "overlap", "stencil": "linear", "matmul": "overlap", "batched": "overlap",
+        "bwd": "overlap", "quant": "linear"}
 MODELS = {
     "dg": ["launch", "workgroups", "wave_tiles", "serial_steps", "lat_steps", "gld_dg_u", "gld_dg_u_unal",
            "gld_dg_u_l2",
@@ -67,6 +71,17 @@ MODELS = {
     "stencil": ["launch", "workgroups", "serial_steps", "gld_st_u", "gst_st_res", "lds_bytes", "valu_f32"],
     "matmul": ["launch", "workgroups", "serial_steps", "barrier_x_wg", "gld_mm_ab", "gst_mm_c",
                "lds_bytes", "mfma_f32"],
+    # one order alone in a batched launch, on the body that runs it
+    "batched": ["launch", "workgroups", "wave_tiles", "serial_steps", "lat_steps", "barrier_x_wg", "gld_idx",
+                "gld_dg_u_unal", "gld_dg_u_l2", "gld_dg_d", "gst_dg_out_unal", "lds_bytes", "mfma_f32",
+                "valu_f32"],
+    # the adjoint's two steps (grad_u on the GEMM or the contraction kernel;
+    # grad_D's split partials and reductions)
+    "bwd": ["launch", "workgroups", "serial_steps", "lat_steps", "barrier_x_wg", "gld_dg_u", "gld_dg_u_unal",
+            "gld_dg_u_l2", "gld_dg_d", "gld_ws", "gst_ws", "gst_dg_out", "gst_dg_out_unal", "lds_bytes",
+            "mfma_f32", "valu_f32"],
+    "quant": ["launch", "workgroups", "serial_steps", "gld_dg_u", "gld_dg_u_unal", "gst_dg_out",
+              "gst_dg_out_unal", "gld_ws", "gst_ws", "lds_bytes", "valu_f32"],
 }
 
 
@@ -116,6 +131,134 @@ def empty_variants(quick=False):
     return [{"family": "empty", "wgs": w} for w in (16, 64, 256, 1024, 4096, 16384, 65536)]
 
 
+def batched_variants(quick=False):
+    """One order alone in a batched launch: order 1 on its one-element-per-
+    thread body and on resident panels, orders 2..5 on resident panels (two
+    column-block counts, and half the operator panels per work-group), orders
+    4 and 5 also on GEMM tiles, orders 6 and 7 on GEMM tiles."""
+    out = []
+    for p in range(1, 8):
+        n = (p + 1) ** 3
+        sizes = [14, 16, 18, 20] if p <= 5 else [13, 15, 17]
+        if quick:
+            sizes = sizes[::2]
+        if p == 1:
+            shapes = [None, {"elems_per_wave": 16}, {"elems_per_wave": 32}]
+        elif p <= 5:
+            kq = 4 * -(-(-(-n // 4)) // 4)
+            max_ppg = (80 * 1024) // (16 * (4 * kq + 4) * 4)
+            panels = 3 * -(-n // 16)
+            shapes = [{"elems_per_wave": 16}, {"elems_per_wave": 32},
+                      {"elems_per_wave": 16, "d_panels": max(1, min(max_ppg, panels) // 2)}]
+            if p >= 4:
+                shapes.append({"flags": 4})
+        else:
+            shapes = [None]
+        for sz in sizes:
+            for t in shapes:
+                out.append({"family": "batched", "p": p, "nunit": n, "nelem": 1 << sz, "tile": t})
+    return out
+
+
+def bwd_variants(quick=False):
+    """The adjoint's steps alone (grad_u, grad_D), FP32, orders 2..5."""
+    out = []
+    for p in range(2, 6):
+        sizes = [14, 16, 18, 19] if not quick else [14, 18]
+        for sz in sizes:
+            for step in ("u", "d"):
+                out.append({"family": "bwd", "p": p, "nunit": (p + 1) ** 3, "nelem": 1 << sz, "step": step})
+    return out
+
+
+def quant_variants(quick=False):
+    """The quantiser: per-row scales (BF16, FP8) over row lengths of the DG
+    orders and longer rows; one scale for a whole array (FP8)."""
+    out = []
+    for to in ("bf16", "fp8"):
+        for cols in (27, 64, 125, 216, 512, 2048):
+            for sz in ([14, 17, 20] if not quick else [14, 20]):
+                if cols * (1 << sz) > (1 << 28):
+                    continue
+                out.append({"family": "quant", "to": to, "cols": cols, "rows": 1 << sz, "per_row": 1})
+    for sz in (14, 17, 20):
+        out.append({"family": "quant", "to": "fp8", "cols": 216, "rows": 1 << sz, "per_row": 0})
+    return out
+
+
+def fresh_variants():
+    """Variants never measured while the feature sets and model forms were
+    chosen: sizes off the calibration grids (3 * 2^k elements, n between
+    grid points), inputs from a fresh seed.  Scored once with the models
+    fitted on every calibration row."""
+    out = []
+    for p in (2, 3, 4, 5):
+        for t in (dict(), dict(elems_per_wave=16), dict(elems_per_wave=32)):
+            out.append({"family": "dg", "p": p, "nunit": (p + 1) ** 3, "nelem": 3 << 18, "tile": t})
+    for t in (dict(), dict(elems_per_wave=16)):
+        out.append({"family": "dg", "p": 6, "nunit": 343, "nelem": 3 << 16, "tile": t})
+    out += [{"family": "stencil", "n": n} for n in (7168, 11264)]
+    out += [{"family": "matmul", "n": n} for n in (3328, 5632)]
+    for p, t in ((2, {"elems_per_wave": 16}), (2, {"elems_per_wave": 32}), (5, {"elems_per_wave": 16}),
+                 (5, {"flags": 4}), (1, None), (6, None)):
+        out.append({"family": "batched", "p": p, "nunit": (p + 1) ** 3, "nelem": 3 << 16, "tile": t})
+    for p in (3, 4):
+        for step in ("u", "d"):
+            out.append({"family": "bwd", "p": p, "nunit": (p + 1) ** 3, "nelem": 3 << 16, "step": step})
+    for to in ("bf16", "fp8"):
+        out.append({"family": "quant", "to": to, "cols": 343, "rows": 3 << 17, "per_row": 1})
+    return out
+
+
+SEED_FRESH = 8
+
+
+def micro_variants(quick=False):
+    """The microbenchmark calibration set (Section "Measurement Kernel Sets for
+    Evaluation"): each kernel varies one feature while the others stay fixed.
+    Global memory (16-byte streams with 1, 2, 4 inputs; 4-byte loads at
+    lane strides 1 and 32), FP32 fused multiply-adds, FP32 and BF16 matrix
+    instructions, LDS moves (4 and 16 bytes), barriers, and the local/global
+    overlap kernel (one global load, m LDS pairs, one global store)."""
+    out = []
+    sizes = [16, 18, 20, 22, 24] if not quick else [18, 22]
+    for nin in (1, 2, 4):
+        for sz in sizes:
+            out.append({"family": "micro", "kind": "stream", "n": 1 << sz, "a": nin, "b": 0, "dtype": "f32"})
+    for S in (1, 32):
+        for sz in (20, 22, 24):
+            out.append({"family": "micro", "kind": "strided", "n": 1 << sz, "a": S, "b": 0, "dtype": "f32"})
+    for nwg in (1024, 4096):
+        for it in (64, 256, 1024):
+            out.append({"family": "micro", "kind": "fma", "n": nwg, "a": it, "b": 0, "dtype": "f32"})
+            for dt in ("f32", "bf16"):
+                out.append({"family": "micro", "kind": "mfma", "n": nwg, "a": it, "b": 0, "dtype": dt})
+            for w in (1, 4):
+                out.append({"family": "micro", "kind": "lds", "n": nwg, "a": it, "b": w, "dtype": "f32"})
+            out.append({"family": "micro", "kind": "barrier", "n": nwg, "a": 4 * it, "b": 0, "dtype": "f32"})
+    for m in (0, 1, 2, 4, 6, 8, 12, 16, 24, 32, 48, 64):
+        out.append({"family": "micro", "kind": "overlap", "n": 1 << 22, "a": m, "b": 0, "dtype": "f32"})
+    return out
+
+
+def twin_variants(quick=False):
+    """Work-removed twins (Section "Measurement Workload Synthesis by Work
+    Removal Transformation") of the modelled kernels: the DG forward at each
+    order with the launch shapes of its calibration set at 2^18 and 2^20
+    elements (2^16, 2^18 for orders 6, 7), the stencil and matmul at three
+    sizes each."""
+    out = []
+    for v in dg_variants(quick):
+        big = v["p"] >= 6
+        if v["nelem"] in ((1 << 16, 1 << 18) if big else (1 << 18, 1 << 20)):
+            out.append({**v, "family": "twin", "of": "dg"})
+    for n in (2048, 8192, 16384):
+        out.append({"family": "twin", "of": "stencil", "n": n})
+    for n in (1024, 4096, 8192):
+        out.append({"family": "twin", "of": "matmul", "n": n})
+    return out
+
+
 # ------------------------------------------------------------------ timing
 
 def time_launch(fn, trials=60, warmup=5, flush=None):
@@ -142,7 +285,8 @@ def time_launch(fn, trials=60, warmup=5, flush=None):
             "kept": int(kept.size), "dropped": int(s.size - kept.size)}
 
 
-def measure(path, quick=False, trials=60, families=("dg", "stencil", "matmul", "empty")):
+def measure(path, quick=False, trials=60, families=("dg", "stencil", "matmul", "empty", "batched", "bwd",
+                                                    "quant", "micro", "twin")):
     import torch
 
     from . import _lib, inputs
@@ -207,9 +351,162 @@ def measure(path, quick=False, trials=60, families=("dg", "stencil", "matmul", "
             # pair then brackets GPU time only, not the host's launch latency
             tm = time_launch(lambda: _lib.dg_empty_launch(v["wgs"]), trials, flush=flush)
             emit({**v, "t": tm, "features": _lib.perf_features_count("empty", "f32", v["wgs"]).tolist()})
+    for fam, gen in (("batched", batched_variants), ("bwd", bwd_variants), ("quant", quant_variants),
+                     ("micro", micro_variants), ("twin", twin_variants)):
+        if fam in families:
+            for v in gen(quick):
+                r = measure_one(v, trials, flush, num_cu)
+                if r is not None:
+                    emit(r)
     meta = {"meta": True, "device": torch.cuda.get_device_name(0), "num_cu": num_cu,
             "feature_names": _lib.feature_names(), "trials": trials, "protocol": "cold",
             "seconds": time.time() - t_start}
+    with open(path, "w") as fh:
+        fh.write(json.dumps(meta) + "\n")
+        for r in rows:
+            fh.write(json.dumps(r) + "\n")
+    return meta, rows
+
+
+def measure_one(v, trials, flush, num_cu, seed=0):
+    """Time one variant of the batched, adjoint or quantiser families (or, for
+    the fresh set, any family) and count its features; None if the library
+    refuses the shape.  Inputs are drawn on the GPU from `seed` (their values
+    do not change the schedule)."""
+    import torch
+
+    from . import _lib, inputs
+
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    fam = v["family"]
+    try:
+        if fam == "dg":
+            n, E = v["nunit"], v["nelem"]
+            D = torch.from_numpy(inputs.gll_dmats(v["p"])).float().to(dev)
+            u = torch.rand((E, n), generator=gen, device=dev) * 2 - 1
+            out = torch.empty((3, E, n), device=dev)
+            tile = _lib.resolve_tile("f32", 3, E, n, v["tile"])
+            tm = time_launch(lambda: _lib.dgdiff_apply(D, u, out=out, tile=tile), trials, flush=flush)
+            return {**v, "tile": tile, "t": tm,
+                    "features": _lib.perf_features_count("dg", "f32", E, n, 3, tile, num_cu).tolist()}
+        if fam == "stencil":
+            n = v["n"]
+            ld = ((n + 2 + 63) // 64) * 64
+            ug = torch.rand((n + 2, ld), generator=gen, device=dev)
+            res = torch.empty((n, n), device=dev)
+            tm = time_launch(lambda: _lib.stencil5_apply(ug, res=res, n=n), trials, flush=flush)
+            return {**v, "t": tm, "features": _lib.perf_features_count("stencil", "f32", n).tolist()}
+        if fam == "matmul":
+            n = v["n"]
+            a = torch.randn((n, n), generator=gen, device=dev)
+            b = torch.randn((n, n), generator=gen, device=dev)
+            c = torch.empty((n, n), device=dev)
+            tm = time_launch(lambda: _lib.matmul_apply(a, b, c), trials, flush=flush)
+            return {**v, "t": tm,
+                    "features": _lib.perf_features_count("matmul", "f32", n, num_cu=num_cu).tolist()}
+        if fam == "batched":
+            p, E = v["p"], v["nelem"]
+            order = np.full(E, p, dtype=np.int8)
+            plan = _lib.BatchedPlan(order, tiles={p: v["tile"]} if v["tile"] else None)
+            Ds = {p: torch.from_numpy(inputs.gll_dmats(p)).float().to(dev)}
+            u = torch.rand(plan.total, generator=gen, device=dev) * 2 - 1
+            o = torch.empty((3, plan.total), device=dev)
+            tm = time_launch(lambda: plan.apply(Ds, u, out=o), trials, flush=flush)
+            info = {p: plan.info(p)}
+            return {**v, "shape": info[p]["tile"], "workgroups": info[p]["workgroups"], "t": tm,
+                    "features": _lib.batched_counts(info, num_cu).tolist()}
+        if fam == "bwd":
+            n, E = v["nunit"], v["nelem"]
+            D = torch.from_numpy(inputs.gll_dmats(v["p"])).float().to(dev)
+            u = torch.rand((E, n), generator=gen, device=dev) * 2 - 1
+            g = torch.randn((3, E, n), generator=gen, device=dev)
+            want_u = v["step"] == "u"
+            tu, td = _lib.resolve_backward("f32", 3, E, n)
+            tm = time_launch(lambda: _lib.dgdiff_backward(D, u, g, want_u=want_u, want_D=not want_u), trials,
+                             flush=flush)
+            f = (_lib.perf_features_count("bwd_u", "f32", E, n, 3, tu, num_cu) if want_u
+                 else _lib.perf_features_count("bwd_d", "f32", E, n, 3, td, num_cu))
+            return {**v, "shape": tu if want_u else td, "t": tm, "features": f.tolist()}
+        if fam == "micro":
+            k, n, a_, b_ = v["kind"], v["n"], v["a"], v["b"]
+            ins, out = [], None
+            if k == "stream":
+                ins = [torch.rand(4 * n, generator=gen, device=dev) for _ in range(a_)]
+                out = torch.empty(4 * n, device=dev)
+            elif k == "strided":
+                ins = [torch.rand(n * a_, generator=gen, device=dev)]
+                out = torch.empty(n, device=dev)
+            elif k in ("fma", "barrier"):
+                out = torch.empty(256 * n, device=dev)
+            elif k == "mfma":
+                out = torch.empty(1024 * n, device=dev)
+            elif k == "lds":
+                ins = [torch.rand(256 * n * b_, generator=gen, device=dev)]
+                out = torch.empty(256 * n * b_, device=dev)
+            elif k == "overlap":
+                ins = [torch.rand(4 * n, generator=gen, device=dev)]
+                out = torch.empty(4 * n, device=dev)
+            tm = time_launch(lambda: _lib.dg_ubench_run(k, n, ins, out, a=a_, b=b_, dtype=v["dtype"]), trials,
+                             flush=flush)
+            return {**v, "t": tm,
+                    "features": _lib.perf_ubench_count(k, n, a_, b_, v["dtype"], num_cu=num_cu).tolist()}
+        if fam == "twin":
+            if v["of"] == "dg":
+                n, E = v["nunit"], v["nelem"]
+                D = torch.rand((3, n, n), generator=gen, device=dev)
+                u = torch.rand((E, n), generator=gen, device=dev)
+                out = torch.empty((3, E, n), device=dev)
+                tile = _lib.resolve_tile("f32", 3, E, n, v["tile"])
+                tm = time_launch(lambda: _lib.dg_ubench_run("twin_dg", E, [D, u], out, a=n, b=3, tile=tile),
+                                 trials, flush=flush)
+                return {**v, "tile": tile, "t": tm,
+                        "features": _lib.perf_ubench_count("twin_dg", E, n, 3, tile=tile, num_cu=num_cu).tolist()}
+            n = v["n"]
+            if v["of"] == "stencil":
+                ld = ((n + 2 + 63) // 64) * 64
+                ug = torch.rand((n + 2, ld), generator=gen, device=dev)
+                res = torch.empty((n, n), device=dev)
+                tm = time_launch(lambda: _lib.dg_ubench_run("twin_stencil", n, [ug], res, a=ld, b=n), trials,
+                                 flush=flush)
+                return {**v, "t": tm, "features": _lib.perf_ubench_count("twin_stencil", n, ld, n).tolist()}
+            a = torch.rand((n, n), generator=gen, device=dev)
+            b = torch.rand((n, n), generator=gen, device=dev)
+            c = torch.empty((n, n), device=dev)
+            tm = time_launch(lambda: _lib.dg_ubench_run("twin_matmul", n, [a, b], c), trials, flush=flush)
+            return {**v, "t": tm,
+                    "features": _lib.perf_ubench_count("twin_matmul", n, num_cu=num_cu).tolist()}
+        if fam == "quant":
+            x = torch.rand((v["rows"], v["cols"]), generator=gen, device=dev) * 2 - 1
+            to = "bf16" if v["to"] == "bf16" else "e4m3"
+            tm = time_launch(lambda: _lib.dgdiff_quantize(x, to, per_row=bool(v["per_row"])), trials,
+                             flush=flush)
+            return {**v, "t": tm, "features": _lib.perf_features_count("quant", v["to"], v["rows"], v["cols"],
+                                                                        v["per_row"]).tolist()}
+    except _lib.DGError as err:
+        print(f"calibrate: skip {v}: {err}", file=sys.stderr)
+        return None
+    raise ValueError(fam)
+
+
+def measure_fresh(path, trials=60):
+    """Time the fresh held-out set (fresh_variants, inputs from SEED_FRESH)."""
+    import torch
+
+    from . import _lib
+
+    dev = torch.device("cuda:0")
+    flush = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+    num_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    rows = []
+    for v in fresh_variants():
+        r = measure_one(v, trials, flush, num_cu, seed=SEED_FRESH)
+        if r is not None:
+            rows.append(r)
+            print(json.dumps({k: r[k] for k in r if k != "features"}), flush=True)
+        torch.cuda.empty_cache()
+    meta = {"meta": True, "fresh": True, "feature_names": _lib.feature_names(), "seed": SEED_FRESH}
     with open(path, "w") as fh:
         fh.write(json.dumps(meta) + "\n")
         for r in rows:
@@ -344,10 +641,11 @@ def fit_family(meta, rows, family, L, kind=None, with_overhead_rows=True):
     The model form is the paper's (overlap for DG and matmul, linear for the
     stencil) unless the linear form has the lower cross-validation error on
     the training rows (the held-out rows take no part in the choice); both
-    held-out errors are reported.  The primary fit is unconstrained, as the
-    paper fits it; any negative weight is listed.  The same model fitted with
-    every cost weight >= 0 (the paper's interpretability criterion) is
-    reported under "nonneg"."""
+    held-out errors are reported.  The primary fit keeps every cost weight
+    >= 0 (the paper's interpretability criterion, Section "Assumptions and
+    Limitations": a cost that needs a negative weight is not one); the
+    unconstrained fit, as the paper computes it, is reported beside it under
+    "unconstrained" with its negative weights listed."""
     names = meta["feature_names"]
     cols = [names.index(f) for f in MODELS[family]]
     group = [GROUP[f] for f in MODELS[family]]
@@ -395,23 +693,81 @@ def fit_family(meta, rows, family, L, kind=None, with_overhead_rows=True):
     out = {"family": family, "kind": kind, "paper_kind": KIND[family], "cv_error": cv,
            "features": MODELS[family], "groups": group,
            "n_train": int(len(train)), "n_heldout": int(len(held))}
-    prim, pred = one(False)
+    prim, pred = one(True)
     out.update(prim)
-    out["nonneg"] = one(True)[0]
+    out["unconstrained"], upred = one(False)
     out["heldout"] = [{"variant": {k: fam[i][k] for k in fam[i] if k not in ("features", "t")},
                        "measured_s": float(t[i]), "predicted_s": float(pred[i])} for i in held]
-    if family == "dg":
+    if family in ("dg", "batched"):
         # launch shapes of one problem (order, element count), ranked by the
         # model fitted on the training rows
         out["ranking"] = ranking([(r["p"], r["nelem"]) for r in fam], pred, t)
+        out["unconstrained"]["ranking"] = ranking([(r["p"], r["nelem"]) for r in fam], upred, t)
+    return out
+
+
+def final_model(meta, rows, family, L, kind):
+    """The family's model in the chosen form fitted on every calibration row
+    (training and held-out) plus the empty-kernel rows, weights >= 0."""
+    names = meta["feature_names"]
+    cols = [names.index(f) for f in MODELS[family]]
+    group = [GROUP[f] for f in MODELS[family]]
+    use = [r for r in rows if r["family"] in (family, "empty")]
+    F = np.array([[r["features"][c] for c in cols] for r in use], dtype=np.float64)
+    t = np.array([r["t"]["mean"] for r in use])
+    lin = L.perf_model_fit(F, t, relative=True, nonneg=True)
+    if kind == "linear":
+        return {"kind": kind, "features": MODELS[family], "groups": group,
+                "params": [float(x) for x in lin["p"]], "edge": None}
+    fit = fit_overlap(L, F, t, group, lin["p"], True)
+    return {"kind": kind, "features": MODELS[family], "groups": group,
+            "params": [float(x) for x in fit["p"]], "edge": fit["edge"]}
+
+
+def predict_rows(model, names, rows, L):
+    cols = [names.index(f) for f in model["features"]]
+    F = np.array([[r["features"][c] for c in cols] for r in rows], dtype=np.float64)
+    if model["kind"] == "linear":
+        return L.perf_model_predict(F, model["params"])
+    return L.perf_model_predict_overlap(F, model["groups"], model["params"], model["edge"])
+
+
+def score_fresh(summary, cal_path, fresh_path):
+    """Score the fresh set once: each family's model, in the form chosen on
+    the calibration rows, fitted on all of them, predicts every fresh row.
+    MAPE, geomean and (DG, batched) the ranking of the launch shapes."""
+    from . import _lib
+    meta, rows = load(cal_path)
+    fmeta, frows = load(fresh_path)
+    if fmeta["feature_names"] != meta["feature_names"]:
+        raise ValueError("fresh rows were counted with other feature names")
+    out = {"seed": fmeta.get("seed"), "families": {}}
+    allp, allm = [], []
+    for fam, f in summary["families"].items():
+        fr = [r for r in frows if r["family"] == fam]
+        if not fr:
+            continue
+        model = final_model(meta, rows, fam, _lib, f["kind"])
+        pred = predict_rows(model, meta["feature_names"], fr, _lib)
+        meas = np.array([r["t"]["mean"] for r in fr])
+        ent = {"n": len(fr), "kind": model["kind"], "mape": mape(pred, meas), "geomean": geomean(pred, meas),
+               "rows": [{"variant": {k: r[k] for k in r if k not in ("features", "t")},
+                         "measured_s": float(m), "predicted_s": float(q)} for r, m, q in zip(fr, meas, pred)]}
+        if fam in ("dg", "batched"):
+            ent["ranking"] = ranking([(r["p"], r["nelem"]) for r in fr], pred, meas)
+        out["families"][fam] = ent
+        allp += list(pred)
+        allm += list(meas)
+    out["mape_all"] = mape(allp, allm) if allm else None
+    out["geomean_all"] = geomean(allp, allm) if allm else None
     return out
 
 
 # ------------------------------------------------------------ cross-kernel
 # The paper calibrates on kernels other than the one predicted (Section
 # "Results": microbenchmarks, then the application kernels).  Here the model
-# is fitted on the companion and empty kernels only and predicts the DG
-# variants.  Their tagged counts are summed into kernel-independent features
+# is fitted on the companion, empty, adjoint and quantiser kernels only and
+# predicts the DG forward variants.  Their tagged counts are summed into kernel-independent features
 # (global bytes loaded and stored, whatever the array or pattern), so what the
 # tags distinguish -- aligned vs unaligned rows, L2 re-reads by other operator
 # groups -- is invisible to this model by construction.
@@ -433,7 +789,7 @@ def generic_features(names, rows):
     return np.array([[sum(r["features"][i] for i in ix) for ix in idx] for r in rows], dtype=np.float64)
 
 
-def fit_cross(meta, rows, L, train=("stencil", "matmul", "empty"), target="dg"):
+def fit_cross(meta, rows, L, train=("stencil", "matmul", "empty", "bwd", "quant"), target="dg"):
     """Overlap model on the generic features, fitted on the `train` families,
     scored on every `target` row (non-negative fit, and the unconstrained one
     beside it)."""
@@ -460,7 +816,92 @@ def fit_cross(meta, rows, L, train=("stencil", "matmul", "empty"), target="dg"):
     return out
 
 
-def fit_all(path, kinds=None):
+# ------------------------------------------------------ microbenchmark calibration
+# The paper's protocol (Section "Measurement Kernel Sets for Evaluation"):
+# the model of a computation is calibrated on measurement kernels that do not
+# include it -- microbenchmarks, each exercising one feature, and the
+# work-removed twins of the computation, which measure its global-memory
+# access pattern alone -- and then predicts the computation.
+MICRO_EXTRA = ["gld_ub", "gst_ub", "gld_ub_strided", "valu_f32", "barrier_x_wg", "lds_bytes", "mfma_f32",
+               "mfma_bf16"]
+
+
+def micro_features(target):
+    """The target's own model features, plus the microbenchmarks' global-
+    memory, VALU and matrix features (zero for the target; they carry the
+    microbenchmarks' own costs)."""
+    return list(dict.fromkeys(MODELS[target] + MICRO_EXTRA))
+
+
+def fit_micro(meta, rows, L, target):
+    """Overlap model (weights >= 0) of `target` fitted on the microbenchmarks,
+    the target's twins and the empty kernels only; scored on every target
+    row.  The linear model on the same rows is reported beside it."""
+    names = meta["feature_names"]
+    feats = micro_features(target)
+    cols = [names.index(f) for f in feats]
+    group = [GROUP[f] for f in feats]
+    tr = [r for r in rows if r["family"] in ("micro", "empty") or
+          (r["family"] == "twin" and r.get("of") == target)]
+    tg = [r for r in rows if r["family"] == target]
+    if not tg or not any(r["family"] == "micro" for r in tr):
+        return None
+    Ftr = np.array([[r["features"][c] for c in cols] for r in tr], dtype=np.float64)
+    ttr = np.array([r["t"]["mean"] for r in tr])
+    Ftg = np.array([[r["features"][c] for c in cols] for r in tg], dtype=np.float64)
+    ttg = np.array([r["t"]["mean"] for r in tg])
+    lin = L.perf_model_fit(Ftr, ttr, relative=True, nonneg=True)
+    fit = fit_overlap(L, Ftr, ttr, group, lin["p"], True)
+    pred = L.perf_model_predict_overlap(Ftg, group, fit["p"], fit["edge"])
+    lpred = L.perf_model_predict(Ftg, lin["p"])
+    out = {"target": target, "features": feats, "groups": group, "n_train": len(tr), "n_target": len(tg),
+           "train_kinds": sorted({r.get("kind", r["family"]) if r["family"] == "micro" else
+                                  ("twin" if r["family"] == "twin" else r["family"]) for r in tr}),
+           "params": [float(x) for x in fit["p"]], "edge": fit["edge"],
+           "mape_train": mape(L.perf_model_predict_overlap(Ftr, group, fit["p"], fit["edge"]), ttr),
+           "mape": mape(pred, ttg), "geomean": geomean(pred, ttg),
+           "linear_mape": mape(lpred, ttg)}
+    if target == "dg":
+        out["ranking"] = ranking([(r["p"], r["nelem"]) for r in tg], pred, ttg)
+    return out
+
+
+def overlap_diagnosis(meta, rows, micro_fit):
+    """The paper's use of the work remover to decide on an overlap model: for
+    each DG problem with a twin measured at the same launch shape, the twin's
+    time (global memory alone), the on-chip time the microbenchmark rates
+    give for the kernel's LDS and matrix work, and the kernel's time.  A
+    kernel time near max(gmem, on-chip) means the two overlap; near their
+    sum, they do not.  overlap = (gmem + on_chip - t) / min(gmem, on_chip):
+    1 for complete overlap, 0 for none."""
+    if not micro_fit:
+        return None
+    names = meta["feature_names"]
+    p = dict(zip(micro_fit["features"], micro_fit["params"]))
+    onchip_feats = [f for f, g in zip(micro_fit["features"], micro_fit["groups"]) if g == 2]
+    key = lambda r: (r["p"], r["nelem"], json.dumps(r["tile"], sort_keys=True))  # noqa: E731
+    twins = {key(r): r for r in rows if r["family"] == "twin" and r.get("of") == "dg"}
+    out = []
+    for r in rows:
+        if r["family"] != "dg" or key(r) not in twins:
+            continue
+        f = dict(zip(names, r["features"]))
+        onchip = sum(p[k] * f[k] for k in onchip_feats)
+        gmem = twins[key(r)]["t"]["mean"]
+        t = r["t"]["mean"]
+        lo = min(gmem, onchip)
+        out.append({"p": r["p"], "nelem": r["nelem"], "tile": r["tile"], "t": t, "gmem_twin": gmem,
+                    "onchip_micro": onchip, "overlap": (gmem + onchip - t) / lo if lo > 0 else None})
+    if not out:
+        return None
+    per_order = {}
+    for d in out:
+        per_order.setdefault(d["p"], []).append(d["overlap"])
+    return {"rows": out, "overlap_median_per_order": {k: float(np.median([x for x in v if x is not None]))
+                                                      for k, v in sorted(per_order.items())}}
+
+
+def fit_all(path, kinds=None, fresh_path=None):
     from . import _lib
     meta, rows = load(path)
     out = {"device": meta["device"], "protocol": meta["protocol"], "families": {}}
@@ -474,6 +915,10 @@ def fit_all(path, kinds=None):
     out["mape_heldout_all"] = mape(allp, allm) if allm else None
     out["geomean_heldout_all"] = geomean(allp, allm) if allm else None
     out["cross"] = fit_cross(meta, rows, _lib)
+    out["micro"] = {t: fit_micro(meta, rows, _lib, t) for t in ("dg", "stencil", "matmul")}
+    out["overlap"] = overlap_diagnosis(meta, rows, out["micro"]["dg"])
+    if fresh_path:
+        out["fresh"] = score_fresh(out, path, fresh_path)
     return out
 
 
@@ -484,12 +929,16 @@ def main(argv=None):
     ap.add_argument("--json")
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--trials", type=int, default=60)
-    ap.add_argument("--families", default="dg,stencil,matmul,empty")
+    ap.add_argument("--families", default="dg,stencil,matmul,empty,batched,bwd,quant,micro,twin")
+    ap.add_argument("--fresh", help="measure the fresh held-out set into this file (with --measure), "
+                                    "or score it (with --fit)")
     a = ap.parse_args(argv)
     if a.measure:
         measure(a.measure, quick=a.quick, trials=a.trials, families=tuple(a.families.split(",")))
+        if a.fresh:
+            measure_fresh(a.fresh, trials=a.trials)
     if a.fit:
-        s = fit_all(a.fit)
+        s = fit_all(a.fit, fresh_path=a.fresh)
         for fam, f in s["families"].items():
             extra = (f"  (linear model: {100 * f['linear_mape_heldout']:.1f}%)"
                      if "linear_mape_heldout" in f else "")
@@ -497,6 +946,11 @@ def main(argv=None):
                   f"{100 * f['geomean_heldout']:.1f}%  train MAPE {100 * f['mape_train']:.1f}%  "
                   f"rank {f['rank']}/{len(f['features'])}  negative {f['negative_params']}{extra}")
         print(f"all families: held-out MAPE {100 * s['mape_heldout_all']:.1f}%")
+        if "fresh" in s:
+            print(f"fresh set (seed {s['fresh']['seed']}): MAPE {100 * s['fresh']['mape_all']:.1f}%")
+        for t, m in (s.get("micro") or {}).items():
+            if m:
+                print(f"microbenchmark-calibrated {t}: MAPE {100 * m['mape']:.1f}% (linear {100 * m['linear_mape']:.1f}%)")
         if a.json:
             with open(a.json, "w") as fh:
                 json.dump(s, fh, indent=1)

@@ -52,6 +52,77 @@ dg_status current_device(DeviceInfo* out) {
 
 using namespace dg;
 
+namespace dg {
+// Sizes of a measurement-kernel descriptor (shared by the launch and the counts).
+dg_status check_ubench(const dg_ubench_desc* d) {
+    if (d->n < 0) return fail(DG_EINVAL, "measurement kernel: negative size");
+    switch (d->kind) {
+        case DG_UB_STREAM:
+            if (d->a < 1 || d->a > 4) return fail(DG_EINVAL, "stream: 1..4 inputs");
+            return DG_OK;
+        case DG_UB_STRIDED:
+            if (d->a < 1) return fail(DG_EINVAL, "strided: stride >= 1");
+            return DG_OK;
+        case DG_UB_FMA:
+        case DG_UB_BARRIER:
+            if (d->a < 0 || d->n > INT32_MAX) return fail(DG_EINVAL, "loop trips >= 0, work-groups < 2^31");
+            return DG_OK;
+        case DG_UB_MFMA:
+            if (d->a < 0 || d->n > INT32_MAX) return fail(DG_EINVAL, "loop trips >= 0, work-groups < 2^31");
+            if (d->dtype != DG_F32 && d->dtype != DG_BF16) return fail(DG_EUNSUPPORTED, "mfma: F32 or BF16");
+            return DG_OK;
+        case DG_UB_LDS:
+            if (d->a < 0 || (d->b != 1 && d->b != 4) || d->n > INT32_MAX)
+                return fail(DG_EINVAL, "lds: trips >= 0, width 1 or 4");
+            return DG_OK;
+        case DG_UB_OVERLAP:
+            if (d->a < 0) return fail(DG_EINVAL, "overlap: m >= 0");
+            return DG_OK;
+        case DG_UB_TWIN_DG:
+            if (d->a < 1 || d->a > 512 || d->b < 1 || d->b > 8) return fail(DG_EUNSUPPORTED, "DG twin: sizes");
+            return DG_OK;
+        case DG_UB_TWIN_STENCIL:
+            if (d->n % 4 || d->a < d->n + 2 || d->a % 4 || d->b < d->n || d->b % 4)
+                return fail(DG_EUNSUPPORTED, "stencil twin: n and leading dimensions multiples of 4");
+            return DG_OK;
+        case DG_UB_TWIN_MATMUL:
+            return DG_OK;
+    }
+    return fail(DG_EINVAL, "unknown measurement kernel");
+}
+}  // namespace dg
+
+// Argument checks shared by both backward entry points; *done is set when
+// there is nothing to compute.
+static dg_status check_backward(const char* name, dg_dtype t, int32_t nmat, int64_t nelem,
+                                int32_t nunit, const void* D, const void* u, const void* g,
+                                void* grad_u, void* grad_D, void* ws, size_t ws_bytes, bool* done) {
+    const std::string fn(name);
+    if (t != DG_F32 && t != DG_F64) return fail(DG_EUNSUPPORTED, fn + ": FP32 or FP64 only");
+    if (nelem < 0 || nmat < 1 || nunit < 1) return fail(DG_EINVAL, fn + ": sizes must be positive");
+    if (nmat > 8 || nunit > 512) return fail(DG_EUNSUPPORTED, fn + ": nmat <= 8 and nunit <= 512");
+    if (!grad_u && !grad_D) {
+        *done = true;
+        return DG_OK;
+    }
+    if (nelem > 0 && (!g || (grad_u && !D) || (grad_D && !u)))
+        return fail(DG_EINVAL, fn + ": NULL input");
+    const size_t es = dtype_size(t);
+    const size_t nD = (size_t)nmat * nunit * nunit * es, nu = (size_t)nelem * nunit * es;
+    const size_t ng = (size_t)nmat * nelem * nunit * es;
+    if (grad_u && (overlaps(grad_u, nu, D, nD) || overlaps(grad_u, nu, u, nu) ||
+                   overlaps(grad_u, nu, g, ng) || overlaps(grad_u, nu, grad_D, nD) ||
+                   overlaps(grad_u, nu, ws, ws_bytes)))
+        return fail(DG_EINVAL, fn + ": grad_u overlaps another array");
+    if (grad_D && (overlaps(grad_D, nD, D, nD) || overlaps(grad_D, nD, u, nu) ||
+                   overlaps(grad_D, nD, g, ng) || overlaps(grad_D, nD, ws, ws_bytes)))
+        return fail(DG_EINVAL, fn + ": grad_D overlaps another array");
+    if (ws && (overlaps(ws, ws_bytes, D, nD) || overlaps(ws, ws_bytes, u, nu) ||
+               overlaps(ws, ws_bytes, g, ng)))
+        return fail(DG_EINVAL, fn + ": workspace overlaps an input");
+    return DG_OK;
+}
+
 extern "C" {
 
 const char* dg_last_error(void) { return g_last_error.c_str(); }
@@ -114,25 +185,10 @@ dg_status dgdiff_backward(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit
                           const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
                           size_t ws_bytes, dg_stream_t stream) {
     set_error("");
-    if (t != DG_F32 && t != DG_F64) return fail(DG_EUNSUPPORTED, "dgdiff_backward: FP32 or FP64 only");
-    if (nelem < 0 || nmat < 1 || nunit < 1) return fail(DG_EINVAL, "dgdiff_backward: sizes must be positive");
-    if (nmat > 8 || nunit > 512) return fail(DG_EUNSUPPORTED, "dgdiff_backward: nmat <= 8 and nunit <= 512");
-    if (!grad_u && !grad_D) return DG_OK;
-    if (nelem > 0 && (!g || (grad_u && !D) || (grad_D && !u)))
-        return fail(DG_EINVAL, "dgdiff_backward: NULL input");
-    const size_t es = dtype_size(t);
-    const size_t nD = (size_t)nmat * nunit * nunit * es, nu = (size_t)nelem * nunit * es;
-    const size_t ng = (size_t)nmat * nelem * nunit * es;
-    if (grad_u && (overlaps(grad_u, nu, D, nD) || overlaps(grad_u, nu, u, nu) ||
-                   overlaps(grad_u, nu, g, ng) || overlaps(grad_u, nu, grad_D, nD) ||
-                   overlaps(grad_u, nu, ws, ws_bytes)))
-        return fail(DG_EINVAL, "dgdiff_backward: grad_u overlaps another array");
-    if (grad_D && (overlaps(grad_D, nD, D, nD) || overlaps(grad_D, nD, u, nu) ||
-                   overlaps(grad_D, nD, g, ng) || overlaps(grad_D, nD, ws, ws_bytes)))
-        return fail(DG_EINVAL, "dgdiff_backward: grad_D overlaps another array");
-    if (ws && (overlaps(ws, ws_bytes, D, nD) || overlaps(ws, ws_bytes, u, nu) ||
-               overlaps(ws, ws_bytes, g, ng)))
-        return fail(DG_EINVAL, "dgdiff_backward: workspace overlaps an input");
+    bool done = false;
+    dg_status st = check_backward("dgdiff_backward", t, nmat, nelem, nunit, D, u, g, grad_u, grad_D,
+                                  ws, ws_bytes, &done);
+    if (st != DG_OK || done) return st;
     return launch_dg_backward(t, nmat, nelem, nunit, D, u, g, grad_u, grad_D, ws, ws_bytes,
                               reinterpret_cast<hipStream_t>(stream));
 }
@@ -149,6 +205,22 @@ dg_status stencil5_apply(dg_dtype t, int64_t n, const void* u, int64_t ld_u, voi
     if (overlaps(res, (size_t)n * ld_res * es, u, (size_t)(n + 2) * ld_u * es))
         return fail(DG_EINVAL, "stencil5_apply: res overlaps u");
     return launch_stencil5(t, n, u, ld_u, res, ld_res, reinterpret_cast<hipStream_t>(stream));
+}
+
+dg_status dg_ubench_run(const dg_ubench_desc* d, const void* const* in, void* out, dg_stream_t stream) {
+    set_error("");
+    if (!d) return fail(DG_EINVAL, "dg_ubench_run: NULL descriptor");
+    dg_status st = check_ubench(d);
+    if (st != DG_OK) return st;
+    if (d->n == 0) return DG_OK;
+    const int nin = d->kind == DG_UB_STREAM ? d->a
+                  : (d->kind == DG_UB_TWIN_DG || d->kind == DG_UB_TWIN_MATMUL) ? 2
+                  : (d->kind == DG_UB_STRIDED || d->kind == DG_UB_LDS || d->kind == DG_UB_OVERLAP ||
+                     d->kind == DG_UB_TWIN_STENCIL) ? 1 : 0;
+    if (!out || (nin && !in)) return fail(DG_EINVAL, "dg_ubench_run: NULL array");
+    for (int k = 0; k < nin; ++k)
+        if (!in[k]) return fail(DG_EINVAL, "dg_ubench_run: NULL input");
+    return launch_ubench(d, in, out, reinterpret_cast<hipStream_t>(stream));
 }
 
 dg_status dg_empty_launch(int64_t workgroups, dg_stream_t stream) {

@@ -73,6 +73,7 @@ struct LpPlan {
     size_t panel_bytes, smem;
 };
 int lp_format(dg_dtype in_t, const dg_tile* tile);
+bool lp_pair_ok(const LpPlan& P, int nunit, bool vec_out);
 dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_tile* tile, int per_cu,
                        int num_cu, LpPlan* P);
 dg_status resolve_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nunit, dg_tile* tile);
@@ -83,22 +84,43 @@ dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nun
                                  const float* inv_su, const dg_tile* tile, hipStream_t s);
 
 size_t backward_workspace_bytes(dg_dtype t, int nmat, int64_t nelem, int nunit);
+dg_status resolve_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_tile* tu, dg_tile* td);
 dg_status launch_dg_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D,
                              const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
                              size_t ws_bytes, hipStream_t s);
 
+// Launch shape of dgdiff_quantize (a pure function of the sizes; shared with
+// the feature counter): kShortRows = rows of at most 1024 values in
+// registers, nv 4-value vectors per lane, four rows per wave and step;
+// kRows = one wave per longer row; kGlobal = FP8 with one scale for the
+// whole array (init, grid-wide maximum, encode, final: four launches).
+struct QuantPlan {
+    enum Kind { kShortRows, kRows, kGlobal } kind;
+    int nv;
+    int64_t blocks;  // 256-thread work-groups of the main kernel(s)
+    int64_t rows, cols;
+};
+QuantPlan quant_plan(int fp8, int64_t rows, int64_t cols, int per_row);
 dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, const float* x,
                           void* q, float* inv_scale, hipStream_t s);
 
+// work = false: the work-removed twin of the vector path
 dg_status launch_stencil5(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,
-                          int64_t ld_res, hipStream_t s);
+                          int64_t ld_res, hipStream_t s, bool work = true);
 bool stencil5_vector_ok(dg_dtype t, int64_t n, const void* u, int64_t ld_u, const void* res,
                         int64_t ld_res);
 int stencil5_rows_per_strip(int64_t n);
 
 dg_status launch_empty(int64_t workgroups, hipStream_t s);
 
-dg_status launch_matmul(int64_t n, const void* a, const void* b, void* c, hipStream_t s);
+// Measurement kernels (ubench.hip).  The stream kernel's grid: at most this
+// many 256-thread work-groups, grid-stride beyond.
+constexpr int64_t kUbStreamBlocks = 8192;
+dg_status launch_ubench(const dg_ubench_desc* d, const void* const* in, void* out, hipStream_t s);
+dg_status check_ubench(const dg_ubench_desc* d);
+
+// work = false: the work-removed twin (global-memory accesses only)
+dg_status launch_matmul(int64_t n, const void* a, const void* b, void* c, hipStream_t s, bool work = true);
 bool matmul_vector_ok(int64_t n, const void* a, const void* b, const void* c);
 
 }  // namespace dg

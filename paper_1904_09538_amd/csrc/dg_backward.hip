@@ -30,8 +30,8 @@ using namespace kern;
 
 // ------------------------------------------------------------------ grad_D
 
-constexpr int GT = 128;     // output tile (rows i x cols j): all of i and j up to nunit 128
-constexpr int GK = 16;      // elements per LDS chunk
+constexpr int GT = kBwdTile;    // output tile (rows i x cols j): all of i and j up to nunit 128
+constexpr int GK = kBwdChunk;   // elements per LDS chunk
 
 struct GdArgs {
     const void* g;
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) grad_d_reduce_kernel(const T* __restrict_
 
 // Partials are summed in two fixed-order stages (groups of kRedGroup splits,
 // then the group sums), so the result does not depend on scheduling.
-constexpr int64_t kRedGroup = 16;
+constexpr int64_t kRedGroup = kBwdRedGroup;
 
 template <typename T>
 __global__ void __launch_bounds__(256) grad_d_reduce_groups_kernel(const T* __restrict__ ws,
@@ -194,38 +194,31 @@ __global__ void __launch_bounds__(256) grad_d_reduce_groups_kernel(const T* __re
     ws2[(int64_t)blockIdx.y * count + idx] = s;
 }
 
-struct SplitPlan {
-    int64_t nsplit;
-    int64_t split_len;
-    int64_t ngroups;  // ceil(nsplit / kRedGroup)
-};
-
-// As many splits as make one full round of resident work-groups (the
-// kernel's occupancy on the current device): a second, partial round would
-// leave most of the GPU idle at the end.
+// Resident work-groups per CU of the split-partial kernel on the current device.
 template <typename T>
-dg_status plan_splits(int nmat, int64_t nelem, int nunit, SplitPlan* sp) {
+dg_status grad_d_per_cu(int* per_cu) {
+    DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        per_cu, reinterpret_cast<const void*>(grad_d_partial_kernel<T>), 256, 0));
+    *per_cu = std::max(*per_cu, 1);
+    return DG_OK;
+}
+
+template <typename T>
+dg_status plan_splits(int nmat, int64_t nelem, int nunit, SplitPlan* sp, size_t cap_bytes = 0) {
     DeviceInfo dev;
     dg_status st = current_device(&dev);
     if (st != DG_OK) return st;
     int per_cu = 1;
-    DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(grad_d_partial_kernel<T>), 256, 0));
-    per_cu = std::max(per_cu, 1);
-    const int64_t tiles = (int64_t)nmat * ceil_div(nunit, GT) * ceil_div(nunit, GT);
-    const int64_t target = (int64_t)per_cu * dev.num_cu;
-    int64_t ns = std::max<int64_t>(1, target / tiles);
-    ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(nelem, 256)));
-    const int64_t len = round_up(ceil_div(std::max<int64_t>(nelem, 1), ns), GK);
-    sp->nsplit = std::max<int64_t>(1, ceil_div(nelem, len));
-    sp->split_len = len;
-    sp->ngroups = ceil_div(sp->nsplit, kRedGroup);
+    st = grad_d_per_cu<T>(&per_cu);
+    if (st != DG_OK) return st;
+    if (!bwd_split_plan(nmat, nelem, nunit, per_cu, dev.num_cu, sizeof(T), cap_bytes, sp))
+        return fail(DG_EUNSUPPORTED, "grad_D partials exceed the fixed scratch");
     return DG_OK;
 }
 
 template <typename T>
 dg_status launch_grad_d(int nmat, int64_t nelem, int nunit, const void* u, const void* g,
-                        void* grad_D, void* ws, size_t ws_bytes, hipStream_t s) {
+                        void* grad_D, void* ws, size_t ws_bytes, bool fit_ws, hipStream_t s) {
     const int64_t count = (int64_t)nmat * nunit * nunit;
     if (nelem == 0) {
         // empty sum: zeros, written by the reduce kernel with no partials
@@ -236,7 +229,7 @@ dg_status launch_grad_d(int nmat, int64_t nelem, int nunit, const void* u, const
         return DG_OK;
     }
     SplitPlan sp;
-    dg_status st = plan_splits<T>(nmat, nelem, nunit, &sp);
+    dg_status st = plan_splits<T>(nmat, nelem, nunit, &sp, fit_ws ? ws_bytes : 0);
     if (st != DG_OK) return st;
     const size_t need = (size_t)(sp.nsplit + sp.ngroups) * count * sizeof(T);
     if (!ws || ws_bytes < need) return fail(DG_EINVAL, "dgdiff_backward: workspace too small");
@@ -437,7 +430,9 @@ dg_status launch_grad_u(int nmat, int64_t nelem, int nunit, const void* D, const
         if (nmat == 2) return launch<T, 2>(a, 1, kq, 1, tile, waves, one, s);
         return launch<T, 3>(a, 1, kq, 1, tile, waves, one, s);
     }
-    // one operator per launch; launches after the first accumulate
+    // one operator per launch; launches after the first accumulate, with the
+    // first launch's resident work-groups per CU (one schedule for all)
+    dg_tile tm = tile ? *tile : dg_tile{};
     for (int m = 0; m < nmat; ++m) {
         KArgs am = a;
         am.D = static_cast<const T*>(D) + (int64_t)m * nunit * nunit;
@@ -449,13 +444,65 @@ dg_status launch_grad_u(int nmat, int64_t nelem, int nunit, const void* D, const
         DG_KQ_LIST(X)
 #undef X
         if (!fn) return fail(DG_EUNSUPPORTED, "no grad_u kernel instance");
-        dg_status st = launch<T, 1>(am, 1, kq, 1, tile, waves, fn, s);
+        int per_cu = 0;
+        dg_status st = launch<T, 1>(am, 1, kq, 1, &tm, waves, fn, s, nullptr, &per_cu);
         if (st != DG_OK) return st;
+        tm.groups_per_cu = per_cu;
     }
     return DG_OK;
 }
 
 }  // namespace
+
+namespace {
+
+template <typename T>
+dg_status resolve_bwd(int nmat, int64_t nelem, int nunit, dg_tile* tu, dg_tile* td) {
+    DeviceInfo dev;
+    dg_status st = current_device(&dev);
+    if (st != DG_OK) return st;
+    if (td) {
+        *td = dg_tile{};
+        int per_cu = 1;
+        st = grad_d_per_cu<T>(&per_cu);
+        if (st != DG_OK) return st;
+        td->groups_per_cu = per_cu;
+    }
+    if (!tu) return DG_OK;
+    *tu = dg_tile{};
+    if (sizeof(T) == 4 && nunit >= kGradUGemmMin) {
+        int per_cu = 1;
+        DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(grad_u_gemm_kernel), 256, 0));
+        *tu = dg_tile{UT, 4, std::max(per_cu, 1), 0, DG_TILE_BATCH_GEMM};
+        return DG_OK;
+    }
+    const int kq = kq_for(nunit);
+    if (kq < 0) return fail(DG_EUNSUPPORTED, "nunit too large for the DG kernel");
+    const int nseg = grad_u_segments(sizeof(T), nmat, kq);
+    kern_fn fn = nseg == 1 ? pick_kernel<T, 1, 1>(kq)
+               : nseg == 2 ? pick_kernel<T, 1, 2>(kq) : pick_kernel<T, 1, 3>(kq);
+    if (!fn) return fail(DG_EUNSUPPORTED, "no grad_u kernel instance");
+    const int V = (int)(16 / sizeof(T));
+    const bool vec = nunit % V == 0 && (nseg == 1 || (nelem * nunit) % V == 0);
+    Plan P;
+    st = make_plan(sizeof(T), nseg, 1, nelem, nunit, kq, 1, 4, 0, 1, dev.num_cu, vec, &P);
+    if (st != DG_OK) return st;
+    DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
+    int per_cu = 1;
+    DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
+                                                              256, P.smem));
+    *tu = dg_tile{16, 4, std::max(per_cu, 1), P.ppg, 0};
+    return DG_OK;
+}
+
+}  // namespace
+
+dg_status resolve_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_tile* tu, dg_tile* td) {
+    return t == DG_F64 ? resolve_bwd<double>(nmat, nelem, nunit, tu, td)
+                       : resolve_bwd<float>(nmat, nelem, nunit, tu, td);
+}
 
 size_t backward_workspace_bytes(dg_dtype t, int nmat, int64_t nelem, int nunit) {
     if (nelem <= 0) return 0;
@@ -466,13 +513,16 @@ size_t backward_workspace_bytes(dg_dtype t, int nmat, int64_t nelem, int nunit) 
     return (size_t)(sp.nsplit + sp.ngroups) * nmat * nunit * nunit * dtype_size(t);
 }
 
-dg_status launch_dg_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D,
-                             const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
-                             size_t ws_bytes, hipStream_t s) {
+namespace {
+
+dg_status backward(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D, const void* u,
+                   const void* g, void* grad_u, void* grad_D, void* ws, size_t ws_bytes, bool fit_ws,
+                   hipStream_t s) {
     if (grad_D) {
-        dg_status st = t == DG_F32
-                           ? launch_grad_d<float>(nmat, nelem, nunit, u, g, grad_D, ws, ws_bytes, s)
-                           : launch_grad_d<double>(nmat, nelem, nunit, u, g, grad_D, ws, ws_bytes, s);
+        dg_status st =
+            t == DG_F32
+                ? launch_grad_d<float>(nmat, nelem, nunit, u, g, grad_D, ws, ws_bytes, fit_ws, s)
+                : launch_grad_d<double>(nmat, nelem, nunit, u, g, grad_D, ws, ws_bytes, fit_ws, s);
         if (st != DG_OK) return st;
     }
     if (grad_u && nelem > 0) {
@@ -481,6 +531,14 @@ dg_status launch_dg_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, con
         if (st != DG_OK) return st;
     }
     return DG_OK;
+}
+
+}  // namespace
+
+dg_status launch_dg_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D,
+                             const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
+                             size_t ws_bytes, hipStream_t s) {
+    return backward(t, nmat, nelem, nunit, D, u, g, grad_u, grad_D, ws, ws_bytes, false, s);
 }
 
 }  // namespace dg

@@ -460,6 +460,25 @@ static double eval_model(const int64_t* f, const double* cost, const int32_t* gr
     return c[0] + c[2] + d * 0.5 * (std::tanh(edge * d) + 1.0);
 }
 
+// Work-groups an order's share would have alone on the GPU with the
+// planner's rule (two work-groups per CU, a whole number of streams per
+// operator group, no more streams than tiles): the share its candidates are
+// priced at.
+static int64_t standalone_share(const dg_tile& t, int64_t count, int n, int nmat, int num_cu) {
+    int64_t unit = 8, ntiles;
+    if (t.flags & DG_TILE_BATCH_GEMM) {
+        ntiles = ceil_div((int64_t)nmat * n, (int64_t)GBM) * ceil_div(count, (int64_t)GBN);
+    } else if (t.elems_per_wave == 256) {
+        ntiles = ceil_div(count, (int64_t)256);
+    } else {
+        const int64_t panels = (int64_t)nmat * ceil_div(n, 16);
+        unit = 8 * ceil_div(panels, (int64_t)std::max(1, t.d_panels));
+        ntiles = ceil_div(count, (int64_t)t.elems_per_wave * 4);
+    }
+    int64_t blocks = std::max<int64_t>(unit, (2 * (int64_t)num_cu / unit) * unit);
+    return std::min<int64_t>(blocks, unit * std::max<int64_t>(1, ceil_div(ntiles, 8)));
+}
+
 dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const dg_tile* tiles,
                             const double* cost, const int32_t* group, double edge, BatchPlan** out) {
     if (nelem < 0 || !order || !out) return fail(DG_EINVAL, "dgdiff_plan_create: bad arguments");
@@ -510,9 +529,12 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
         const bool force_panels = tiles && tiles[p].elems_per_wave && !force_gemm;
         const bool use_valu = n == 8 && !force_gemm && !force_panels;
         const bool use_gemm = !use_valu && (n >= kGemmMinNunit || force_gemm);
-        const bool use_panels = !use_valu && !use_gemm;
         std::vector<dg_tile> cands;
-        if (tiles && tiles[p].elems_per_wave) {
+        if (use_valu) {
+            cands.push_back(dg_tile{256, 4, 2, 0, 0});
+        } else if (use_gemm) {
+            cands.push_back(dg_tile{GBN, 4, 1, GBM / 16, DG_TILE_BATCH_GEMM});
+        } else if (tiles && tiles[p].elems_per_wave) {
             dg_tile t = tiles[p];
             if (t.elems_per_wave != 16 && t.elems_per_wave != 32) {
                 delete P;
@@ -529,13 +551,13 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
             t.d_panels = (int)ceil_div(panels, ceil_div(panels, want));
             t.waves = 4;
             if (t.groups_per_cu <= 0) t.groups_per_cu = 2;
+            t.flags = 0;
             cands.push_back(t);
         } else {
             // operator-group counts reachable within the LDS budget (a few of
             // the smallest), each with balanced groups
-            // (for the other bodies the ranked shape only prices the order)
             for (int cb : {1, 2}) {
-                if (use_panels && variant_of(kq, cb) < 0) continue;
+                if (variant_of(kq, cb) < 0) continue;
                 std::set<int> ngs;
                 for (int ppg = max_ppg_for(cb); ppg >= 1 && ngs.size() < 5; --ppg)
                     ngs.insert((int)ceil_div(panels, ppg));
@@ -550,27 +572,41 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
                 }
             }
         }
-        // a fitted model may predict a negative time for a tiny launch, so the
-        // first scored candidate is taken as found whatever its sign
+        // Each candidate is priced as the body that runs it, standalone on the
+        // whole GPU: the share it would get alone (two work-groups per CU, no
+        // more streams than tiles).  A fitted model may predict a negative
+        // time for a tiny launch, so the first scored candidate is taken as
+        // found whatever its sign.
         double best = 0;
         bool found = false;
         for (const dg_tile& t : cands) {
             double pred = 0;
             if (cost) {
                 perf_kernel_desc d = {};
-                d.kernel = DG_K_DGDIFF;
+                d.kernel = DG_K_BATCHED;
                 d.dtype = DG_F32;
                 d.n0 = po.count;
                 d.nunit = n;
                 d.nmat = nmat;
                 d.tile = t;
                 d.num_cu = dev.num_cu;
+                d.workgroups = standalone_share(t, po.count, n, nmat, dev.num_cu);
                 int64_t f[PF_COUNT];
                 if (perf_features_count(&d, f) != DG_OK) continue;
+                if (t.flags & DG_TILE_BATCH_GEMM) {
+                    perf_kernel_desc q = {};
+                    q.kernel = DG_K_BATCHED_POOL;
+                    q.dtype = DG_F32;
+                    q.n0 = d.workgroups;
+                    int64_t fq[PF_COUNT];
+                    if (perf_features_count(&q, fq) != DG_OK) continue;
+                    for (int k = 0; k < PF_COUNT; ++k) f[k] += fq[k];
+                }
                 pred = eval_model(f, cost, group, edge);
             } else {
                 // no model: the smallest number of operator groups, one column block
-                pred = (double)ceil_div(panels, t.d_panels) + (t.elems_per_wave == 16 ? 0 : 0.5);
+                pred = t.d_panels > 0 ? (double)ceil_div(panels, t.d_panels) + (t.elems_per_wave == 16 ? 0 : 0.5)
+                                      : 0.0;
             }
             if (!found || pred < best) {
                 best = pred;
@@ -593,7 +629,6 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
         size_t lds;
         if (use_valu) {
             // order 1: one element per thread
-            po.tile = dg_tile{256, 4, 0, 0, 0};
             b.ppg = 1;
             b.ngroups = 1;
             b.cb = 1;
@@ -601,9 +636,7 @@ dg_status batch_plan_create(int64_t nelem, const int8_t* order, int nmat, const 
             b.ntiles = ceil_div(po.count, (int64_t)256);
             lds = 0;
         } else if (use_gemm) {
-            // large orders: GEMM tiling (GBM operator rows x GBN elements); the
-            // ranked resident-panel shape serves only as the cost prediction
-            po.tile = dg_tile{GBN, 4, 1, GBM / 16, DG_TILE_BATCH_GEMM};
+            // large orders: GEMM tiling (GBM operator rows x GBN elements)
             b.ppg = 1;
             b.ngroups = 1;
             b.cb = 1;

@@ -789,7 +789,7 @@ inline bool pipelined_loads(size_t tsize, int nunit, int kq, int cb, bool vec_ou
 // for the kernel launched).
 template <typename T, int NSEG>
 dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, int waves, kern_fn fn,
-                 hipStream_t s, kern_fn fn_pair = nullptr) {
+                 hipStream_t s, kern_fn fn_pair = nullptr, int* per_cu_used = nullptr) {
     if (!fn) return fail(DG_EUNSUPPORTED, "no DG kernel instance for this shape");
     DeviceInfo dev;
     dg_status st = current_device(&dev);
@@ -821,6 +821,7 @@ dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, in
     st = make_plan(sizeof(T), NSEG, out_slabs, a.nelem, a.nunit, kq, cb, waves,
                    tile ? tile->d_panels : 0, per_cu, dev.num_cu, src_vec_ok, &P);
     if (st != DG_OK) return st;
+    if (per_cu_used) *per_cu_used = per_cu;
     a.ntiles = P.ntiles;
     a.mblk = P.mblk;
     a.panels_total = P.panels_total;
@@ -881,6 +882,53 @@ inline int forward_waves(size_t tsize, int nunit, int kq, int cb, bool rows_alig
     const bool piped = rows_aligned && nunit % 32 == 0 && kq * cb <= 32;
     if (tsize == 4 && fits && (!rows_aligned || kq >= 32 || piped)) return 8;
     return 4;
+}
+
+// Split plan of grad_D (the backward's split-K GEMM over elements): a pure
+// function of the problem, the partial kernel's resident work-groups per CU
+// and the CU count (shared with the feature counter).  As many splits as make
+// one full round of resident work-groups -- a second, partial round would
+// leave most of the GPU idle at the end -- and at most one per 256 elements;
+// a non-zero cap_bytes bounds the workspace (partials plus group sums)
+// instead: fewer, longer splits.
+constexpr int kBwdTile = 128;     // output tile (rows i x cols j)
+constexpr int kBwdChunk = 16;     // elements per LDS chunk
+constexpr int64_t kBwdRedGroup = 16;  // splits summed per first-stage group
+
+struct SplitPlan {
+    int64_t nsplit;
+    int64_t split_len;  // elements per split (multiple of kBwdChunk)
+    int64_t ngroups;    // ceil(nsplit / kBwdRedGroup)
+};
+
+inline bool bwd_split_plan(int nmat, int64_t nelem, int nunit, int per_cu, int num_cu, size_t tsize,
+                           size_t cap_bytes, SplitPlan* sp) {
+    const int64_t tiles = (int64_t)nmat * ceil_div(nunit, kBwdTile) * ceil_div(nunit, kBwdTile);
+    const int64_t target = (int64_t)std::max(per_cu, 1) * num_cu;
+    int64_t ns = std::max<int64_t>(1, target / tiles);
+    ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(nelem, 256)));
+    if (cap_bytes) {
+        // nsplit + ceil(nsplit / kBwdRedGroup) partial tiles must fit
+        const int64_t count_bytes = (int64_t)nmat * nunit * nunit * (int64_t)tsize;
+        const int64_t fit = (int64_t)(cap_bytes / (size_t)count_bytes);
+        int64_t cap = fit;
+        while (cap > 0 && cap + ceil_div(cap, kBwdRedGroup) > fit) --cap;
+        if (cap < 1) return false;
+        ns = std::min(ns, cap);
+    }
+    const int64_t len = round_up(ceil_div(std::max<int64_t>(nelem, 1), ns), (int64_t)kBwdChunk);
+    sp->nsplit = std::max<int64_t>(1, ceil_div(nelem, len));
+    sp->split_len = len;
+    sp->ngroups = ceil_div(sp->nsplit, kBwdRedGroup);
+    return true;
+}
+
+// grad_u on the contraction kernel: the operator transposed, the nmat slabs
+// of g as contraction segments of one launch when an instance with that many
+// segments exists and its fragments fit the registers, else one launch per
+// operator (later launches accumulate).  Returns the segments per launch.
+inline int grad_u_segments(size_t tsize, int nmat, int kq) {
+    return (nmat <= 3 && (nmat == 1 || (size_t)nmat * kq * tsize <= 768)) ? nmat : 1;
 }
 
 }  // namespace kern

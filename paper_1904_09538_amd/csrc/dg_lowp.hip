@@ -395,7 +395,7 @@ dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_til
 
 // Paired stores (lp_panels) for rows of a multiple of 32 nodes written as
 // 16-byte vectors, with an even number of panels per group.
-static bool lp_pair_ok(const LpPlan& P, int nunit, bool vec_out) {
+bool lp_pair_ok(const LpPlan& P, int nunit, bool vec_out) {
     return vec_out && nunit % 32 == 0 && P.mblk % 2 == 0 && P.ppg % 2 == 0;
 }
 

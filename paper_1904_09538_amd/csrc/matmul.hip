@@ -69,10 +69,48 @@ __device__ inline void store_chunk(float* As, float* Bs, int t, const f32x4 (&ra
     reinterpret_cast<f32x4*>(brow)[1] = rb[1];
 }
 
-template <bool VEC>
+// WORK = false: the kernel with its on-chip work removed (the paper's
+// work-removal transformation, Section "Measurement Workload Synthesis by
+// Work Removal Transformation"): the same grid and the same global loads and
+// stores, every loaded value added into one register, that register stored
+// wherever the kernel stores a result; no LDS, no matrix-core work, no
+// barriers.  It measures this kernel's global-memory access pattern alone.
+template <bool VEC, bool WORK = true>
 __global__ void __launch_bounds__(256) matmul_kernel(const float* __restrict__ a,
                                                      const float* __restrict__ b,
                                                      float* __restrict__ c, int64_t n) {
+    if constexpr (!WORK) {
+        const int t = threadIdx.x;
+        const int lane = t & 63, wave = t >> 6, cl = lane & 15, g = lane >> 4;
+        const int64_t row0 = (int64_t)blockIdx.y * BM, col0 = (int64_t)blockIdx.x * BM;
+        float tgt = 0.f;
+        for (int64_t kc = 0; kc < ceil_div(n, BK); ++kc) {
+            f32x4 ra[2], rb[2];
+            load_chunk<VEC>(a, b, n, row0, col0, kc * BK, t, ra, rb);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tgt += ra[h][q] + rb[h][q];
+        }
+        const f32x4 v = {tgt, tgt, tgt, tgt};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t r = row0 + (wave >> 1) * 64 + i * 16 + cl;
+            if (r >= n) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t col = col0 + (wave & 1) * 64 + j * 16 + 4 * g;
+                if constexpr (VEC) {
+                    if (col < n) *reinterpret_cast<f32x4*>(c + r * n + col) = v;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (col + q < n) c[r * n + col + q] = tgt;
+                }
+            }
+        }
+        return;
+    }
     __shared__ __attribute__((aligned(16))) float As_[2][BM * LDK];  // [buf][row][k]
     __shared__ __attribute__((aligned(16))) float Bs_[2][BK * LDB];  // [buf][k][col]
     const int t = threadIdx.x;
@@ -149,16 +187,13 @@ bool matmul_vector_ok(int64_t n, const void* a, const void* b, const void* c) {
            reinterpret_cast<uintptr_t>(b) % 16 == 0 && reinterpret_cast<uintptr_t>(c) % 16 == 0;
 }
 
-dg_status launch_matmul(int64_t n, const void* a, const void* b, void* c, hipStream_t s) {
+dg_status launch_matmul(int64_t n, const void* a, const void* b, void* c, hipStream_t s, bool work) {
     dim3 grid((unsigned)ceil_div(n, BM), (unsigned)ceil_div(n, BM));
-    if (matmul_vector_ok(n, a, b, c))
-        hipLaunchKernelGGL(matmul_kernel<true>, grid, dim3(256), 0, s,
-                           static_cast<const float*>(a), static_cast<const float*>(b),
-                           static_cast<float*>(c), n);
-    else
-        hipLaunchKernelGGL(matmul_kernel<false>, grid, dim3(256), 0, s,
-                           static_cast<const float*>(a), static_cast<const float*>(b),
-                           static_cast<float*>(c), n);
+    const bool vec = matmul_vector_ok(n, a, b, c);
+    auto fn = vec ? (work ? matmul_kernel<true, true> : matmul_kernel<true, false>)
+                  : (work ? matmul_kernel<false, true> : matmul_kernel<false, false>);
+    hipLaunchKernelGGL(fn, grid, dim3(256), 0, s, static_cast<const float*>(a), static_cast<const float*>(b),
+                       static_cast<float*>(c), n);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
 }

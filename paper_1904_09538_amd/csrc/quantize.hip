@@ -11,8 +11,12 @@
 //
 // Rows up to 1024 values: one wave per row held in registers (below).  Longer
 // rows: one wave per row, a max-reduction over the row (order-independent,
-// exact), then the encode pass reading the row again.  The whole-array scale
-// runs one wave over everything; it is meant for small operator stacks.
+// exact), then the encode pass reading the row again.  One scale for the
+// whole array (FP8): the maximum over the whole grid (an integer atomic
+// maximum of |x|'s bit pattern, which orders non-negative floats, taken in
+// inv_scale[0] itself), then an encode pass over the grid, then inv_scale[0]
+// is replaced by 1/s.  Every path's launch shape is a pure function of the
+// sizes (quant_plan), shared with the feature counter.
 #include "common.hpp"
 
 namespace dg {
@@ -232,37 +236,143 @@ __global__ void __launch_bounds__(256) quantize_short_rows_kernel(int to_fp8, in
     }
 }
 
+// ---- one scale for the whole array (FP8): four launches on the stream.
+// inv_scale[0] holds the bit pattern of amax between the first and the last.
+
+__global__ void __launch_bounds__(64) quantize_global_init(uint32_t* amax_bits) {
+    if (threadIdx.x == 0) *amax_bits = 0u;
+}
+
+// Values i of the flat array taken by a thread: 4-value vectors 4*(gid + k*stride)
+// while a whole vector fits (the array is 16-byte aligned), then the tail
+// value by value (threads 0 .. N%4-1 of the grid).
+template <bool VEC>
+__global__ void __launch_bounds__(256) quantize_global_amax(const float* __restrict__ x, int64_t N,
+                                                            uint32_t* amax_bits) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    float amax = 0.0f;
+    int64_t tail = 0;
+    if (VEC) {
+        const int64_t nv = N / 4;
+        for (int64_t v = gid; v < nv; v += stride) {
+            f4v t;
+            __builtin_memcpy(&t, x + 4 * v, 16);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float a = fabsf(t[q]);
+                amax = a > amax ? a : amax;   // NaN entries do not take part
+            }
+        }
+        tail = 4 * nv;
+    }
+    for (int64_t i = tail + gid; i < N; i += stride) {
+        const float a = fabsf(x[i]);
+        amax = a > amax ? a : amax;
+    }
+    amax = wave_max(amax);
+    if ((threadIdx.x & 63) == 0) atomicMax(amax_bits, f32_bits(amax));
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(256) quantize_global_encode(const float* __restrict__ x, int64_t N,
+                                                              uint8_t* __restrict__ q,
+                                                              const uint32_t* __restrict__ amax_bits) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int ks = pow2_scale_exp_448(__builtin_bit_cast(float, *amax_bits));
+    const float sc = exp2_bits(ks);
+    int64_t tail = 0;
+    if (VEC) {
+        const int64_t nv = N / 4;
+        for (int64_t v = gid; v < nv; v += stride) {
+            f4v t;
+            __builtin_memcpy(&t, x + 4 * v, 16);
+            uint8_t b[4];
+            e4m3_rne4(t * sc, b);
+            __builtin_memcpy(q + 4 * v, b, 4);
+        }
+        tail = 4 * nv;
+    }
+    for (int64_t i = tail + gid; i < N; i += stride) q[i] = e4m3_rne(x[i] * sc);
+}
+
+__global__ void __launch_bounds__(64) quantize_global_final(uint32_t* amax_bits_then_inv) {
+    if (threadIdx.x == 0) {
+        const int ks = pow2_scale_exp_448(__builtin_bit_cast(float, *amax_bits_then_inv));
+        *reinterpret_cast<float*>(amax_bits_then_inv) = exp2_bits(-ks);
+    }
+}
+
+__global__ void __launch_bounds__(64) quantize_set_one(float* inv_scale) {
+    if (threadIdx.x == 0) *inv_scale = 1.0f;
+}
+
 }  // namespace
 
-dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, const float* x,
-                          void* q, float* inv_scale, hipStream_t s) {
-    if (!per_row) {
-        // one "row" covering everything
-        cols = rows * cols;
-        rows = 1;
+QuantPlan quant_plan(int fp8, int64_t rows, int64_t cols, int per_row) {
+    QuantPlan P = {};
+    P.rows = rows;
+    P.cols = cols;
+    if (!per_row && fp8) {
+        P.kind = QuantPlan::kGlobal;
+        P.blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(rows * cols, 1024), 2048));
+        return P;
     }
-    const int fp8 = to == DG_FP8E4M3 ? 1 : 0;
     if (cols <= 1024) {
         // four rows per wave and step; measured at 2^20 rows of 216: BF16 is
         // fastest with one step per wave, FP8 with four (65536 waves)
+        P.kind = QuantPlan::kShortRows;
+        P.nv = cols <= 256 ? 1 : cols <= 512 ? 2 : 4;
         const int64_t waves = std::min<int64_t>(ceil_div(rows, 4), fp8 ? 65536 : 262144);
-        const int64_t blocks = ceil_div(waves, 4);
-        if (cols <= 256)
-            hipLaunchKernelGGL(quantize_short_rows_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, fp8,
-                               rows, cols, x, q, inv_scale);
-        else if (cols <= 512)
-            hipLaunchKernelGGL(quantize_short_rows_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, fp8,
-                               rows, cols, x, q, inv_scale);
-        else
-            hipLaunchKernelGGL(quantize_short_rows_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, s, fp8,
-                               rows, cols, x, q, inv_scale);
+        P.blocks = ceil_div(waves, 4);
+    } else {
+        P.kind = QuantPlan::kRows;
+        P.blocks = ceil_div(std::min<int64_t>(rows, 65536), 4);
+    }
+    return P;
+}
+
+dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, const float* x,
+                          void* q, float* inv_scale, hipStream_t s) {
+    const int fp8 = to == DG_FP8E4M3 ? 1 : 0;
+    const QuantPlan P = quant_plan(fp8, rows, cols, per_row);
+    if (P.kind == QuantPlan::kGlobal) {
+        const int64_t N = rows * cols;
+        uint32_t* bits = reinterpret_cast<uint32_t*>(inv_scale);
+        const bool vec = reinterpret_cast<uintptr_t>(x) % 16 == 0 && reinterpret_cast<uintptr_t>(q) % 4 == 0;
+        hipLaunchKernelGGL(quantize_global_init, dim3(1), dim3(64), 0, s, bits);
+        if (vec) {
+            hipLaunchKernelGGL(quantize_global_amax<true>, dim3((unsigned)P.blocks), dim3(256), 0, s, x, N, bits);
+            hipLaunchKernelGGL(quantize_global_encode<true>, dim3((unsigned)P.blocks), dim3(256), 0, s, x, N,
+                               static_cast<uint8_t*>(q), bits);
+        } else {
+            hipLaunchKernelGGL(quantize_global_amax<false>, dim3((unsigned)P.blocks), dim3(256), 0, s, x, N, bits);
+            hipLaunchKernelGGL(quantize_global_encode<false>, dim3((unsigned)P.blocks), dim3(256), 0, s, x, N,
+                               static_cast<uint8_t*>(q), bits);
+        }
+        hipLaunchKernelGGL(quantize_global_final, dim3(1), dim3(64), 0, s, bits);
         DG_HIP_CHECK(hipGetLastError());
         return DG_OK;
     }
-    const int64_t waves = std::min<int64_t>(rows, 65536);
-    const int64_t blocks = ceil_div(waves, 4);
-    hipLaunchKernelGGL(quantize_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, fp8, rows, cols, x, q,
-                       inv_scale);
+    // per-row scales, or BF16 (whose codes need no scale): one inverse scale
+    // per row is written by the row kernels only when per_row is set
+    float* inv_rows = per_row ? inv_scale : nullptr;
+    if (P.kind == QuantPlan::kShortRows) {
+        if (P.nv == 1)
+            hipLaunchKernelGGL(quantize_short_rows_kernel<1>, dim3((unsigned)P.blocks), dim3(256), 0, s, fp8,
+                               rows, cols, x, q, inv_rows);
+        else if (P.nv == 2)
+            hipLaunchKernelGGL(quantize_short_rows_kernel<2>, dim3((unsigned)P.blocks), dim3(256), 0, s, fp8,
+                               rows, cols, x, q, inv_rows);
+        else
+            hipLaunchKernelGGL(quantize_short_rows_kernel<4>, dim3((unsigned)P.blocks), dim3(256), 0, s, fp8,
+                               rows, cols, x, q, inv_rows);
+    } else {
+        hipLaunchKernelGGL(quantize_rows_kernel, dim3((unsigned)P.blocks), dim3(256), 0, s, fp8, rows, cols, x,
+                           q, inv_rows);
+    }
+    if (!per_row && inv_scale) hipLaunchKernelGGL(quantize_set_one, dim3(1), dim3(64), 0, s, inv_scale);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;
 }

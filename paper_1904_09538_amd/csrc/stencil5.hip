@@ -48,9 +48,40 @@ __device__ inline Row6 load_row6(const float* __restrict__ row, int64_t j0, bool
     return r;
 }
 
+// WORK = false: the work-removed twin (same grid, the same global loads and
+// streaming stores; the loaded values summed into one register, which is
+// what every store writes; no shuffles, no arithmetic of the stencil).
+template <bool WORK = true>
 __global__ void __launch_bounds__(256) stencil5_vec_kernel(const float* __restrict__ u, int64_t ld_u,
                                                            float* __restrict__ res, int64_t ld_res,
                                                            int64_t n, int rows_per_strip) {
+    if constexpr (!WORK) {
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * 256 + 4 * lane;
+        const bool active = j0 < n;
+        const bool self_halo = (lane == 63) || (j0 + 4 >= n);
+        const int64_t i_lo = (int64_t)blockIdx.y * rows_per_strip;
+        const int64_t i_hi = min<int64_t>(n, i_lo + rows_per_strip);
+        if (i_lo >= n) return;
+        float tgt = 0.f;
+        auto take = [&](int64_t r) {
+            const float* row = u + r * ld_u;
+            if (active) {
+                const f32x4 q = *reinterpret_cast<const f32x4*>(row + j0);
+                tgt += q[0] + q[1] + q[2] + q[3];
+                if (self_halo) tgt += row[j0 + 4] + row[j0 + 5];
+            }
+        };
+        take(i_lo);
+        take(i_lo + 1);
+        for (int64_t i = i_lo; i < i_hi; ++i) {
+            take(i + 2);
+            const f32x4 o = {tgt, tgt, tgt, tgt};
+            if (active) __builtin_nontemporal_store(o, reinterpret_cast<f32x4*>(res + i * ld_res + j0));
+        }
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t j0 = ((int64_t)blockIdx.x * 4 + wave) * 256 + 4 * lane;
@@ -115,14 +146,15 @@ bool stencil5_vector_ok(dg_dtype t, int64_t n, const void* u, int64_t ld_u, cons
 }
 
 dg_status launch_stencil5(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,
-                          int64_t ld_res, hipStream_t s) {
+                          int64_t ld_res, hipStream_t s, bool work) {
     if (stencil5_vector_ok(t, n, u, ld_u, res, ld_res)) {
         const int R = stencil5_rows_per_strip(n);
         dim3 grid((unsigned)ceil_div(n, 1024), (unsigned)ceil_div(n, R));
-        hipLaunchKernelGGL(stencil5_vec_kernel, grid, dim3(256), 0, s,
+        hipLaunchKernelGGL(work ? stencil5_vec_kernel<true> : stencil5_vec_kernel<false>, grid, dim3(256), 0, s,
                            static_cast<const float*>(u), ld_u, static_cast<float*>(res), ld_res, n,
                            R);
     } else {
+        if (!work) return fail(DG_EUNSUPPORTED, "stencil twin: the vector path's layout only");
         dim3 grid((unsigned)ceil_div(n, 64), (unsigned)ceil_div(n, 4));
         if (t == DG_F32)
             hipLaunchKernelGGL(stencil5_scalar_kernel<float>, grid, dim3(256), 0, s,

@@ -25,12 +25,106 @@ def _synthetic_rows(L, law):
         rows.append({**v, "features": L.perf_features_count("matmul", "f32", v["n"]).tolist()})
     for v in C.empty_variants():
         rows.append({**v, "features": L.perf_features_count("empty", "f32", v["wgs"]).tolist()})
+    rows += _synthetic_new_family_rows(L, C.batched_variants() + C.bwd_variants() + C.quant_variants())
     for r in rows:
         f = dict(zip(names, r["features"]))
         used = C.MODELS.get(r["family"], ["launch", "workgroups"])
         r["t"] = {"mean": sum(law.get(k, 0.0) * f[k] for k in used)}
     return {"meta": True, "device": "synthetic", "num_cu": 256, "feature_names": names,
             "trials": 0, "protocol": "synthetic"}, rows
+
+
+def _batched_tile(v):
+    """A launch shape of the kind the planner reports for a single-order batch."""
+    p, n = v["p"], v["nunit"]
+    t = v.get("tile") or {}
+    if p >= 6 or t.get("flags"):
+        return dict(elems_per_wave=128, waves=4, groups_per_cu=1, d_panels=8, flags=4), 512
+    if p == 1 and not t:
+        return dict(elems_per_wave=256, waves=4), 512
+    panels = 3 * ((n + 15) // 16)
+    ppg = t.get("d_panels") or panels
+    ng = -(-panels // ppg)
+    return dict(elems_per_wave=t.get("elems_per_wave", 16), waves=4, groups_per_cu=2, d_panels=ppg), 8 * ng * 4
+
+
+def _synthetic_new_family_rows(L, variants):
+    rows = []
+    for v in variants:
+        if v["family"] == "batched":
+            tile, G = _batched_tile(v)
+            f = L.perf_features_count("batched", "f32", v["nelem"], v["nunit"], 3, tile, 256, G)
+            if tile.get("flags"):
+                f = f + L.perf_features_count("batched_pool", "f32", G)
+            rows.append({**v, "features": f.tolist()})
+        elif v["family"] == "bwd":
+            E, n = v["nelem"], v["nunit"]
+            if v["step"] == "u":
+                tu = (dict(elems_per_wave=128, waves=4, groups_per_cu=2, flags=4) if n >= 97
+                      else dict(elems_per_wave=16, waves=4, groups_per_cu=2, d_panels=(n + 15) // 16))
+                f = L.perf_features_count("bwd_u", "f32", E, n, 3, tu, 256)
+            else:
+                f = L.perf_features_count("bwd_d", "f32", E, n, 3, dict(groups_per_cu=2), 256)
+            rows.append({**v, "features": f.tolist()})
+        elif v["family"] == "quant":
+            f = L.perf_features_count("quant", v["to"], v["rows"], v["cols"], v["per_row"])
+            rows.append({**v, "features": f.tolist()})
+        else:
+            raise ValueError(v["family"])
+    return rows
+
+
+LAW = {"launch": 4e-6, "workgroups": 2e-9, "gld_dg_u": 1 / 5e12, "gld_dg_u_l2": 1 / 20e12,
+       "gld_dg_d": 1 / 30e12, "gst_dg_out": 1 / 6e12, "lds_bytes": 1 / 60e12,
+       "mfma_f32": 1 / 150e12, "gld_st_u": 1 / 5e12, "gst_st_res": 1 / 6e12,
+       "valu_f32": 1 / 50e12, "barrier_x_wg": 1e-9, "gld_mm_ab": 1 / 9e12, "gst_mm_c": 1 / 6e12,
+       "gld_dg_u_unal": 1 / 4e12, "gst_dg_out_unal": 1 / 5e12, "gld_idx": 1 / 8e12, "gld_ws": 1 / 7e12,
+       "gst_ws": 1 / 7e12, "serial_steps": 1e-7}
+
+
+def _write(path, meta, rows):
+    with open(path, "w") as fh:
+        fh.write(json.dumps(meta) + "\n")
+        for r in rows:
+            fh.write(json.dumps(r) + "\n")
+
+
+def test_new_families_and_fresh_set_recover_a_linear_law(tmp_path):
+    """Batched, adjoint and quantiser rows, and a fresh set of other sizes,
+    timed by one linear law: each family's fit reproduces its training rows,
+    and the final models (fitted on every calibration row) predict the fresh
+    rows."""
+    from paper_1904_09538_amd import _lib as L
+    meta, rows = _synthetic_rows(L, LAW)
+    cal = tmp_path / "cal.jsonl"
+    _write(cal, meta, rows)
+    names = meta["feature_names"]
+    fresh = []
+    for v in C.fresh_variants():
+        if v["family"] in ("batched", "bwd", "quant"):
+            fresh += _synthetic_new_family_rows(L, [v])
+        elif v["family"] == "dg":
+            tile = dict(v["tile"])
+            tile.setdefault("elems_per_wave", 16)
+            tile.update(waves=4, groups_per_cu=2, d_panels=min(4, 3 * ((v["nunit"] + 15) // 16)))
+            fresh.append({**v, "tile": tile, "features": L.perf_features_count(
+                "dg", "f32", v["nelem"], v["nunit"], 3, tile, 256).tolist()})
+        elif v["family"] == "stencil":
+            fresh.append({**v, "features": L.perf_features_count("stencil", "f32", v["n"]).tolist()})
+        else:
+            fresh.append({**v, "features": L.perf_features_count("matmul", "f32", v["n"]).tolist()})
+    for r in fresh:
+        f = dict(zip(names, r["features"]))
+        r["t"] = {"mean": sum(LAW.get(k, 0.0) * f[k] for k in C.MODELS[r["family"]])}
+    fp = tmp_path / "fresh.jsonl"
+    _write(fp, {"meta": True, "fresh": True, "feature_names": names, "seed": C.SEED_FRESH}, fresh)
+    kinds = {k: "linear" for k in C.MODELS}
+    s = C.fit_all(str(cal), kinds=kinds, fresh_path=str(fp))
+    for fam in ("batched", "bwd", "quant"):
+        assert s["families"][fam]["mape_train"] < 1e-6, fam
+    assert set(s["fresh"]["families"]) == {"dg", "stencil", "matmul", "batched", "bwd", "quant"}
+    for fam, f in s["fresh"]["families"].items():
+        assert f["mape"] < 0.02, (fam, f["mape"])
 
 
 def test_fit_recovers_linear_law(tmp_path):
@@ -102,8 +196,10 @@ def test_generic_features_sum_the_tags():
 
 def test_cross_kernel_fit_recovers_a_shared_law(tmp_path):
     """Times that follow one overlap law on the kernel-independent features
-    for every family: fitted on stencil, matmul and empty kernels, the model
-    predicts the DG variants it never saw.  The law switches sharply between
+    for every family: fitted on the stencil, matmul, empty, adjoint and
+    quantiser kernels, the model predicts the DG forward variants it never
+    saw (the adjoint's LDS-to-MFMA ratio differs from matmul's, which makes
+    the two costs separable).  The law switches sharply between
     memory and on-chip cost (edge 1e3): the stencil and matmul rows lie far on
     either side of the switch, so a soft switch would not be identifiable from
     them."""
@@ -120,3 +216,55 @@ def test_cross_kernel_fit_recovers_a_shared_law(tmp_path):
     assert x["nonneg"]["mape_train"] < 1e-6
     assert x["nonneg"]["mape"] < 1e-4, x["nonneg"]["mape"]
     np.testing.assert_allclose(x["nonneg"]["params"], p_true, rtol=1e-3)
+
+
+def _micro_rows(L):
+    rows = []
+    for v in C.micro_variants():
+        f = L.perf_ubench_count(v["kind"], v["n"], v["a"], v["b"], v["dtype"], num_cu=256)
+        rows.append({**v, "features": f.tolist()})
+    for v in C.twin_variants():
+        if v["of"] == "dg":
+            tile = dict(v["tile"])
+            tile.setdefault("elems_per_wave", 16)
+            tile.update(waves=4, groups_per_cu=2, d_panels=min(4, 3 * ((v["nunit"] + 15) // 16)))
+            f = L.perf_ubench_count("twin_dg", v["nelem"], v["nunit"], 3, tile=tile, num_cu=256)
+            rows.append({**v, "tile": tile, "features": f.tolist()})
+        elif v["of"] == "stencil":
+            n = v["n"]
+            rows.append({**v, "features": L.perf_ubench_count("twin_stencil", n, n + 64, n).tolist()})
+        else:
+            rows.append({**v, "features": L.perf_ubench_count("twin_matmul", v["n"], num_cu=256).tolist()})
+    return rows
+
+
+def test_microbenchmark_calibration_predicts_the_kernels(tmp_path):
+    """One overlap law for every kernel (its global-memory cost and its
+    on-chip cost switched by tanh): fitted on the microbenchmarks, the twins
+    and the empty kernels only, the model predicts the DG, stencil and matmul
+    rows it never saw; the overlap diagnosis finds complete overlap."""
+    from paper_1904_09538_amd import _lib as L
+    meta, rows = _synthetic_rows(L, {})
+    rows += _micro_rows(L)
+    names = meta["feature_names"]
+    law = {"launch": 4e-6, "workgroups": 2e-9, "barrier_x_wg": 1e-9, "serial_steps": 1e-7,
+           "gld_dg_u": 1 / 5e12, "gld_dg_u_unal": 1 / 4e12, "gld_dg_u_l2": 1 / 20e12, "gld_dg_d": 1 / 30e12,
+           "gst_dg_out": 1 / 6e12, "gst_dg_out_unal": 1 / 5e12, "gld_st_u": 1 / 5e12, "gst_st_res": 1 / 6e12,
+           "gld_mm_ab": 1 / 9e12, "gst_mm_c": 1 / 6e12, "gld_ub": 1 / 5.5e12, "gst_ub": 1 / 6.5e12,
+           "gld_ub_strided": 1 / 1e12, "lds_bytes": 1 / 60e12, "mfma_f32": 1 / 150e12,
+           "mfma_bf16": 1 / 2000e12, "valu_f32": 1 / 50e12}
+    for r in rows:
+        f = dict(zip(names, r["features"]))
+        c = [0.0, 0.0, 0.0]
+        for k, v in law.items():
+            c[C.GROUP[k]] += v * f[k]
+        r["t"] = {"mean": c[0] + max(c[1], c[2]) + 1e-9}
+    path = tmp_path / "cal.jsonl"
+    _write(path, meta, rows)
+    mrows = C.load(str(path))[1]
+    for target in ("dg", "stencil", "matmul"):
+        m = C.fit_micro(meta, mrows, L, target)
+        assert m["mape_train"] < 0.02, (target, m["mape_train"])
+        assert m["mape"] < 0.05, (target, m["mape"])
+    d = C.overlap_diagnosis(meta, mrows, C.fit_micro(meta, mrows, L, "dg"))
+    assert d["rows"] and all(x is None or x > 0.9 for x in d["overlap_median_per_order"].values())

@@ -114,6 +114,194 @@ def test_dg_counts_invariants(L):
         assert c["mfma_f32"] >= 2 * 3 * 64 * 64 * 5000   # at least the algorithmic flops
 
 
+# ------------------------------------------------------------------ adjoint, quantiser, batched
+
+
+def _both(orc, L, kernel, dtype, n0, nunit, nmat, tile, num_cu=256, workgroups=0):
+    """(library closed form, oracle walk); None where a side refuses the descriptor."""
+    try:
+        got = L.perf_features_count(kernel, dtype, n0, nunit, nmat, tile, num_cu, workgroups)
+    except L.DGError:
+        got = None
+    try:
+        ref = orc.features(kernel, dtype, n0, nunit, nmat, tile.get("elems_per_wave", 0), tile.get("waves", 0),
+                           tile.get("groups_per_cu", 0), tile.get("d_panels", 0), tile.get("flags", 0), num_cu,
+                           workgroups)
+    except ValueError:
+        ref = None
+    return got, ref
+
+
+def _bwd_u_cases():
+    cases = []
+    # the GEMM body: FP32 rows of 97 nodes or more, ragged element tiles and XCD groups
+    for n in (97, 125, 128, 129, 216, 343, 512):
+        for E in (1, 127, 128, 129, 1000, 128 * 9 + 5):
+            for M in (1, 3):
+                cases.append(("f32", n, M, E, dict(elems_per_wave=128, waves=4, groups_per_cu=2, flags=4)))
+    # the contraction body: one launch with nmat segments, or one per operator
+    rng = np.random.default_rng(5)
+    for dtype in ("f32", "f64"):
+        for n in (1, 5, 8, 27, 64, 96, 125, 216, 343, 512):
+            if dtype == "f32" and n >= 97:
+                continue
+            for M in (1, 2, 3, 4):
+                E = int(rng.choice([1, 17, 300, 4097]))
+                per_cu = int(rng.choice([1, 2, 3]))
+                ppg = int(rng.choice([1, 2, (n + 15) // 16]))
+                cases.append((dtype, n, M, E, dict(elems_per_wave=16, waves=4, groups_per_cu=per_cu,
+                                                   d_panels=ppg)))
+    return cases
+
+
+@pytest.mark.parametrize("case", _bwd_u_cases())
+def test_bwd_u_counts_match_brute_force(orc, L, case):
+    dtype, n, M, E, tile = case
+    got, ref = _both(orc, L, "bwd_u", dtype, E, n, M, tile)
+    assert (got is None) == (ref is None), (got is None, ref is None)
+    if got is not None:
+        np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n,M", [(1, 1), (8, 3), (27, 3), (64, 2), (125, 3), (129, 1), (216, 3), (512, 1)])
+@pytest.mark.parametrize("E", [0, 1, 16, 255, 256, 4097, 70001])
+@pytest.mark.parametrize("per_cu", [1, 2, 4])
+def test_bwd_d_counts_match_brute_force(orc, L, dtype, n, M, E, per_cu):
+    if n * n * M * E > 2e9:
+        pytest.skip("walk too long for the CPU suite (covered by smaller shapes)")
+    got, ref = _both(orc, L, "bwd_d", dtype, E, n, M, dict(groups_per_cu=per_cu))
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("to", ["bf16", "fp8"])
+@pytest.mark.parametrize("rows,cols", [(1, 1), (3, 5), (1000, 27), (4097, 64), (513, 125), (100, 216),
+                                       (70, 257), (9, 512), (33, 513), (5, 1024), (3, 1025), (2, 3001),
+                                       (1 << 18, 8), (300000, 4)])
+@pytest.mark.parametrize("per_row", [0, 1])
+def test_quant_counts_match_brute_force(orc, L, to, rows, cols, per_row):
+    got, ref = _both(orc, L, "quant", to, rows, cols, per_row, {})
+    np.testing.assert_array_equal(got, ref)
+
+
+def _batched_cases():
+    cases = []
+    # one element per thread (order 1)
+    for cnt in (1, 63, 64, 65, 256, 1000, 100003):
+        for G in (8, 16, 64, 512):
+            cases.append((cnt, 8, dict(elems_per_wave=256, waves=4), G))
+    # resident panels: every order, column blocks, panel groups, shares
+    rng = np.random.default_rng(11)
+    for p in (1, 2, 3, 4, 5):
+        n = (p + 1) ** 3
+        panels = 3 * ((n + 15) // 16)
+        for cb in (1, 2):
+            for _ in range(4):
+                ppg = int(rng.choice([1, 2, max(1, panels // 3), panels]))
+                ng = -(-panels // ppg)
+                G = 8 * ng * int(rng.choice([1, 2, 5]))
+                cnt = int(rng.choice([1, 15, 64, 129, 3000]))
+                cases.append((cnt, n, dict(elems_per_wave=16 * cb, waves=4, groups_per_cu=2, d_panels=ppg), G))
+    # GEMM tiles (orders 6, 7 and forced lower orders)
+    for p in (3, 5, 6, 7):
+        for cnt in (1, 127, 128, 129, 1031, 2500):
+            cases.append((cnt, (p + 1) ** 3, dict(elems_per_wave=128, waves=4, groups_per_cu=1, d_panels=8,
+                                                  flags=4), 16))
+    return cases
+
+
+@pytest.mark.parametrize("case", _batched_cases())
+def test_batched_counts_match_brute_force(orc, L, case):
+    cnt, n, tile, G = case
+    got, ref = _both(orc, L, "batched", "f32", cnt, n, 3, tile, 256, G)
+    assert (got is None) == (ref is None), (got is None, ref is None)
+    if got is not None:
+        np.testing.assert_array_equal(got, ref)
+
+
+def test_batched_pool_and_refusals(orc, L):
+    for G in (1, 8, 777):
+        np.testing.assert_array_equal(L.perf_features_count("batched_pool", "f32", G),
+                                      orc.features("batched_pool", "f32", G))
+    # a share that is not a whole number of streams per operator group, and
+    # one element per thread for a row of 27 nodes, are refused by both sides
+    for tile, n, G in ((dict(elems_per_wave=16, waves=4, groups_per_cu=2, d_panels=1), 64, 8),
+                       (dict(elems_per_wave=256, waves=4), 27, 8)):
+        got, ref = _both(orc, L, "batched", "f32", 100, n, 3, tile, 256, G)
+        assert got is None and ref is None
+
+
+def test_adjoint_quant_batched_invariants(L):
+    """What the method fixes whatever the schedule: every output value
+    written once, every input row read (at least) once, at least the
+    algorithmic matrix flops."""
+    names = L.feature_names()
+    E, n, M = 3001, 125, 3
+    cu = dict(zip(names, L.perf_features_count("bwd_u", "f32", E, n, M,
+                                               dict(elems_per_wave=128, waves=4, groups_per_cu=2, flags=4),
+                                               256)))
+    assert cu["gst_dg_out"] + cu["gst_dg_out_unal"] == E * n * 4
+    assert cu["gld_dg_u"] + cu["gld_dg_u_unal"] == M * E * n * 4
+    assert cu["mfma_f32"] >= 2 * M * n * n * E
+    cd = dict(zip(names, L.perf_features_count("bwd_d", "f32", E, n, M, dict(groups_per_cu=2), 256)))
+    assert cd["gst_dg_out_unal"] == M * n * n * 4
+    assert cd["mfma_f32"] >= 2 * M * n * n * E
+    assert cd["gld_ws"] == cd["gst_ws"]      # every partial written is read back once
+    for to, esz in (("bf16", 2), ("fp8", 1)):
+        q = dict(zip(names, L.perf_features_count("quant", to, 1 << 16, 216, 1)))
+        assert q["gst_dg_out"] == (1 << 16) * 216 * esz and q["gld_dg_u"] == (1 << 16) * 216 * 4
+    for cnt, n, tile, G in ((1000, 8, dict(elems_per_wave=256, waves=4), 64),
+                            (1000, 64, dict(elems_per_wave=16, waves=4, groups_per_cu=2, d_panels=12), 8),
+                            (1000, 343, dict(elems_per_wave=128, waves=4, flags=4), 8)):
+        b = dict(zip(names, L.perf_features_count("batched", "f32", cnt, n, 3, tile, 256, G)))
+        assert b["gst_dg_out_unal"] == 3 * cnt * n * 4
+        assert b["gld_dg_u_unal"] == cnt * n * 4
+        assert b["mfma_f32"] + b["valu_f32"] >= 2 * 3 * n * n * cnt
+
+
+# ------------------------------------------------------------------ measurement kernels
+
+def _ub_cases():
+    cases = [("stream", 1, 1, 0), ("stream", 1000, 3, 0), ("stream", 8192 * 256 + 5, 2, 0),
+             ("stream", 3 * 8192 * 256, 4, 0), ("strided", 1, 1, 0), ("strided", 1000, 33, 0),
+             ("fma", 3, 0, 0), ("fma", 2, 7, 0), ("mfma", 2, 5, 0), ("lds", 3, 0, 1), ("lds", 2, 9, 4),
+             ("barrier", 5, 17, 0), ("overlap", 1, 3, 0), ("overlap", 257, 0, 0), ("overlap", 1000, 12, 0),
+             ("twin_stencil", 1024, 1088, 1024), ("twin_stencil", 4100, 4160, 4100),
+             ("twin_matmul", 1000, 0, 0), ("twin_matmul", 1024, 0, 0)]
+    return cases
+
+
+@pytest.mark.parametrize("case", _ub_cases())
+def test_ubench_counts_match_brute_force(orc, L, case):
+    kind, n, a, b = case
+    for dtype in (("f32", "bf16") if kind == "mfma" else ("f32",)):
+        np.testing.assert_array_equal(L.perf_ubench_count(kind, n, a, b, dtype, num_cu=256),
+                                      orc.ubench_features(kind, n, a, b, dtype, num_cu=256))
+
+
+@pytest.mark.parametrize("nunit,E,tile", [
+    (27, 100003, dict(elems_per_wave=32, waves=8, groups_per_cu=3, d_panels=6)),
+    (64, 1 << 18, dict(elems_per_wave=16, waves=8, groups_per_cu=2, d_panels=12)),
+    (64, 5001, dict(elems_per_wave=32, waves=4, groups_per_cu=3, d_panels=12)),
+    (125, 70000, dict(elems_per_wave=32, waves=8, groups_per_cu=1, d_panels=12)),
+    (216, 4097, dict(elems_per_wave=16, waves=8, groups_per_cu=1, d_panels=11)),
+    (8, 999, dict(elems_per_wave=16, waves=4, groups_per_cu=4, d_panels=3))])
+def test_dg_twin_counts(orc, L, nunit, E, tile):
+    """The DG twin: the forward's global accesses and schedule exactly (walk
+    == closed form), no on-chip work, one add per loaded value."""
+    got = L.perf_ubench_count("twin_dg", E, nunit, 3, tile=tile, num_cu=256)
+    ref = orc.ubench_features("twin_dg", E, nunit, 3, tile=tile, num_cu=256)
+    np.testing.assert_array_equal(got, ref)
+    fwd = dict(zip(L.feature_names(), L.perf_features_count("dg", "f32", E, nunit, 3, tile, 256)))
+    tw = dict(zip(L.feature_names(), got))
+    for k in fwd:
+        if k.startswith("gld_") or k.startswith("gst_") or k in ("workgroups", "launch", "wave_tiles",
+                                                                   "serial_steps"):
+            assert tw[k] == fwd[k], k
+    assert tw["lds_bytes"] == tw["mfma_f32"] == tw["barrier_x_wg"] == 0
+    assert tw["valu_f32"] * 4 == sum(v for k, v in tw.items() if k.startswith("gld_"))
+
+
 # ------------------------------------------------------------------ model fit
 
 

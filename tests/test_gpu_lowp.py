@@ -62,6 +62,32 @@ def test_quantize_bit_exact(orc, ops, to, per_row):
 
 
 @pytest.mark.parametrize("to", ["bf16", "e4m3"])
+@pytest.mark.parametrize("rows,cols,misalign", [(1, 5, 0), (7, 13, 0), (4097, 216, 0), (3, 3001, 0),
+                                                (1 << 14, 343, 0), (7, 13, 1), (1000, 27, 1)])
+def test_quantize_one_scale_grid_wide(orc, ops, to, rows, cols, misalign):
+    """One scale for the whole array: the grid-wide maximum and encode passes
+    over many work-groups, 16-byte vectors with a value-by-value tail, and an
+    input 4 bytes off 16-byte alignment (value-by-value throughout)."""
+    rng = np.random.default_rng(rows + cols)
+    x = rng.uniform(-1, 1, size=(rows, cols)).astype(np.float32)
+    x[rows // 2, cols // 2] = 300.0          # the array's maximum, anywhere in the grid
+    base = torch.empty(rows * cols + misalign, device="cuda")
+    xt = base[misalign:].view(rows, cols)
+    xt.copy_(torch.from_numpy(x).cuda())
+    assert (xt.data_ptr() % 16 == 0) == (misalign == 0)
+    q, inv = ops.dgdiff_quantize(xt, to, per_row=False)
+    torch.cuda.synchronize()
+    codes = q.view(torch.int16 if to == "bf16" else torch.uint8).cpu().numpy()
+    codes = codes.view(np.uint16) if to == "bf16" else codes
+    qo, invo = orc.quantize(x, to, False)
+    np.testing.assert_array_equal(codes, qo)
+    if to == "e4m3":
+        np.testing.assert_array_equal(inv.cpu().numpy(), invo)
+    else:
+        assert inv.cpu().numpy().tolist() == [1.0]
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
 def test_quantize_random_bit_patterns(orc, ops, to):
     """2^20 random FP32 bit patterns (all exponents, NaN, inf, subnormals)
     in rows of 64: codes and scales bit-equal to the oracle."""
