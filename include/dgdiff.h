@@ -152,6 +152,23 @@ dg_status dgdiff_backward(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit
                           const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
                           size_t ws_bytes, dg_stream_t stream);
 
+/* dgdiff_backward without a workspace, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc).  Same arguments, results and errors as
+   dgdiff_backward minus ws/ws_bytes; it calls no allocating routine.
+   grad_D's split partials live in a fixed 24 MiB device array that the
+   library holds on each GPU it runs on until the process ends (so the
+   element range may be split into fewer, longer pieces than dgdiff_backward
+   uses: same sum in another grouping, FP32/FP64 rounding differences only).
+   Limit: 2 * nmat * nunit^2 * sizeof(t) <= 24 MiB, else DG_EUNSUPPORTED
+   before any launch (every FP32 shape fits; FP64 at nunit 512 needs
+   nmat <= 6).  Every call on one GPU shares that GPU's array: calls that
+   overlap in time on one GPU (different streams, or threads) race and give
+   wrong grad_D; issue them on one stream.  Nothing in the array needs
+   clearing between calls (each call overwrites what it reads).            */
+dg_status dgdiff_backward_noalloc(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit,
+                                  const void* D, const void* u, const void* g, void* grad_u,
+                                  void* grad_D, dg_stream_t stream);
 
 /* Quantise an FP32 [rows][cols] array for the low-precision DG path.
      to = DG_BF16:     q (uint16 [rows][cols]) = round-to-nearest-even BF16 of x;

@@ -88,6 +88,8 @@ def _declare(L):
     L.dgdiff_backward.restype = _i32
     L.dgdiff_backward.argtypes = [_i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                                   ctypes.c_size_t, _vp]
+    L.dgdiff_backward_noalloc.restype = _i32
+    L.dgdiff_backward_noalloc.argtypes = [_i32, _i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
     L.dgdiff_quantize.restype = _i32
     L.dgdiff_quantize.argtypes = [_i32, _i64, _i64, _i32, _vp, _vp, _vp, _vp]
     L.dgdiff_plan_create.restype = _i32
@@ -261,6 +263,23 @@ def dgdiff_backward(D, u, g, want_u=True, want_D=True, stream=None):
     ws = torch.empty(nbytes, dtype=torch.uint8, device=u.device) if nbytes else None
     check(lib().dgdiff_backward(t, nmat, nelem, nunit, _ptr(D), _ptr(u), _ptr(g), _ptr(gu), _ptr(gD),
                                 _ptr(ws), nbytes, _stream(stream)))
+    return gu, gD
+
+
+def dgdiff_backward_noalloc(D, u, g, want_u=True, want_D=True, stream=None):
+    """dgdiff_backward through the entry point that allocates nothing (its
+    grad_D partials use the library's fixed per-device scratch)."""
+    nmat, nunit, _ = D.shape
+    nelem = u.shape[0]
+    if g.shape != (nmat, nelem, nunit):
+        raise ValueError("g must be [nmat][nelem][nunit]")
+    if not (D.dtype == u.dtype == g.dtype):
+        raise TypeError("D, u, g must share a dtype")
+    t = _dtype_code(u.dtype)
+    gu = torch.empty_like(u) if want_u else None
+    gD = torch.empty_like(D) if want_D else None
+    check(lib().dgdiff_backward_noalloc(t, nmat, nelem, nunit, _ptr(D), _ptr(u), _ptr(g), _ptr(gu),
+                                        _ptr(gD), _stream(stream)))
     return gu, gD
 
 

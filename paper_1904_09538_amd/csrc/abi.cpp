@@ -193,6 +193,22 @@ dg_status dgdiff_backward(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit
                               reinterpret_cast<hipStream_t>(stream));
 }
 
+dg_status dgdiff_backward_noalloc(dg_dtype t, int32_t nmat, int64_t nelem, int32_t nunit,
+                                  const void* D, const void* u, const void* g, void* grad_u,
+                                  void* grad_D, dg_stream_t stream) {
+    set_error("");
+    bool done = false;
+    dg_status st = check_backward("dgdiff_backward_noalloc", t, nmat, nelem, nunit, D, u, g, grad_u,
+                                  grad_D, nullptr, 0, &done);
+    if (st != DG_OK || done) return st;
+    if (grad_D && 2 * (size_t)nmat * nunit * nunit * dtype_size(t) > kBackwardScratchBytes)
+        return fail(DG_EUNSUPPORTED, "dgdiff_backward_noalloc: 2 * nmat * nunit^2 * sizeof(t) exceeds "
+                                     "the fixed scratch of " +
+                                         std::to_string(kBackwardScratchBytes) + " bytes");
+    return launch_dg_backward_noalloc(t, nmat, nelem, nunit, D, u, g, grad_u, grad_D,
+                                      reinterpret_cast<hipStream_t>(stream));
+}
+
 dg_status stencil5_apply(dg_dtype t, int64_t n, const void* u, int64_t ld_u, void* res,
                          int64_t ld_res, dg_stream_t stream) {
     set_error("");

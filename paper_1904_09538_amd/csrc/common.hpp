@@ -88,6 +88,12 @@ dg_status resolve_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_ti
 dg_status launch_dg_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D,
                              const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
                              size_t ws_bytes, hipStream_t s);
+// No-allocation backward: grad_D's partials live in a fixed device array of
+// kBackwardScratchBytes per device (see dgdiff_backward_noalloc).
+constexpr size_t kBackwardScratchBytes = (size_t)24 << 20;
+dg_status launch_dg_backward_noalloc(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D,
+                                     const void* u, const void* g, void* grad_u, void* grad_D,
+                                     hipStream_t s);
 
 // Launch shape of dgdiff_quantize (a pure function of the sizes; shared with
 // the feature counter): kShortRows = rows of at most 1024 values in

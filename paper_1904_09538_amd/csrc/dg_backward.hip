@@ -21,6 +21,8 @@
 // workspace; a second kernel adds the partials of every entry in split order
 // 0, 1, 2, ...  The result is therefore deterministic (no atomics, no
 // order-dependent accumulation).
+#include <mutex>
+
 #include "dg_kernel.hpp"
 
 namespace dg {
@@ -533,12 +535,50 @@ dg_status backward(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D
     return DG_OK;
 }
 
+// Fixed scratch of the no-allocation backward: grad_D's split partials and
+// group sums.  Every work-group of the partial kernel writes its whole tile
+// and the group stage writes every group sum, so nothing needs clearing
+// between calls.  In host code `scratch` names a host-side stand-in; kernels
+// get the device address taken by hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kBackwardScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+dg_status scratch_ptr(void** out) {
+    int dev = -1;
+    DG_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DG_EUNSUPPORTED, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DG_OK;
+}
+
 }  // namespace
 
 dg_status launch_dg_backward(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D,
                              const void* u, const void* g, void* grad_u, void* grad_D, void* ws,
                              size_t ws_bytes, hipStream_t s) {
     return backward(t, nmat, nelem, nunit, D, u, g, grad_u, grad_D, ws, ws_bytes, false, s);
+}
+
+dg_status launch_dg_backward_noalloc(dg_dtype t, int nmat, int64_t nelem, int nunit, const void* D,
+                                     const void* u, const void* g, void* grad_u, void* grad_D,
+                                     hipStream_t s) {
+    void* ws = nullptr;
+    if (grad_D && nelem > 0) {
+        dg_status st = scratch_ptr(&ws);
+        if (st != DG_OK) return st;
+    }
+    return backward(t, nmat, nelem, nunit, D, u, g, grad_u, grad_D, ws, ws ? kBackwardScratchBytes : 0,
+                    true, s);
 }
 
 }  // namespace dg
