@@ -244,11 +244,16 @@ def row_batched(L, I, torch, steps, model, checks):
     plan = L.BatchedPlan(order, model=model)
     o = torch.empty((3, total), device="cuda")
     tb = timed(lambda: plan.apply(Ds, u, out=o), steps, 2)
-    # the model's prediction of the launch that ran: the counted features of
-    # every order's share (its body, its work-groups) under the batched model
+    # the model's predictions of the launch that ran, under the batched-family
+    # model: (a) each order priced alone on the whole GPU on the body that
+    # runs it (the planner's own estimates, the configuration the family was
+    # calibrated on), the orders sharing the GPU so their times add; (b) the
+    # counted features of the whole launch (every order's share: work adds,
+    # the longest chain is the launch's)
     info = {p: plan.info(p) for p in range(1, 8)}
+    pred = sum(i["predicted_s"] for i in info.values() if i["count"]) if model else None
     feats = L.batched_counts(info, torch.cuda.get_device_properties(0).multi_processor_count)
-    pred = model_predict(model, feats) if model else None
+    pred_counts = model_predict(model, feats) if model else None
     sel = sample_elements(E)
     for p in range(1, 8):
         sp = sel[order[sel] == p]
@@ -284,7 +289,10 @@ def row_batched(L, I, torch, steps, model, checks):
            "seven_plain_launches_ms": t7 * 1e3, "speedup_vs_plain": t7 / tb,
            "predicted_ms": pred * 1e3 if pred else None,
            "model_rel_error": (pred - tb) / tb if pred else None,
-           "predicted_by": "batched-family model on the counts of every order's share (the bodies that ran)",
+           "predicted_by": "batched-family model: sum of every order's time alone on the GPU, on the body "
+                           "that ran it",
+           "predicted_ms_launch_counts": pred_counts * 1e3 if pred_counts else None,
+           "launch_counts_rel_error": (pred_counts - tb) / tb if pred_counts else None,
            "shapes": {p: plan.info(p)["tile"] for p in range(1, 8)}}
     log(f"batched: {tb * 1e3:.3f} ms vs 7 launches {t7 * 1e3:.3f} ms, predicted "
         f"{pred * 1e3 if pred else float('nan'):.3f} ms")

@@ -69,6 +69,13 @@ typedef struct {
                                 matrix cores, with true FP32 accumulation) */
 #define DG_TILE_BATCH_GEMM 4 /* batched plans: run this order on the GEMM-tiled body
                                 (128 operator rows x 128 elements per work-group) */
+#define DG_TILE_LP_LDS_PANELS 8 /* BF16/FP8 input: run the body with operator panels
+                                   resident in LDS and results stored from the matrix
+                                   registers (default where nunit % 8 == 0 and D, u,
+                                   out are 16-byte aligned: the staged body, operator
+                                   rows in registers, element and result tiles
+                                   staged in LDS, whole output rows written with
+                                   streaming stores whatever DG_TILE_NT_STORE says) */
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* dg_last_error(void);

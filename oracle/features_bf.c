@@ -869,6 +869,141 @@ static int batched_walk(int64_t cnt, int n, int M, int epw, int ppg_in, int per_
     return 0;
 }
 
+/* The staged low-precision body (rows of a multiple of 8 nodes, BF16 or FP8
+   widened to BF16, unless flags bit 8 asks for the LDS-panel body):
+   a work-group owns rb = d_panels consecutive 16-row blocks of one operator
+   slab, waves x pw = rb (pw = 1 or 2 blocks per wave, held in registers);
+   tiles of 16 cb elements; per thread cb 8-node element chunks and 2 cb
+   16-byte result chunks per tile (fixed counts; out-of-range ones move no
+   memory).  Walked: every work-group, its operator rows, and the call order
+   of its loop, whose loads run two tiles ahead: load tiles 0, 1, 2, copy
+   tiles 0 and 1 to LDS, multiply tile 0; then per tile k: load tile k + 3,
+   write tile k, multiply tile k + 1, copy tile k + 2 (indices past the
+   stream's last tile meaning that last tile). */
+static int lp_staged_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int per_cu, int rb,
+                          int num_cu, int64_t* c) {
+    const int fp8 = dtype == T_FP8;
+    const int64_t eg = fp8 ? 1 : 2;
+    const int KS = (int)cdiv(n, 32), KQ = 8 * KS;
+    if (KS > 16) return 1;
+    if (epw != 16 && epw != 32) return 1;
+    if (waves < 1 || waves > 16 || rb < 1 || rb % waves) return 1;
+    const int pw = rb / waves;
+    if (pw != 1 && pw != 2) return 1;
+    if (pw == 2 && KS > 8) return 1;
+    const int cb = epw / 16;
+    if (pw == 2 && cb == 2 && waves > 8) return 1;
+    const int64_t TE = 16LL * cb, T = 64LL * waves;
+    const int mblk = (int)cdiv(n, 16);
+    const int nrg = (int)cdiv(mblk, rb);
+    const int NG = M * nrg;
+    const int nch_u = n / 8;
+    /* staging limits and LDS (element buffers, result buffers, scales, dump) */
+    if (TE * nch_u > T * cb || TE * mini((int64_t)rb * 16, n) / 4 > T * 2 * cb) return 1;
+    {
+        const int64_t upitch = TE * 16 + 16;
+        const int64_t lds = 2 * 4LL * KS * upitch + 2 * TE * rb * 16 * 4 + 2 * TE * 4 + T * 16;
+        if (lds > 160 * 1024) return 1;
+    }
+    const int64_t ntiles = cdiv(E, TE);
+    const int64_t cap = maxi(1, (int64_t)per_cu * num_cu / (8LL * NG));
+    const int64_t slots = maxi(1, mini(cap, cdiv(ntiles, 8)));
+    const int64_t G = 8 * NG * slots, ns = 8 * slots;
+    c[F_LAUNCH] += 1;
+    c[F_WG] += G;
+    int64_t serial = 0;
+    for (int64_t b = 0; b < G; ++b) {
+        const int64_t xcd = b % 8, kb = b / 8;
+        const int gi = (int)(kb % NG);
+        const int rg = gi % nrg;   /* slab gi / nrg: the counts do not depend on it */
+        const int64_t stream = (kb / NG) * 8 + xcd;
+        if (stream >= ntiles) continue;
+        const int r0 = rg * rb * 16;
+        const int rows_g = (int)mini((int64_t)rb * 16, n - r0);
+        /* padding chunk rows of both element buffers */
+        for (int64_t idx = 0; idx < 2LL * (4 * KS - nch_u) * TE; ++idx) c[F_LDS] += 16;
+        /* operator rows: wave w holds blocks w pw .. w pw + pw - 1 of the group */
+        int nbw[16];
+        for (int w = 0; w < waves; ++w) {
+            nbw[w] = 0;
+            for (int q = 0; q < pw; ++q) {
+                const int lb = w * pw + q;
+                if (lb < rb && r0 + lb * 16 < n) nbw[w] = q + 1;
+            }
+            for (int lane = 0; lane < 64; ++lane) {
+                const int cc = lane & 15, g = lane >> 4;
+                for (int q = 0; q < nbw[w]; ++q) {
+                    const int i = r0 + (w * pw + q) * 16 + cc;
+                    for (int s = 0; s < KS; ++s)
+                        if (i < n && g * KQ + 8 * s < n) c[F_D] += 8 * eg;
+                }
+            }
+            if (fp8) c[F_D] += 4;   /* the slab's operator scale, one read per wave */
+        }
+        /* the loop's order of tile stages, writes and multiplies */
+        int64_t K = 0;
+        for (int64_t t = stream; t < ntiles; t += ns) ++K;
+        int64_t* tiles = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * K + 4));
+        if (!tiles) return 1;
+        int64_t* stage_seq = tiles + K;
+        K = 0;
+        for (int64_t t = stream; t < ntiles; t += ns) tiles[K++] = t;
+        if (K > serial) serial = K;
+        /* the loads: tiles 0 .. K + 1 (past the end: the last tile) */
+        int64_t nst = 0;
+        for (int64_t k = 0; k < K + 2; ++k) stage_seq[nst++] = tiles[k < K ? k : K - 1];
+        c[F_BAR] += K + 1;
+        c[F_WAVE_TILES] += K;
+        /* group 0's first load of a tile from HBM, every other from L2, with
+           the element scales */
+        for (int64_t q = 0; q < nst; ++q) {
+            const int64_t t = stage_seq[q];
+            int first = gi == 0;
+            for (int64_t r = 0; r < q; ++r)
+                if (stage_seq[r] == t) first = 0;
+            const int64_t nel = mini(TE, E - t * TE);
+            for (int64_t th = 0; th < T; ++th) {
+                for (int kk = 0; kk < cb; ++kk)
+                    if (th + kk * T < nel * nch_u) c[first ? F_U : F_U_L2] += 8 * eg;
+                if (fp8 && th % TE < nel) c[F_U_UNAL] += 4;
+            }
+        }
+        /* the LDS copies: tiles 0 .. K (every thread its cb chunks and a scale) */
+        for (int64_t q = 0; q < K + 1; ++q)
+            for (int64_t th = 0; th < T; ++th) c[F_LDS] += 16LL * cb + 4;
+        /* multiplies (every tile once) and writes */
+        for (int64_t k = 0; k < K; ++k) {
+            const int64_t t = tiles[k];
+            const int64_t nel = mini(TE, E - t * TE);
+            for (int w = 0; w < waves; ++w) {
+                if (nbw[w] == 0) continue;
+                for (int s = 0; s < KS; ++s)
+                    for (int q = 0; q < cb; ++q) {
+                        c[F_LDS] += 64 * 16;
+                        c[F_MFMA_BF16] += 16384LL * nbw[w];
+                    }
+                for (int q = 0; q < cb; ++q) {
+                    c[F_LDS] += 64 * 4;                          /* element scale per lane */
+                    c[F_VALU_F32] += 64 * (1 + 4 * nbw[w]);      /* scale product, de-scaling */
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int p = 0; p < nbw[w]; ++p)
+                            if ((w * pw + p) * 16 + 4 * (lane >> 4) < rows_g) c[F_LDS] += 16;
+                }
+            }
+            for (int64_t th = 0; th < T; ++th)
+                for (int kk = 0; kk < 2 * cb; ++kk) {
+                    const int64_t ch = th + kk * T;
+                    c[F_LDS] += 16;
+                    if (ch < nel * (rows_g / 4)) c[F_OUT] += 16;
+                }
+        }
+        free(tiles);
+    }
+    c[F_SERIAL] += serial;
+    c[F_LAT] += serial * 64 / ((int64_t)per_cu * waves);
+    return 0;
+}
+
 /* counts[F_N] overwritten; returns 0 on success */
 int orc_features(int kernel, int dtype, int64_t n0, int nunit, int nmat, int epw, int waves,
                  int per_cu, int d_panels, int flags, int num_cu, int64_t workgroups, int64_t* counts) {
@@ -876,6 +1011,8 @@ int orc_features(int kernel, int dtype, int64_t n0, int nunit, int nmat, int epw
     switch (kernel) {
         case K_DG:
             if (n0 == 0) return 0;
+            if ((dtype == T_BF16 || (dtype == T_FP8 && !(flags & 2))) && nunit % 8 == 0 && !(flags & 8))
+                return lp_staged_walk(dtype, n0, nunit, nmat, epw, waves, per_cu, d_panels, num_cu, counts);
             return dg_walk(dtype, n0, nunit, 1, nmat, epw, waves, per_cu, d_panels, flags, num_cu, 1, 0,
                            counts);
         case K_STENCIL:

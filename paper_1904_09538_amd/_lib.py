@@ -35,6 +35,7 @@ class dg_tile(ctypes.Structure):
 DG_TILE_NT_STORE = 1
 DG_TILE_FP8_NATIVE = 2
 DG_TILE_BATCH_GEMM = 4
+DG_TILE_LP_LDS_PANELS = 8
 
 (DG_K_DGDIFF, DG_K_STENCIL5, DG_K_MATMUL, DG_K_EMPTY, DG_K_BWD_U, DG_K_BWD_D, DG_K_QUANT,
  DG_K_BATCHED, DG_K_BATCHED_POOL) = range(9)
@@ -358,27 +359,41 @@ def resolve_backward(dtype, nmat, nelem, nunit):
     return _tile_dict(tu), _tile_dict(td)
 
 
+# features that measure a chain of dependent steps rather than an amount of work
+CHAIN_FEATURES = ("serial_steps", "lat_steps")
+
+
 def batched_counts(plan_info, num_cu=0):
     """Counted features of a whole batched launch from dgdiff_plan_info's
-    per-order report ({p: info}): the orders' shares summed, the GEMM pool's
-    fixed cost added when an order runs GEMM tiles, one launch."""
+    per-order report ({p: info}), one launch.  The orders' shares run side by
+    side on the GPU, so their amounts of work (bytes, flops, work-groups,
+    barriers) add, while the launch's chain of dependent steps is the longest
+    of the orders' chains; the GEMM pool's fixed cost is added when an order
+    runs GEMM tiles."""
     import numpy as np
+    names = feature_names()
+    chain = [names.index(k) for k in CHAIN_FEATURES]
     tot = None
     grid = sum(int(i["workgroups"]) for i in plan_info.values() if int(i["count"]) > 0)
     pool = False
     for p, i in plan_info.items():
         if int(i["count"]) == 0:
             continue
-        c = perf_features_count("batched", "f32", int(i["count"]), (int(p) + 1) ** 3, 3, i["tile"], num_cu,
-                                int(i["workgroups"]))
+        c = np.asarray(perf_features_count("batched", "f32", int(i["count"]), (int(p) + 1) ** 3, 3, i["tile"],
+                                           num_cu, int(i["workgroups"])))
         pool = pool or bool(int(i["tile"]["flags"]) & DG_TILE_BATCH_GEMM)
-        tot = c if tot is None else tot + c
+        if tot is None:
+            tot = c.copy()
+        else:
+            longest = np.maximum(tot[chain], c[chain])
+            tot = tot + c
+            tot[chain] = longest
     if tot is None:
         return None
     if pool:
-        tot = tot + perf_features_count("batched_pool", "f32", grid)
+        tot = tot + np.asarray(perf_features_count("batched_pool", "f32", grid))
     tot[0] = 1
-    return np.asarray(tot)
+    return tot
 
 
 def resolve_tile(dtype, nmat, nelem, nunit, tile=None):

@@ -61,6 +61,10 @@ VARIANTS = [
     ("dg_f64_p3_4096", "dg", {"dtype": "f64", "p": 3, "E": 4096}),
     ("dg_bf16_p5_2e20", "dg", {"dtype": "bf16", "p": 5, "E": 1 << 20}),
     ("dg_fp8_p5_2e20", "dg", {"dtype": "fp8", "p": 5, "E": 1 << 20}),
+    ("dg_bf16_p5_2e20_ldspanels", "dg", {"dtype": "bf16", "p": 5, "E": 1 << 20, "tile": {"flags": 8}}),
+    ("dg_fp8_p5_2e20_ldspanels", "dg", {"dtype": "fp8", "p": 5, "E": 1 << 20, "tile": {"flags": 8}}),
+    ("dg_bf16_p5_100003_split", "dg", {"dtype": "bf16", "p": 5, "E": 100003,
+                                       "tile": {"waves": 9, "d_panels": 9}}),
     ("dg_fp8native_p5_2e20", "dg", {"dtype": "fp8", "p": 5, "E": 1 << 20, "tile": {"flags": 2}}),
     ("quant_fp8_rows_2e20x216", "quant", {"to": "fp8", "rows": 1 << 20, "cols": 216}),
     ("quant_bf16_2e20x216", "quant", {"to": "bf16", "rows": 1 << 20, "cols": 216}),

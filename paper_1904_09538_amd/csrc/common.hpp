@@ -65,17 +65,29 @@ dg_status launch_dg_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit,
                                const dg_tile* tile, hipStream_t s);
 
 // Launch plan of the low-precision forward (shared with the feature counter).
+//   staged body (staged = true): a work-group owns rb = waves x pw row blocks
+//   of one operator slab (a row group; nrg of them per slab, ngroups = nmat x
+//   nrg), keeps its operator rows in registers and stages element tiles of
+//   16 cb elements and their result rows in LDS; ppg reports rb.
+//   LDS-panel body (staged = false): ppg operator panels per work-group in LDS.
 struct LpPlan {
     int fmt;       // 0 BF16, 1 FP8 native, 2 FP8 widened to BF16
     int ks, cb, waves, lds_esz;
     int mblk, panels_total, ppg, ngroups;
     int64_t ntiles, slots, grid;
     size_t panel_bytes, smem;
+    bool staged;
+    int pw, rb, nrg, upitch;
 };
+// Staged body: 8-node element chunks and 16-byte result chunks each thread
+// handles per tile of 16 cb elements (its fixed number of loads and stores).
+constexpr int ls_chunks_in(int cb) { return cb; }
+constexpr int ls_chunks_out(int cb) { return 2 * cb; }
 int lp_format(dg_dtype in_t, const dg_tile* tile);
 bool lp_pair_ok(const LpPlan& P, int nunit, bool vec_out);
+// aligned: D, u and out start on 16-byte boundaries (the staged body needs it)
 dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_tile* tile, int per_cu,
-                       int num_cu, LpPlan* P);
+                       int num_cu, LpPlan* P, bool aligned = true);
 dg_status resolve_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nunit, dg_tile* tile);
 dg_status resolve_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_tile* tile);
 

@@ -11,6 +11,8 @@
 // element data arrive as 16-byte (BF16) or 8-byte (FP8) vector loads and the
 // operator rows as LDS reads of the same width.  The 16x16 FP32 accumulator
 // layout is that of the FP32 instruction: lane group g holds rows 4g..4g+3.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace dg {
@@ -74,23 +76,26 @@ __device__ inline uint32_t e4m3_to_bf16_bits(uint32_t b) {
     return r | ((b & 0x80u) << 8);
 }
 
+// Eight E4M3FN values (two words) to eight BF16 values on gfx950's packed
+// conversion (two values per instruction, scale 1): the same bits as
+// e4m3_to_bf16_bits for every finite code, NaN for NaN.
+__device__ inline u32x4 e4m3x8_to_bf16x8(u32x2 v) {
+    u32x4 r;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        r[2 * h] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v[h], 1.0f, false));
+        r[2 * h + 1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(v[h], 1.0f, true));
+    }
+    return r;
+}
+
 template <>
 struct LP<2> {
     typedef uint8_t G;
     typedef uint16_t L;
     typedef u32x2 GF;
     typedef u32x4 F;
-    __device__ static inline F widen(GF v) {
-        F r;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const uint32_t w = v[h];
-            r[2 * h] = e4m3_to_bf16_bits(w & 0xFFu) | (e4m3_to_bf16_bits((w >> 8) & 0xFFu) << 16);
-            r[2 * h + 1] =
-                e4m3_to_bf16_bits((w >> 16) & 0xFFu) | (e4m3_to_bf16_bits(w >> 24) << 16);
-        }
-        return r;
-    }
+    __device__ static inline F widen(GF v) { return e4m3x8_to_bf16x8(v); }
     __device__ static inline L widen1(G v) { return (L)e4m3_to_bf16_bits(v); }
     __device__ static inline f32x4 mma(F a, F b, f32x4 c) { return LP<0>::mma(a, b, c); }
 };
@@ -346,6 +351,326 @@ lp_fn lp_kernel(int fmt, int ks, int cb, bool pair) {
     return cb == 4 ? pick_lp<2, 4>(ks, pair) : cb == 2 ? pick_lp<2, 2>(ks, pair) : pick_lp<2, 1>(ks, pair);
 }
 
+// ---------------------------------------------------------------- staged body
+// Operator rows in registers; element tiles and result rows staged in LDS.
+//
+// A work-group owns rb = waves x PW consecutive 16-row blocks of one operator
+// slab m (a row group, rows r0 .. r0 + rows_g); each wave keeps the MFMA A
+// fragments of its PW blocks in registers for the whole launch (PW x KS x 4
+// registers).  Per tile of 16 CB consecutive elements:
+//   - the tile's element rows, contiguous in HBM, are copied into LDS in
+//     fragment order (chunk row j = 8-node chunk, one 16-byte BF16 vector
+//     per element; FP8 widened to BF16 on the way), their scales beside;
+//   - every wave multiplies its blocks (C^T = D_rows U^T on 16x16x32 BF16
+//     MFMA tiles, the k-steps in the same order as the LDS-panel body) and
+//     writes the scaled results into an LDS copy of the tile's output rows;
+//   - after one barrier the work-group writes those rows with 16-byte
+//     stores: rows_g x 4 contiguous bytes per element, and one contiguous
+//     block of 16 CB x nunit x 4 bytes when the row group is the whole row.
+// Element rows are loaded into registers two tiles ahead (two register
+// sets), so each load has a whole loop iteration to arrive, and are copied to
+// the LDS buffer the tile after next will read; one barrier per tile orders
+// everything (two element and two result buffers).
+
+// word 3 of a raw buffer resource on gfx9-family parts (32-bit data format,
+// no swizzle): range-checked loads and stores on plain byte offsets
+constexpr int kBufferWord3 = 0x00020000;
+// cache policy of the staged body's output stores: non-temporal at system
+// scope (nt sc0 sc1), streamed past the L2.  The kernel never reads its
+// output, and keeping it out of the L2 keeps resident the element tiles the
+// other operator groups re-read (measured at p = 5, 2^20 elements: FP8
+// 0.76 -> 0.54 ms)
+constexpr int kStreamStore = 2 | 1 | 16;
+
+struct LsArgs {
+    const void* D;
+    const void* u;
+    float* out;
+    const float* inv_sD;
+    const float* inv_su;
+    int64_t nelem;
+    int64_t ntiles;
+    int nunit;
+    int mblk;
+    int rb;        // row blocks per work-group
+    int nrg;       // row groups per slab
+    int ngroups;   // nmat x nrg
+    int nstreams;
+    int upitch;    // bytes per chunk row of an element buffer (16 CB elements + pad)
+};
+
+// up to 16 waves per work-group (128 registers per lane); shapes with two
+// column blocks and two row blocks per wave take at most 8 (256 registers)
+template <int CB, int PW>
+constexpr int ls_max_threads() {
+    return CB == 2 && PW == 2 ? 512 : 1024;
+}
+
+template <int FMT, int KS, int CB, int PW>
+__global__ void __launch_bounds__((ls_max_threads<CB, PW>())) dg_lowp_staged_kernel(LsArgs a) {
+    typedef typename LP<FMT>::G GE;
+    typedef typename LP<FMT>::GF GF;
+    typedef u32x4 F;   // BF16 fragment (FP8 widened)
+    constexpr int KQ = 8 * KS;
+    constexpr int TE = 16 * CB;   // elements per tile
+
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int tid = threadIdx.x;
+    const int T = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int c = lane & 15;
+    const int g = lane >> 4;
+    const int nunit = a.nunit;
+
+    const int xcd = blockIdx.x & 7;
+    const int k = blockIdx.x >> 3;
+    const int gi = k % a.ngroups;
+    const int m = gi / a.nrg;
+    const int rg = gi % a.nrg;
+    const int64_t stream = (int64_t)(k / a.ngroups) * 8 + xcd;
+    if (stream >= a.ntiles) return;   // a work-group without tiles does nothing
+    const int r0 = rg * a.rb * 16;
+    const int rows_g = min(a.rb * 16, nunit - r0);
+    const int nch_u = nunit / 8;    // 8-node chunks per element row
+    const int nch_o = rows_g / 4;   // 4-row result chunks per element and row group
+
+    const int usz = 4 * KS * a.upitch;          // bytes per element buffer
+    const int osz = TE * a.rb * 16;             // floats per result buffer
+    unsigned char* us = smem;
+    float* os = reinterpret_cast<float*>(smem + 2 * usz);
+    float* ssu = os + 2 * osz;
+
+    // chunk rows past the element row stay zero (both buffers)
+    {
+        const int zrows = 4 * KS - nch_u;
+        for (int idx = tid; idx < 2 * zrows * TE; idx += T) {
+            const int b = idx / (zrows * TE);
+            const int r = idx % (zrows * TE);
+            *reinterpret_cast<u32x4*>(us + b * usz + (nch_u + r / TE) * a.upitch + (r % TE) * 16) = u32x4(0u);
+        }
+    }
+    // this wave's operator rows: blocks lb = wave * PW + b of the row group
+    int nbw = 0;
+#pragma unroll
+    for (int b = 0; b < PW; ++b) {
+        const int lb = wave * PW + b;
+        if (lb < a.rb && r0 + lb * 16 < nunit) nbw = b + 1;
+    }
+    F A[PW][KS];
+    {
+        const GE* __restrict__ D = static_cast<const GE*>(a.D);
+#pragma unroll
+        for (int b = 0; b < PW; ++b) {
+            const int i = r0 + (wave * PW + b) * 16 + c;
+            const bool rowok = b < nbw && i < nunit;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int col = g * KQ + 8 * s;
+                GF v = GF(0u);
+                if (rowok && col < nunit)
+                    v = *reinterpret_cast<const GF*>(D + ((int64_t)m * nunit + i) * nunit + col);
+                A[b][s] = LP<FMT>::widen(v);
+            }
+        }
+    }
+    const float msc = a.inv_sD ? a.inv_sD[m] : 1.0f;
+    constexpr int NI = ls_chunks_in(CB);
+    constexpr int NO = ls_chunks_out(CB);
+    // per-thread element chunk offsets, fixed for the launch (q = tid + kk T):
+    // element chunk q -> LDS (chunk row q % nch_u, element q / nch_u)
+    int uoff[NI];
+#pragma unroll
+    for (int kk = 0; kk < NI; ++kk) {
+        const int q = tid + kk * T;
+        uoff[kk] = (q % nch_u) * a.upitch + (q / nch_u) * 16;
+    }
+    // result chunk q: element q / nch_o, rows 4 (q % nch_o) of the group, at
+    // this byte offset from the tile's first output row of the group (4 q
+    // floats, one contiguous run, when the group is the whole row); chunks
+    // past the tile's elements fall outside the store's buffer range
+    int goff[NO];
+#pragma unroll
+    for (int kk = 0; kk < NO; ++kk) {
+        const int q = tid + kk * T;
+        goff[kk] = ((q / nch_o) * nunit + 4 * (q % nch_o)) * 4;
+    }
+
+    // Element loads and output stores are buffer operations whose range check
+    // (out-of-range loads read 0, out-of-range stores are dropped) replaces
+    // per-lane branches: every thread issues the same fixed number of them
+    // per tile, so the compiler's wait for a tile's loads leaves the stores
+    // and loads issued after them in flight.
+    constexpr int CHB = (int)sizeof(GF);   // bytes of an 8-node chunk in HBM
+    const GE* __restrict__ u = static_cast<const GE*>(a.u);
+    unsigned char* dump = reinterpret_cast<unsigned char*>(ssu + 2 * TE) + tid * 16;
+    struct Pf {
+        GF v[NI];
+        float s;
+    };
+    auto issue = [&](Pf& pf, int64_t tt) {
+        const int64_t e0 = tt * TE;
+        const int nel = (int)min<int64_t>(TE, a.nelem - e0);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<GE*>(u + e0 * nunit), 0, nel * nch_u * CHB, kBufferWord3);
+#pragma unroll
+        for (int kk = 0; kk < NI; ++kk) {
+            if constexpr (CHB == 16)
+                pf.v[kk] = __builtin_amdgcn_raw_buffer_load_b128(rs, (tid + kk * T) * CHB, 0, 0);
+            else
+                pf.v[kk] = __builtin_amdgcn_raw_buffer_load_b64(rs, (tid + kk * T) * CHB, 0, 0);
+        }
+        // the element scales as a buffer of nel floats (none without scales:
+        // every read out of range, 0, replaced by 1 at the commit)
+        const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+            a.inv_su ? const_cast<float*>(a.inv_su + e0) : a.out, 0, a.inv_su ? nel * 4 : 0, kBufferWord3);
+        pf.s = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rq, 4 * (tid % TE), 0, 0));
+    };
+    auto commit = [&](const Pf& pf, int b, int64_t tt) {
+        const int nq = (int)min<int64_t>(TE, a.nelem - tt * TE) * nch_u;
+        unsigned char* ub = us + b * usz;
+#pragma unroll
+        for (int kk = 0; kk < NI; ++kk) {
+            const int q = tid + kk * T;
+            *reinterpret_cast<u32x4*>(q < nq ? ub + uoff[kk] : dump) = LP<FMT>::widen(pf.v[kk]);
+        }
+        ssu[b * TE + tid % TE] = a.inv_su ? pf.s : 1.0f;   // every thread of a slot writes the same value
+    };
+    // NB valid row blocks: the k-steps' B fragments read ahead of the
+    // products (all of them while registers allow, else one k-step at a time)
+    auto multiply = [&](int b, auto nbc) {
+        constexpr int NB = decltype(nbc)::value;
+        constexpr int AHEAD = KS * CB * PW <= 16 ? KS : 1;
+        const unsigned char* ub = us + b * usz;
+        f32x4 acc[NB][CB];
+#pragma unroll
+        for (int p = 0; p < NB; ++p)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[p][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s0 = 0; s0 < KS; s0 += AHEAD) {
+            F bf[AHEAD][CB];
+#pragma unroll
+            for (int s = 0; s < AHEAD; ++s)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    bf[s][cb] = *reinterpret_cast<const F*>(ub + (g * KS + s0 + s) * a.upitch + (cb * 16 + c) * 16);
+#pragma unroll
+            for (int s = 0; s < AHEAD; ++s)
+#pragma unroll
+                for (int p = 0; p < NB; ++p)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        acc[p][cb] = LP<0>::mma(A[p][s0 + s], bf[s][cb], acc[p][cb]);
+        }
+        float* ob = os + b * osz;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const float sc = msc * ssu[b * TE + cb * 16 + c];  // product of powers of two: exact
+#pragma unroll
+            for (int p = 0; p < NB; ++p) {
+                const int row = (wave * PW + p) * 16 + 4 * g;
+                if (row < rows_g)
+                    *reinterpret_cast<f32x4*>(ob + (cb * 16 + c) * rows_g + row) = acc[p][cb] * sc;
+            }
+        }
+    };
+    auto multiply_tile = [&](int b) {
+        if (nbw == PW) multiply(b, std::integral_constant<int, PW>{});
+        else if (PW == 2 && nbw == 1) multiply(b, std::integral_constant<int, 1>{});
+    };
+    auto write = [&](int b, int64_t tt) {
+        const int64_t e0 = tt * TE;
+        const int nel = (int)min<int64_t>(TE, a.nelem - e0);
+        const float* ob = os + b * osz;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            a.out + ((int64_t)m * a.nelem + e0) * nunit + r0, 0, (nel * nunit - r0) * 4, kBufferWord3);
+        const int qmax = TE * nch_o - 1;
+        f32x4 v[NO];
+#pragma unroll
+        for (int kk = 0; kk < NO; ++kk)
+            v[kk] = *reinterpret_cast<const f32x4*>(ob + 4 * min(tid + kk * T, qmax));
+#pragma unroll
+        for (int kk = 0; kk < NO; ++kk)
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v[kk]), rs, goff[kk], 0,
+                                                   kStreamStore);
+    };
+
+    // the stream's tiles t_k = stream + k ns, k < K; indices past the end
+    // repeat the last tile (their loads are re-reads into idle buffers)
+    const int64_t ns = a.nstreams;
+    const int64_t K = (a.ntiles - stream + ns - 1) / ns;
+    auto tile_at = [&](int64_t k) { return stream + (k < K ? k : K - 1) * ns; };
+    Pf pa, pb;
+    // prologue: tile 0 staged; tiles 1 and 2 loading; tile 0 multiplied;
+    // tile 1 staged
+    issue(pa, tile_at(0));
+    commit(pa, 0, tile_at(0));
+    __syncthreads();
+    issue(pb, tile_at(1));
+    issue(pa, tile_at(2));
+    multiply_tile(0);
+    commit(pb, 1, tile_at(1));
+    __syncthreads();
+    // iteration k: results of tile k in result buffer k & 1, tile k + 1 in
+    // element buffer (k + 1) & 1, tile k + 2 loading into `ahead`; load tile
+    // k + 3 into `next`, store tile k, multiply tile k + 1, stage tile k + 2
+    auto step = [&](int64_t k, Pf& ahead, Pf& next) {
+        const int b = (int)(k & 1);
+        issue(next, tile_at(k + 3));
+        write(b, tile_at(k));
+        multiply_tile(b ^ 1);
+        commit(ahead, b, tile_at(k + 2));
+        __syncthreads();
+    };
+    for (int64_t k = 0;; k += 2) {
+        if (k + 1 >= K) {
+            write((int)(k & 1), tile_at(k));
+            break;
+        }
+        step(k, pa, pb);
+        if (k + 2 >= K) {
+            write((int)((k + 1) & 1), tile_at(k + 1));
+            break;
+        }
+        step(k + 1, pb, pa);
+    }
+}
+
+typedef void (*ls_fn)(LsArgs);
+
+// two row blocks per wave only while their operator rows fit 64 registers
+template <int FMT, int CB, int PW>
+ls_fn pick_ls(int ks) {
+    switch (ks) {
+#define X(K) \
+    case K: return dg_lowp_staged_kernel<FMT, K, CB, PW>;
+        X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+#undef X
+    }
+    if constexpr (PW == 1) {
+        switch (ks) {
+#define X(K) \
+    case K: return dg_lowp_staged_kernel<FMT, K, CB, PW>;
+            X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#undef X
+        }
+    }
+    return nullptr;
+}
+
+ls_fn ls_kernel(int fmt, int ks, int cb, int pw) {
+    if (fmt == 0) {
+        if (cb == 1) return pw == 1 ? pick_ls<0, 1, 1>(ks) : pick_ls<0, 1, 2>(ks);
+        return pw == 1 ? pick_ls<0, 2, 1>(ks) : pick_ls<0, 2, 2>(ks);
+    }
+    if (fmt == 2) {
+        if (cb == 1) return pw == 1 ? pick_ls<2, 1, 1>(ks) : pick_ls<2, 1, 2>(ks);
+        return pw == 1 ? pick_ls<2, 2, 1>(ks) : pick_ls<2, 2, 2>(ks);
+    }
+    return nullptr;
+}
+
 }  // namespace
 
 int lp_format(dg_dtype in_t, const dg_tile* tile) {
@@ -353,11 +678,72 @@ int lp_format(dg_dtype in_t, const dg_tile* tile) {
     return (in_t == DG_BF16) ? 0 : native ? 1 : 2;
 }
 
+// The staged body's plan (see dg_lowp_staged_kernel).  Defaults: one column
+// block per tile, two row blocks per wave while the operator rows take at
+// most 64 registers (KS <= 8), else one, and as many waves (up to 16) as
+// cover one slab's row blocks.
+static dg_status make_staged_plan(int nmat, int64_t nelem, int nunit, const dg_tile* tile, int per_cu,
+                                  int num_cu, LpPlan* P) {
+    const int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : 16;
+    if (epw == 16) P->cb = 1;
+    else if (epw == 32) P->cb = 2;
+    else return fail(DG_EINVAL, "tile.elems_per_wave must be 16 or 32 (elements per tile)");
+    P->mblk = (int)ceil_div(nunit, 16);
+    P->panels_total = nmat * P->mblk;
+    const int pw_def = P->ks <= 8 ? 2 : 1;
+    const int tw = tile ? tile->waves : 0, tp = tile ? tile->d_panels : 0;
+    int W, pw;
+    if (tw > 0 && tp > 0) {
+        if (tp % tw) return fail(DG_EINVAL, "tile.d_panels must be 1 or 2 row blocks per wave");
+        W = tw;
+        pw = tp / tw;
+    } else if (tp > 0) {
+        pw = (tp % 2 == 0 && pw_def == 2) ? 2 : 1;
+        W = tp / pw;
+    } else if (tw > 0) {
+        W = tw;
+        pw = pw_def;
+    } else {
+        pw = pw_def;
+        W = std::min<int>(16, (int)ceil_div(P->mblk, pw));
+    }
+    if (pw != 1 && pw != 2) return fail(DG_EINVAL, "tile.d_panels must be 1 or 2 row blocks per wave");
+    if (pw == 2 && P->ks > 8) return fail(DG_EINVAL, "two row blocks per wave need nunit <= 256");
+    if (W < 1 || W > 16) return fail(DG_EINVAL, "tile.waves must be in 1..16 for the staged body");
+    if (pw == 2 && P->cb == 2 && W > 8)
+        return fail(DG_EINVAL, "two row blocks and two column blocks per wave allow at most 8 waves");
+    P->waves = W;
+    P->pw = pw;
+    P->rb = W * pw;
+    P->nrg = (int)ceil_div(P->mblk, P->rb);
+    const int tile_elems = 16 * P->cb;
+    const int rows_max = std::min(P->rb * 16, nunit);
+    if (tile_elems * (nunit / 8) > 64 * W * ls_chunks_in(P->cb) ||
+        tile_elems * rows_max / 4 > 64 * W * ls_chunks_out(P->cb))
+        return fail(DG_EINVAL, "too few waves to stage a tile of the staged body (nunit / 32 at least)");
+    P->upitch = tile_elems * 16 + 16;
+    P->lds_esz = 2;
+    P->panel_bytes = 0;
+    P->smem = (size_t)2 * 4 * P->ks * P->upitch + (size_t)2 * tile_elems * P->rb * 16 * 4 +
+              (size_t)2 * tile_elems * 4 + (size_t)64 * W * 16;
+    if (P->smem > 160 * 1024) return fail(DG_EINVAL, "staged body: tile exceeds the 160 KB LDS");
+    P->ppg = P->rb;
+    P->ngroups = nmat * P->nrg;
+    P->ntiles = ceil_div(nelem, (int64_t)tile_elems);
+    const int64_t cap = std::max<int64_t>(1, (int64_t)per_cu * num_cu / (8 * P->ngroups));
+    P->slots = std::max<int64_t>(1, std::min<int64_t>(cap, ceil_div(P->ntiles, 8)));
+    P->grid = 8 * P->ngroups * P->slots;
+    return DG_OK;
+}
+
 dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_tile* tile, int per_cu,
-                       int num_cu, LpPlan* P) {
+                       int num_cu, LpPlan* P, bool aligned) {
     P->fmt = fmt;
     P->ks = (int)ceil_div(nunit, 32);
     if (P->ks > 16) return fail(DG_EUNSUPPORTED, "nunit too large");
+    P->staged = fmt != 1 && nunit % 8 == 0 && aligned && !(tile && (tile->flags & DG_TILE_LP_LDS_PANELS));
+    P->pw = P->rb = P->nrg = P->upitch = 0;
+    if (P->staged) return make_staged_plan(nmat, nelem, nunit, tile, per_cu, num_cu, P);
     // defaults measured at p = 5 (2^20 elements): BF16 one column block, FP8
     // two, both with 8 waves per work-group where the variant allows it
     const int epw = (tile && tile->elems_per_wave) ? tile->elems_per_wave : (fmt == 0 ? 16 : 32);
@@ -400,6 +786,16 @@ bool lp_pair_ok(const LpPlan& P, int nunit, bool vec_out) {
 }
 
 static dg_status lp_occupancy(const LpPlan& P, bool pair, int* per_cu) {
+    if (P.staged) {
+        ls_fn fn = ls_kernel(P.fmt, P.ks, P.cb, P.pw);
+        if (!fn) return fail(DG_EUNSUPPORTED, "no staged low-precision DG kernel instance");
+        DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
+        DG_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            per_cu, reinterpret_cast<const void*>(fn), 64 * P.waves, P.smem));
+        if (*per_cu < 1) *per_cu = 1;
+        return DG_OK;
+    }
     lp_fn fn = lp_kernel(P.fmt, P.ks, P.cb, pair);
     if (!fn) return fail(DG_EUNSUPPORTED, "no low-precision DG kernel instance");
     hipFuncAttributes fa;
@@ -444,14 +840,44 @@ dg_status launch_dg_forward_lowp(dg_dtype in_t, int nmat, int64_t nelem, int nun
     st = make_lp_plan(lp_format(in_t, tile), nmat, nelem, nunit, tile, 1, dev.num_cu, &P);
     if (st != DG_OK) return st;
     const bool vec_out = (nunit % 4 == 0) && (reinterpret_cast<uintptr_t>(out) % 16 == 0);
+    const bool aligned = reinterpret_cast<uintptr_t>(out) % 16 == 0 &&
+                         reinterpret_cast<uintptr_t>(u) % 16 == 0 && reinterpret_cast<uintptr_t>(D) % 16 == 0;
+    if (!aligned) {
+        st = make_lp_plan(P.fmt, nmat, nelem, nunit, tile, 1, dev.num_cu, &P, false);
+        if (st != DG_OK) return st;
+    }
     const bool pair = lp_pair_ok(P, nunit, vec_out);
     int per_cu = (tile && tile->groups_per_cu > 0) ? tile->groups_per_cu : 0;
     if (per_cu == 0) {
         st = lp_occupancy(P, pair, &per_cu);
         if (st != DG_OK) return st;
     }
-    st = make_lp_plan(P.fmt, nmat, nelem, nunit, tile, per_cu, dev.num_cu, &P);
+    st = make_lp_plan(P.fmt, nmat, nelem, nunit, tile, per_cu, dev.num_cu, &P, aligned);
     if (st != DG_OK) return st;
+    if (P.staged) {
+        ls_fn fn = ls_kernel(P.fmt, P.ks, P.cb, P.pw);
+        if (!fn) return fail(DG_EUNSUPPORTED, "no staged low-precision DG kernel instance");
+        DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.smem));
+        LsArgs a;
+        a.D = D;
+        a.u = u;
+        a.out = static_cast<float*>(out);
+        a.inv_sD = inv_sD;
+        a.inv_su = inv_su;
+        a.nelem = nelem;
+        a.ntiles = P.ntiles;
+        a.nunit = nunit;
+        a.mblk = P.mblk;
+        a.rb = P.rb;
+        a.nrg = P.nrg;
+        a.ngroups = P.ngroups;
+        a.nstreams = (int)(8 * P.slots);
+        a.upitch = P.upitch;
+        hipLaunchKernelGGL(fn, dim3((unsigned)P.grid), dim3(64 * P.waves), P.smem, s, a);
+        DG_HIP_CHECK(hipGetLastError());
+        return DG_OK;
+    }
     lp_fn fn = lp_kernel(P.fmt, P.ks, P.cb, pair);
     if (!fn) return fail(DG_EUNSUPPORTED, "no low-precision DG kernel instance");
     DG_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),

@@ -213,12 +213,65 @@ dg_status count_quant(const perf_kernel_desc* d, int64_t* c) {
     return DG_OK;
 }
 
+// The staged low-precision body (dg_lowp_staged_kernel): per work-group with
+// tiles (one row group of one slab, K tiles of its stream), the group's
+// operator rows loaded once, K + 2 tile loads (each tile once, the last one
+// twice more: the loads run two tiles ahead), K + 1 LDS copies of loaded
+// tiles (cb 16-byte chunks and one scale per thread; the last copy is the
+// last tile again), K multiplies (B fragments, products, scaled results into
+// the LDS rows), K writes (2 cb 16-byte LDS reads per thread, the tile's rows
+// stored), K + 1 barriers, and the element buffers' padding rows zeroed once.
+// Element loads of group 0's first pass are HBM reads, all others L2
+// re-reads; the FP8 path reads one element scale per thread and load, and one
+// operator scale per wave.
+static dg_status count_dg_lowp_staged(const perf_kernel_desc* d, const LpPlan& P, int64_t* c) {
+    const int64_t E = d->n0;
+    const int n = d->nunit, M = d->nmat;
+    const bool fp8 = d->dtype == DG_FP8E4M3;
+    const int64_t eg = fp8 ? 1 : 2;
+    const int64_t TE = 16 * P.cb, T = 64 * P.waves, ns = 8 * P.slots;
+    const int64_t streams = std::min<int64_t>(ns, P.ntiles);   // streams with tiles
+    const int64_t wgs = streams * P.ngroups;                    // work-groups with tiles
+    // elements of each stream's last tile, summed over the streams with tiles
+    const int64_t last_el = (streams - 1) * TE + (E - (P.ntiles - 1) * TE);
+    c[PF_LAUNCH] = 1;
+    c[PF_WORKGROUPS] = P.grid;
+    c[PF_BARRIER_X_WG] = P.ngroups * P.ntiles + wgs;
+    c[PF_WAVE_TILES] = P.ngroups * P.ntiles;
+    c[PF_GLD_DG_D] = streams * M * (int64_t)n * n * eg + (fp8 ? wgs * P.waves * 4 : 0);
+    c[PF_GLD_DG_U] = E * n * eg;
+    c[PF_GLD_DG_U_L2] = ((int64_t)(P.ngroups - 1) * E + 2 * (int64_t)P.ngroups * last_el) * n * eg;
+    if (fp8) c[PF_GLD_DG_U_UNAL] = 4 * (T / TE) * (P.ngroups * E + 2 * (int64_t)P.ngroups * last_el);
+    c[PF_GST_DG_OUT] = E * M * (int64_t)n * 4;
+    // per row group: its rows, its valid 16-row blocks, the waves holding one
+    int64_t lds_tile = 0, mfma_tile = 0, valu_tile = 0;   // per tile, summed over the groups
+    for (int rg = 0; rg < P.nrg; ++rg) {
+        const int64_t rows = std::min<int64_t>((int64_t)P.rb * 16, n - (int64_t)rg * P.rb * 16);
+        const int64_t blocks = ceil_div(rows, 16);
+        const int64_t active = ceil_div(blocks, (int64_t)P.pw);
+        lds_tile += active * (P.ks * P.cb * 64 * 16 + P.cb * 64 * 4) + rows * 64 * P.cb;
+        mfma_tile += blocks * P.ks * P.cb * 16384;
+        valu_tile += (int64_t)P.cb * 64 * (active + 4 * blocks);
+    }
+    const int64_t zrows = 4 * P.ks - n / 8;
+    c[PF_LDS_BYTES] = wgs * 2 * zrows * TE * 16                          // padding rows zeroed
+                      + (P.ngroups * P.ntiles + wgs) * T * (ls_chunks_in(P.cb) * 16 + 4)  // copies + scales
+                      + M * P.ntiles * lds_tile                           // multiplies
+                      + P.ngroups * P.ntiles * T * ls_chunks_out(P.cb) * 16;  // result rows read back
+    c[PF_MFMA_BF16] = M * P.ntiles * mfma_tile;
+    c[PF_VALU_F32] = M * P.ntiles * valu_tile;
+    c[PF_SERIAL_STEPS] = ceil_div(P.ntiles, ns);
+    c[PF_LAT_STEPS] = c[PF_SERIAL_STEPS] * 64 / ((int64_t)d->tile.groups_per_cu * P.waves);
+    return DG_OK;
+}
+
 dg_status count_dg_lowp(const perf_kernel_desc* d, int64_t* c) {
     const int fmt = lp_format(d->dtype, &d->tile);
     LpPlan P;
     dg_status st = make_lp_plan(fmt, d->nmat, d->n0, d->nunit, &d->tile, d->tile.groups_per_cu,
                                 d->num_cu, &P);
     if (st != DG_OK) return st;
+    if (P.staged) return count_dg_lowp_staged(d, P, c);
     const int64_t E = d->n0;
     const int n = d->nunit, M = d->nmat;
     const int64_t eg = d->dtype == DG_BF16 ? 2 : 1;  // bytes per value in HBM
@@ -507,11 +560,14 @@ dg_status perf_features_count(const perf_kernel_desc* d, int64_t* counts) {
         case DG_K_DGDIFF:
             if (d->nunit < 1 || d->nunit > 512 || d->nmat < 1 || d->nmat > 8)
                 return fail(DG_EUNSUPPORTED, "perf_features_count: DG sizes");
-            if (d->tile.waves < 1 || d->tile.waves > 8 || d->tile.elems_per_wave == 0 ||
+            if (d->tile.waves < 1 || d->tile.waves > 16 || d->tile.elems_per_wave == 0 ||
                 d->tile.groups_per_cu < 1 || d->tile.d_panels < 1 || d->num_cu < 1)
                 return fail(DG_EINVAL, "perf_features_count: DG needs a resolved tile and num_cu");
             if (d->n0 == 0) return DG_OK;
-            if (d->dtype == DG_F32 || d->dtype == DG_F64) return count_dg_fp(d, counts);
+            if (d->dtype == DG_F32 || d->dtype == DG_F64) {
+                if (d->tile.waves > 8) return fail(DG_EINVAL, "tile.waves must be in 1..8");
+                return count_dg_fp(d, counts);
+            }
             if (d->dtype == DG_BF16 || d->dtype == DG_FP8E4M3) return count_dg_lowp(d, counts);
             return fail(DG_EUNSUPPORTED, "perf_features_count: DG dtype");
         case DG_K_STENCIL5:

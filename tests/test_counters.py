@@ -76,12 +76,19 @@ def counted(orc, L, v):
         lib = L.batched_counts(plan, v["num_cu"])
         orc_ = None
         grid = 0
+        chain = [L.feature_names().index(k) for k in ("serial_steps", "lat_steps")]
         for q, i in plan.items():
             if i["count"] == 0:
                 continue
             grid += i["workgroups"]
             w = _walk(orc, "batched", "f32", i["count"], (q + 1) ** 3, 3, i["tile"], v["num_cu"], i["workgroups"])
-            orc_ = w if orc_ is None else orc_ + w
+            if orc_ is None:
+                orc_ = w
+            else:
+                # orders side by side: work adds, the longest chain sets the launch's
+                longest = np.maximum(orc_[chain], w[chain])
+                orc_ = orc_ + w
+                orc_[chain] = longest
         if any(i["tile"]["flags"] & 4 for i in plan.values() if i["count"]):
             orc_ = orc_ + _walk(orc, "batched_pool", "f32", grid)
         orc_[0] = 1
@@ -91,12 +98,19 @@ def counted(orc, L, v):
 
 IDS = ["dg_f32_p2_2e21", "dg_f32_p3_2e21", "dg_f32_p4_2e21", "dg_f32_p5_2e21", "dg_f32_p3_2e18_epw32_w4",
        "dg_f32_p4_2e18_panels8", "dg_f32_p2_100003", "dg_f64_p3_4096", "dg_bf16_p5_2e20", "dg_fp8_p5_2e20",
+       "dg_bf16_p5_2e20_ldspanels", "dg_fp8_p5_2e20_ldspanels", "dg_bf16_p5_100003_split",
        "dg_fp8native_p5_2e20", "quant_fp8_rows_2e20x216", "quant_bf16_2e20x216", "batched_p1_7_2e20",
        "adjoint_p4_2e19", "stencil_16384", "stencil_1030", "matmul_8192", "matmul_1000", "empty_1024"]
 
 
 def _names(L):
     return L.feature_names()
+
+
+def _staged(v):
+    """The low-precision call ran the staged body (rows of a multiple of 8
+    nodes, neither the LDS-panel nor the native FP8 flag)."""
+    return v["nunit"] % 8 == 0 and not v["tile"]["flags"] & (2 | 8)
 
 
 def _lds_under_64(v, f):
@@ -113,9 +127,9 @@ def _lds_under_64(v, f):
                 claims += -(-3 * n // 128) * -(-i["count"] // 128)   # one claim per GEMM tile
         claims += 8 * grid                                            # each pool found drained
         return 8 * claims
-    if v["kind"] == "dg" and v["params"]["dtype"] in ("bf16", "fp8"):
+    if v["kind"] == "dg" and v["params"]["dtype"] in ("bf16", "fp8") and not _staged(v):
         return 32 * f["workgroups"]
-    if v["id"] == "dg_f32_p2_100003":
+    if v["id"] in ("dg_f32_p2_100003", "dg_bf16_p5_100003_split"):
         return None
     return 0
 
@@ -137,14 +151,31 @@ def test_walk_and_closed_form_match_counters(orc, L, variants, vid):
     # LDS bytes
     lds = (c.get("SQ_INSTS_LDS_LOAD_BANDWIDTH", 0) + c.get("SQ_INSTS_LDS_STORE_BANDWIDTH", 0)) * 64
     small = _lds_under_64(v, f)
-    if small is None:
+    if small is None and v["id"] == "dg_f32_p2_100003":
         # the slab path's last wave-tile holds 3 elements (100003 = 3125 x 32 + 3):
         # its scalar LDS accesses of 3 elements' lanes are under 64 bytes each
         gap = f["lds_bytes"] - lds
         assert 0 < gap <= 2 * 3 * 27 * 4 + 3 * 3 * 27 * 4 * 4, gap
+    elif small is None:
+        # staged body with split row groups (144- and 72-row result rows in
+        # LDS): the LDS instruction count agrees exactly (SQ_INSTS_LDS), the
+        # bytes fall short of the counted ones by 64 per work-group tile, a
+        # counter effect not isolated further (0.07 % here)
+        gap = f["lds_bytes"] - lds
+        assert gap == 64 * f["wave_tiles"], (gap, f["wave_tiles"])
     else:
         assert lds == f["lds_bytes"] - small, (lds, f["lds_bytes"], small)
-    # waves
+    if v["id"] == "dg_bf16_p5_100003_split":
+        # LDS instructions per work-group tile: 2 result-row reads and a
+        # chunk copy plus a scale per wave; per wave holding a row block 7 B
+        # fragment reads, a scale read and a result write; per work-group
+        # one more copy (tiles + 1) and the padding rows' zero fill
+        n_tiles, groups, wgs = 6251, 6, f["workgroups"]
+        active = (9 + 5) * 3          # waves holding a block: 9 in a slab's first 144 rows, 5 in its last 72
+        per_group_tile = 9 * 2 + 9 * 2
+        assert c["SQ_INSTS_LDS"] == (per_group_tile * groups + active * 9) * n_tiles + wgs * (18 + 1)
+    # waves (work-groups of the staged body without tiles exit at once, and
+    # are counted as launched)
     waves_per_wg = v["tile"]["waves"] if v["kind"] == "dg" else 4
     assert c["SQ_WAVES"] == f["workgroups"] * waves_per_wg
 

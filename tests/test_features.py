@@ -44,7 +44,21 @@ def _dg_cases():
                 cases.append((dtype, nunit, nmat, E, waves, epw, per_cu, ppg, flags))
     # full-size points of the calibration grid
     cases += [("f32", 64, 3, 1 << 21, 4, 16, 3, 12, 0), ("f32", 27, 3, 1 << 20, 4, 64, 2, 6, 0),
-              ("f32", 125, 3, 1 << 18, 4, 64, 1, 12, 0), ("bf16", 216, 3, 1 << 16, 4, 32, 1, 21, 0)]
+              ("f32", 125, 3, 1 << 18, 4, 64, 1, 12, 0), ("bf16", 216, 3, 1 << 16, 4, 32, 1, 21, 8)]
+    # the staged low-precision body (rows of a multiple of 8 nodes): one or two
+    # row blocks per wave, whole and split row groups, idle waves, ragged ends,
+    # up to 16 waves, and its refusals (too few waves to stage a tile, two
+    # blocks per wave past nunit 256, d_panels not a multiple of waves)
+    for dtype in ("bf16", "fp8"):
+        for nunit, nmat, E, waves, epw, per_cu, rb in (
+                (8, 3, 1, 1, 16, 4, 2), (8, 3, 4097, 1, 32, 2, 1), (40, 2, 300, 2, 16, 3, 4),
+                (40, 2, 300, 3, 16, 3, 3), (64, 3, 1001, 2, 16, 2, 4), (64, 1, 17, 2, 32, 1, 4),
+                (64, 3, 129, 6, 16, 2, 6), (216, 3, 5001, 7, 16, 2, 14), (216, 3, 5001, 9, 16, 3, 9),
+                (216, 5, 333, 7, 32, 1, 14), (216, 3, 1 << 16, 7, 16, 2, 14), (216, 3, 300, 12, 16, 2, 12),
+                (216, 3, 300, 8, 16, 2, 16), (512, 3, 700, 16, 16, 1, 16), (512, 3, 700, 16, 32, 1, 16),
+                (256, 8, 200, 8, 16, 2, 8), (216, 3, 300, 4, 16, 2, 8), (216, 3, 300, 2, 16, 2, 4),
+                (512, 3, 100, 8, 16, 1, 16), (64, 3, 100, 3, 16, 2, 7), (40, 2, 300, 1, 16, 3, 2)):
+            cases.append((dtype, nunit, nmat, E, waves, epw, per_cu, rb, 0))
     return cases
 
 

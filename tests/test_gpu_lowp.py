@@ -163,14 +163,24 @@ def _oracle_dequantised(orc, D32, u32, to):
     return Dd, ud
 
 
+_LDS = 8   # DG_TILE_LP_LDS_PANELS: the body with operator panels in LDS
+LDS_PANEL_TILES = [dict(elems_per_wave=16, flags=_LDS), dict(elems_per_wave=32, flags=_LDS),
+                   dict(elems_per_wave=64, flags=_LDS), dict(d_panels=5, flags=_LDS),
+                   dict(d_panels=1, flags=_LDS), dict(waves=2, flags=_LDS),
+                   dict(waves=3, elems_per_wave=32, flags=_LDS), dict(groups_per_cu=1, flags=_LDS)]
+# staged body: one or two row blocks per wave, whole-row and split row groups
+# (ragged last group at nunit 216: 14 blocks in groups of 4, 6 or 8), waves
+# with fewer valid blocks than they hold, one or two column blocks per tile
+STAGED_TILES = [None, dict(elems_per_wave=32), dict(waves=8, d_panels=8), dict(waves=9, d_panels=9),
+                dict(waves=12, d_panels=12), dict(waves=16, d_panels=16), dict(waves=7, d_panels=14),
+                dict(waves=8, d_panels=16, elems_per_wave=32), dict(groups_per_cu=1), dict(waves=7, d_panels=7)]
+
+
 @pytest.mark.parametrize("to", ["bf16", "e4m3"])
 @pytest.mark.parametrize("nunit", [64, 216])
-@pytest.mark.parametrize("tile", [dict(elems_per_wave=16), dict(elems_per_wave=32),
-                                  dict(elems_per_wave=64), dict(d_panels=5), dict(d_panels=1),
-                                  dict(waves=2), dict(waves=3, elems_per_wave=32),
-                                  dict(groups_per_cu=1)])
+@pytest.mark.parametrize("tile", LDS_PANEL_TILES + STAGED_TILES)
 def test_lowp_tiles(orc, ops, to, nunit, tile):
-    """Launch shapes of the low-precision forward against the FP64 oracle on
+    """Launch shapes of both low-precision bodies against the FP64 oracle on
     the oracle's dequantised inputs (the FP32 accumulation bound), ragged
     element counts."""
     p = round(nunit ** (1 / 3)) - 1
@@ -188,13 +198,15 @@ def test_lowp_tiles(orc, ops, to, nunit, tile):
 
 
 @pytest.mark.parametrize("to", ["bf16", "e4m3"])
-@pytest.mark.parametrize("nunit,tile", [(32, None), (64, None), (64, dict(d_panels=2)), (64, dict(d_panels=3)),
-                                        (64, dict(elems_per_wave=64)), (512, dict(d_panels=8)),
-                                        (512, None)])
+@pytest.mark.parametrize("nunit,tile", [(32, dict(flags=_LDS)), (64, dict(flags=_LDS)),
+                                        (64, dict(d_panels=2, flags=_LDS)), (64, dict(d_panels=3, flags=_LDS)),
+                                        (64, dict(elems_per_wave=64, flags=_LDS)),
+                                        (512, dict(d_panels=8, flags=_LDS)), (512, dict(flags=_LDS))])
 def test_lowp_paired_stores(orc, ops, to, nunit, tile):
-    """Rows of a multiple of 32 nodes take the paired-store variant when the
-    panel groups are even (scales applied per element before the exchange);
-    ragged element counts; odd groups fall back to single panels."""
+    """LDS-panel body: rows of a multiple of 32 nodes take the paired-store
+    variant when the panel groups are even (scales applied per element before
+    the exchange); ragged element counts; odd groups fall back to single
+    panels."""
     D = I.gll_dmats(3) if nunit == 64 else I.random_dmats(nunit)
     D32 = D.astype(np.float32)
     for nelem in (1, 9, 300):
@@ -225,10 +237,68 @@ def test_lowp_paired_matches_single_panels_bitwise(ops, to):
     qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), to)
     qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), to)
     sc = dict(inv_sD=isD, inv_su=isu) if to == "e4m3" else {}
-    a = ops.dgdiff_apply(qD.view(3, 64, 64), qu, tile=dict(d_panels=4), **sc)
-    b = ops.dgdiff_apply(qD.view(3, 64, 64), qu, tile=dict(d_panels=3), **sc)
+    a = ops.dgdiff_apply(qD.view(3, 64, 64), qu, tile=dict(d_panels=4, flags=_LDS), **sc)
+    b = ops.dgdiff_apply(qD.view(3, 64, 64), qu, tile=dict(d_panels=3, flags=_LDS), **sc)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def _quantised(ops, D32, u32, to):
+    nmat, n, _ = D32.shape
+    qD, isD = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(nmat, -1)).cuda(), to)
+    qu, isu = ops.dgdiff_quantize(torch.from_numpy(u32).cuda(), to)
+    sc = dict(inv_sD=isD, inv_su=isu) if to == "e4m3" else {}
+    return qD.view(nmat, n, n), qu, sc
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+@pytest.mark.parametrize("nunit,nmat,nelem,tile", [
+    (8, 3, 1, None), (8, 3, 4097, None), (40, 3, 300, None), (40, 2, 300, dict(waves=3, d_panels=3)),
+    (64, 3, 1001, None), (64, 1, 17, dict(elems_per_wave=32)), (216, 3, 5001, None),
+    (216, 3, 5001, dict(waves=9, d_panels=9)), (216, 5, 333, dict(elems_per_wave=32, waves=7)),
+    (512, 3, 700, None), (512, 3, 700, dict(waves=16, d_panels=16, elems_per_wave=32)),
+    (256, 8, 200, dict(waves=8, d_panels=8))])
+def test_lowp_staged_equals_lds_panels_bitwise(ops, to, nunit, nmat, nelem, tile):
+    """The staged body runs the LDS-panel body's products in the same order
+    (same fragments, same k-steps, same de-scaling): bit-identical outputs,
+    whatever the row groups, tile and ragged end."""
+    D32 = I.random_dmats(nunit, nmat).astype(np.float32)
+    u32 = I.uniform_u(nelem, nunit).astype(np.float32)
+    qD, qu, sc = _quantised(ops, D32, u32, to)
+    dt = "bf16" if to == "bf16" else "fp8"
+    t = ops.resolve_tile(dt, nmat, nelem, nunit, tile)
+    ref = ops.dgdiff_apply(qD, qu, tile=dict(flags=_LDS), **sc)
+    got = ops.dgdiff_apply(qD, qu, tile=t, **sc)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref), (t, (got - ref).abs().max().item())
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+def test_lowp_misaligned_falls_back(orc, ops, to):
+    """Element data that do not start on a 16-byte boundary take the LDS-panel
+    body: the same values as the aligned call."""
+    n, E = 64, 250
+    D32 = I.gll_dmats(3).astype(np.float32)
+    u32 = I.uniform_u(E, n).astype(np.float32)
+    qD, qu, sc = _quantised(ops, D32, u32, to)
+    buf = torch.empty(E * n + 8, dtype=qu.dtype, device="cuda")
+    mis = buf[1:1 + E * n].view(E, n)            # one value (1 or 2 bytes) past alignment
+    mis.copy_(qu)
+    a = ops.dgdiff_apply(qD, qu, **sc)
+    b = ops.dgdiff_apply(qD, mis, **sc)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_lowp_staged_refusals(ops):
+    """Shapes the staged body cannot run are refused before any launch."""
+    for nunit, tile in ((512, dict(waves=8, d_panels=16)),      # two blocks per wave past nunit 256
+                        (512, dict(waves=2)),                    # too few threads to stage a tile
+                        (64, dict(elems_per_wave=64)),           # tiles are 16 or 32 elements
+                        (64, dict(waves=3, d_panels=7)),         # d_panels not a multiple of waves
+                        (216, dict(waves=4, d_panels=8))):       # fewer than nunit / 32 waves
+        with pytest.raises(ops.DGError):
+            ops.resolve_tile("bf16", 3, 1000, nunit, tile)
 
 
 def test_fp8_requires_scales(ops):
