@@ -189,7 +189,10 @@ def row_lowp(L, I, torch, steps, checks):
     res["fp32"] = {"ms": t32 * 1e3, "elements_per_s": E / t32, "roofline": roofline(b, f, t32, "f32")}
     checks.append({"at": ("precision_p5_2e20", "fp32"), "kind": "dg", "D": D64, "u": usel,
                    "got": gather_out(torch, o, sel)})
-    for name, to, flags in (("bf16", "bf16", 0), ("fp8", "e4m3", 0), ("fp8_native", "e4m3", 2)):
+    # default bodies (the staged one at nunit 216), the body with operator
+    # panels in LDS for comparison, and the opt-in native FP8 instruction
+    for name, to, flags in (("bf16", "bf16", 0), ("fp8", "e4m3", 0), ("bf16_lds_panels", "bf16", 8),
+                            ("fp8_lds_panels", "e4m3", 8), ("fp8_native", "e4m3", 2)):
         qD, isD = L.dgdiff_quantize(Dg.reshape(3, -1), to)
         qu, isu = L.dgdiff_quantize(u32, to)
         sc = dict(inv_sD=isD, inv_su=isu) if to == "e4m3" else {}
@@ -205,7 +208,9 @@ def row_lowp(L, I, torch, steps, checks):
         te = timed(e2e, steps, 2)
         eb = 2 if to == "bf16" else 1
         b, f = dg_bytes_flops(E, n, eb, 4)
-        res[name] = {"ms": t * 1e3, "elements_per_s": E / t, "speedup_vs_fp32": t32 / t,
+        shape = L.resolve_tile("bf16" if to == "bf16" else "fp8", 3, E, n, tile)
+        res[name] = {"body": "lds_panels" if flags else "staged", "shape": shape,
+                     "ms": t * 1e3, "elements_per_s": E / t, "speedup_vs_fp32": t32 / t,
                      "quantize_u_and_apply_ms": te * 1e3, "quantize_u_and_apply_speedup_vs_fp32": t32 / te,
                      "roofline": roofline(b, f, t, "bf16" if name != "fp8_native" else "fp8")}
         # the last e2e call wrote o with freshly quantised (identical) codes
@@ -434,7 +439,7 @@ def model_vector(summary, names, family="dg"):
     from paper_1904_09538_amd import calibrate as C
     for feat, p in zip(f["features"], f["params"]):
         cost[names.index(feat)] = p
-        group[names.index(feat)] = C.GROUP[feat]
+        group[names.index(feat)] = C.group_of(family, feat)
     if f["kind"] == "linear":
         return {"cost": cost, "group": None}
     return {"cost": cost, "group": group, "edge": f["edge"]}

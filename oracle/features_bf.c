@@ -600,18 +600,22 @@ static int quant_walk(int dtype, int64_t rows, int64_t cols, int per_row, int64_
     if (rows == 0 || cols == 0) return 0;
     if (!per_row && fp8) {
         const int64_t N = rows * cols;
-        const int64_t blocks = maxi(1, mini(cdiv(N, 1024), 2048)), T = blocks * 256;
+        const int64_t blocks = maxi(1, mini(cdiv(N, 1024), 1024)), T = blocks * 256;
         const int64_t nv = N / 4;
         c[F_LAUNCH] += 4;
         c[F_WG] += 1 + blocks + blocks + 1;
         c[F_WS_ST] += 4;                                   /* clear the maximum */
         for (int pass = 0; pass < 2; ++pass) {             /* maximum, encode */
-            for (int64_t w = 0; w < T / 64; ++w) {
-                if (pass == 0) {
-                    c[F_WS_ST] += 4;                           /* atomic maximum */
-                } else {
-                    c[F_WS_LD] += 4;                           /* the maximum, wave-uniform */
+            if (pass == 0)
+                for (int64_t b = 0; b < blocks; ++b) {
+                    c[F_LDS] += 4 * 4 + 4 * 4;                 /* four wave maxima stored, read once */
+                    c[F_WS_ST] += 4;                           /* one atomic maximum per work-group */
+                    c[F_BAR] += 1;
                 }
+            for (int64_t w = 0; w < T / 64; ++w) {
+                if (pass == 1) c[F_WS_LD] += 4;                /* the maximum, wave-uniform */
+                /* the wave's vector-loop trips (its first lane has the most) */
+                for (int64_t v = 64 * w; v < nv; v += T) c[F_WAVE_TILES] += 1;
             }
             for (int64_t gid = 0; gid < T; ++gid) {
                 for (int64_t v = gid; v < nv; v += T) {
@@ -647,6 +651,7 @@ static int quant_walk(int dtype, int64_t rows, int64_t cols, int per_row, int64_
             int64_t steps = 0;
             for (int64_t r0 = w; r0 < rows; r0 += 4 * W) {
                 ++steps;
+                c[F_WAVE_TILES] += 1;   /* one wave-step: four rows in flight */
                 for (int j = 0; j < 4; ++j) {
                     const int64_t r = r0 + j * W;
                     if (r >= rows) continue;
@@ -677,6 +682,7 @@ static int quant_walk(int dtype, int64_t rows, int64_t cols, int per_row, int64_
             int64_t steps = 0;
             for (int64_t r = w; r < rows; r += W) {
                 ++steps;
+                c[F_WAVE_TILES] += 1;   /* one wave-step: one row */
                 for (int lane = 0; lane < 64; ++lane) {
                     for (int64_t cc = lane; cc < cols; cc += 64) {
                         c[F_U_UNAL] += 4;

@@ -61,7 +61,16 @@ GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0, "seri
 # adjoint are contractions like DG (overlap), the quantiser a streaming pass
 # like the stencil (linear)
 KIND = {"dg": "overlap", "stencil": "linear", "matmul": "overlap", "batched": "overlap",
-        "bwd": "overlap", "quant": "linear"}
+        "bwd": "overlap", "quant": "overlap"}
+# Family-specific cost groups.  The quantiser's wave-steps are round trips
+# whose latency overlaps the streaming of other waves' rows (short rows are
+# bound by the steps, long ones by the bytes), so they compete with the
+# global traffic on the on-chip side of the overlap model.
+FAMILY_GROUP = {"quant": {"wave_tiles": 2}}
+
+
+def group_of(family, feat):
+    return FAMILY_GROUP.get(family, {}).get(feat, GROUP[feat])
 MODELS = {
     "dg": ["launch", "workgroups", "wave_tiles", "serial_steps", "lat_steps", "gld_dg_u", "gld_dg_u_unal",
            "gld_dg_u_l2",
@@ -80,7 +89,9 @@ MODELS = {
     "bwd": ["launch", "workgroups", "serial_steps", "lat_steps", "barrier_x_wg", "gld_dg_u", "gld_dg_u_unal",
             "gld_dg_u_l2", "gld_dg_d", "gld_ws", "gst_ws", "gst_dg_out", "gst_dg_out_unal", "lds_bytes",
             "mfma_f32", "valu_f32"],
-    "quant": ["launch", "workgroups", "serial_steps", "gld_dg_u", "gld_dg_u_unal", "gst_dg_out",
+    # wave_tiles: wave-steps (four short rows, or one long row, or one trip of
+    # the whole-array loops), each a round trip of loads and stores
+    "quant": ["launch", "workgroups", "wave_tiles", "serial_steps", "gld_dg_u", "gld_dg_u_unal", "gst_dg_out",
               "gst_dg_out_unal", "gld_ws", "gst_ws", "lds_bytes", "valu_f32"],
 }
 
@@ -648,7 +659,7 @@ def fit_family(meta, rows, family, L, kind=None, with_overhead_rows=True):
     "unconstrained" with its negative weights listed."""
     names = meta["feature_names"]
     cols = [names.index(f) for f in MODELS[family]]
-    group = [GROUP[f] for f in MODELS[family]]
+    group = [group_of(family, f) for f in MODELS[family]]
     fam = [r for r in rows if r["family"] == family]
     F = np.array([[r["features"][c] for c in cols] for r in fam], dtype=np.float64)
     t = np.array([r["t"]["mean"] for r in fam])
@@ -711,7 +722,7 @@ def final_model(meta, rows, family, L, kind):
     (training and held-out) plus the empty-kernel rows, weights >= 0."""
     names = meta["feature_names"]
     cols = [names.index(f) for f in MODELS[family]]
-    group = [GROUP[f] for f in MODELS[family]]
+    group = [group_of(family, f) for f in MODELS[family]]
     use = [r for r in rows if r["family"] in (family, "empty")]
     F = np.array([[r["features"][c] for c in cols] for r in use], dtype=np.float64)
     t = np.array([r["t"]["mean"] for r in use])

@@ -397,6 +397,95 @@ def _write_md(out, md_out, command):
         fh.write("\n".join(lines) + "\n")
 
 
+# ------------------------------------------------------------------ one kernel's profile
+
+def _read_stats(d):
+    """Kernel rows of a rocprofv3 --kernel-trace --stats folder:
+    {name: (calls, avg_ns, min_ns, max_ns)}."""
+    files = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no kernel_stats.csv under {d}")
+    out = {}
+    with open(files[0], newline="") as fh:
+        for row in csv.DictReader(fh):
+            out[row["Name"]] = (int(row["Calls"]), float(row["AverageNs"]), float(row["MinNs"]),
+                                float(row["MaxNs"]))
+    return out
+
+
+def profile(name, match, trace_dir, fetch_dir, write_dir, commands, md_out, traffic_json, key, sources):
+    """Summarise one kernel's rocprofv3 runs: the kernel-trace statistics of
+    every kernel, and the kernel's HBM bytes per launch from FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for the plain device
+    copy in the same run (bytes / counter KiB).  Writes the markdown summary
+    and the traffic entry (with a hash of the kernel's sources, so that a
+    changed kernel drops its stale traffic)."""
+    import hashlib
+    stats = _read_stats(trace_dir)
+    fetch = _read_pmc(fetch_dir)
+    write = _read_pmc(write_dir)
+
+    def per_launch(disp, counter):
+        mine = [c[counter] for _, n, _, c in disp if match in n]
+        copy = [(c[counter], g) for _, n, g, c in disp if "copyBuffer" in n]
+        if not mine or not copy:
+            raise ValueError(f"{counter}: kernel or copy probe missing")
+        return sum(mine) / len(mine), copy[-1][0]
+
+    f_kib, f_copy = per_launch(fetch, "FETCH_SIZE")
+    w_kib, w_copy = per_launch(write, "WRITE_SIZE")
+    copy_bytes = 1 << 30
+    fs, ws = copy_bytes / (f_copy * 1024), copy_bytes / (w_copy * 1024)
+    rd, wr = f_kib * 1024 * fs, w_kib * 1024 * ws
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for f in sources:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    mine = {n: v for n, v in stats.items() if match in n}
+    avg = next(iter(mine.values()))[1] * 1e-9 if mine else None
+    lines = [f"# rocprofv3 summary: {name}", "", "## Kernel trace (--kernel-trace --stats)", "", "Command:", "",
+             "```", commands[0], "```", "", "| kernel | calls | avg (us) | min (us) | max (us) |", "|---|---|---|---|---|"]
+    for n, (calls, a, lo, hi) in sorted(stats.items(), key=lambda kv: -kv[1][0] * kv[1][1])[:8]:
+        lines.append(f"| `{n[:110]}` | {calls} | {a / 1e3:.1f} | {lo / 1e3:.1f} | {hi / 1e3:.1f} |")
+    lines += ["", "## HBM traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE, separate runs)", "", "Commands:", "",
+              "```", commands[1], commands[2], "```", "",
+              f"Calibration: a plain 1 GiB device copy (`__amd_rocclr_copyBuffer`) reads FETCH_SIZE = "
+              f"{f_copy:.0f} KiB and WRITE_SIZE = {w_copy:.0f} KiB per dispatch,",
+              f"so the scale factors are fetch x{fs:.4f} and write x{ws:.4f}.", "",
+              "| quantity | per launch |", "|---|---|",
+              f"| HBM read (FETCH_SIZE x {fs:.4f}) | {rd:.4e} B |",
+              f"| HBM written (WRITE_SIZE x {ws:.4f}) | {wr:.4e} B |",
+              f"| total | {rd + wr:.4e} B |"]
+    if avg:
+        lines.append(f"| average duration (trace) | {avg * 1e6:.1f} us |")
+    with open(md_out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    data = {}
+    if os.path.exists(traffic_json):
+        with open(traffic_json) as fh:
+            data = json.load(fh)
+    data[key] = {"avg_duration_s": avg, "fetch_scale": fs, "write_scale": ws, "read_bytes": rd,
+                 "write_bytes": wr, "hbm_bytes_per_launch": rd + wr, "source_hash": h.hexdigest()[:16],
+                 "summary": os.path.relpath(md_out, root)}
+    with open(traffic_json, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    return data[key]
+
+
+def stats_table(trace_dir, title, preamble, command, md_out, top=40):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (kernels by
+    total time)."""
+    stats = _read_stats(trace_dir)
+    lines = [f"# rocprofv3 summary: {title}", ""] + preamble + ["", "Command:", "", "```", command, "```", "",
+                                                                "| kernel | calls | avg (us) | min (us) | max (us) |",
+                                                                "|---|---|---|---|---|"]
+    for n, (calls, a, lo, hi) in sorted(stats.items(), key=lambda kv: -kv[1][0] * kv[1][1])[:top]:
+        lines.append(f"| `{n[:110]}` | {calls} | {a / 1e3:.1f} | {lo / 1e3:.1f} | {hi / 1e3:.1f} |")
+    with open(md_out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -408,9 +497,31 @@ def main():
     s.add_argument("--json", required=True)
     s.add_argument("--md", required=True)
     s.add_argument("--command", default="")
+    f = sub.add_parser("profile")
+    f.add_argument("--name", required=True)
+    f.add_argument("--match", required=True, help="substring of the kernel's name")
+    f.add_argument("--trace", required=True)
+    f.add_argument("--fetch", required=True)
+    f.add_argument("--write", required=True)
+    f.add_argument("--commands", nargs=3, required=True, help="trace, fetch and write commands")
+    f.add_argument("--md", required=True)
+    f.add_argument("--traffic", required=True)
+    f.add_argument("--key", required=True)
+    f.add_argument("--sources", nargs="+", required=True)
+    t = sub.add_parser("stats")
+    t.add_argument("--trace", required=True)
+    t.add_argument("--title", required=True)
+    t.add_argument("--preamble", nargs="*", default=[])
+    t.add_argument("--command", required=True)
+    t.add_argument("--md", required=True)
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.out)
+    elif a.cmd == "stats":
+        stats_table(a.trace, a.title, a.preamble, a.command, a.md)
+    elif a.cmd == "profile":
+        print(json.dumps(profile(a.name, a.match, a.trace, a.fetch, a.write, a.commands, a.md, a.traffic,
+                                 a.key, a.sources)))
     else:
         summarise(a.variants, a.pmc, a.json, a.md, a.command)
 

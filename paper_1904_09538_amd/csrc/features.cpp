@@ -184,14 +184,20 @@ dg_status count_quant(const perf_kernel_desc* d, int64_t* c) {
         const int64_t N = rows * cols, tail = N % 4, waves = 4 * P.blocks;
         c[PF_LAUNCH] += 4;
         c[PF_WORKGROUPS] += 2 + 2 * P.blocks;
-        c[PF_GST_WS] += 4 + 4 * waves;          // cleared maximum; one atomic maximum per wave
+        c[PF_GST_WS] += 4 + 4 * P.blocks;       // cleared maximum; one atomic maximum per work-group
         c[PF_GLD_WS] += 4 * waves + 4;          // the maximum, read once per encode wave and at the end
+        c[PF_LDS_BYTES] += 32 * P.blocks;       // four wave maxima stored and read back per work-group
+        c[PF_BARRIER_X_WG] += P.blocks;
         c[PF_GLD_DG_U] += 2 * 4 * (N - tail);   // maximum pass and encode pass, 16-byte vectors
         c[PF_GLD_DG_U_UNAL] += 2 * 4 * tail;
         c[PF_GST_DG_OUT] += N - tail;           // four codes per store
         c[PF_GST_DG_OUT_UNAL] += tail + 4;      // tail codes; the inverse scale
         c[PF_VALU_F32] += N;                    // x * s
         c[PF_SERIAL_STEPS] += ceil_div(N / 4, 256 * P.blocks);
+        // wave-steps of the two vector loops: with T threads, wave w runs
+        // nv / T trips plus one while its first vector 64 w is below nv % T
+        const int64_t T = 256 * P.blocks, nv = N / 4;
+        c[PF_WAVE_TILES] += 2 * ((T / 64) * (nv / T) + ceil_div(nv % T, 64));
         return DG_OK;
     }
     const int64_t vec = cols % 4 == 0;
@@ -203,11 +209,15 @@ dg_status count_quant(const perf_kernel_desc* d, int64_t* c) {
         c[vec ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] += rows * cols * esz;
         if (fp8) c[PF_VALU_F32] += rows * 4 * ceil_div(cols, 4);   // x * s on whole 4-value vectors
         c[PF_SERIAL_STEPS] += ceil_div(rows, 4 * nwaves);
+        // wave-steps of four rows: wave w takes rows w, w + W, w + 2W, w + 3W,
+        // then w + 4W ...: rows / 4W steps plus one while w < rows % 4W
+        c[PF_WAVE_TILES] += nwaves * (rows / (4 * nwaves)) + std::min<int64_t>(nwaves, rows % (4 * nwaves));
     } else {
         c[PF_GLD_DG_U_UNAL] += rows * cols * 4 * (fp8 ? 2 : 1);  // FP8 reads the row twice
         c[PF_GST_DG_OUT_UNAL] += rows * cols * esz;
         if (fp8) c[PF_VALU_F32] += rows * cols;
         c[PF_SERIAL_STEPS] += ceil_div(rows, nwaves);
+        c[PF_WAVE_TILES] += rows;   // one row per wave-step
     }
     c[PF_GST_DG_OUT_UNAL] += per_row ? rows * 4 : 4;  // inverse scales (always requested)
     return DG_OK;

@@ -270,8 +270,18 @@ __global__ void __launch_bounds__(256) quantize_global_amax(const float* __restr
         const float a = fabsf(x[i]);
         amax = a > amax ? a : amax;
     }
+    // the work-group's maximum (four wave maxima through LDS), then one
+    // atomic per work-group: thousands of waves contending for one word
+    // cost more than the pass itself on small arrays
+    __shared__ float wmax[4];
     amax = wave_max(amax);
-    if ((threadIdx.x & 63) == 0) atomicMax(amax_bits, f32_bits(amax));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = wmax[0];
+        for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+        atomicMax(amax_bits, f32_bits(m));
+    }
 }
 
 template <bool VEC>
@@ -316,7 +326,7 @@ QuantPlan quant_plan(int fp8, int64_t rows, int64_t cols, int per_row) {
     P.cols = cols;
     if (!per_row && fp8) {
         P.kind = QuantPlan::kGlobal;
-        P.blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(rows * cols, 1024), 2048));
+        P.blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(rows * cols, 1024), 1024));
         return P;
     }
     if (cols <= 1024) {
