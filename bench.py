@@ -237,7 +237,7 @@ def row_lowp(L, I, torch, steps, checks):
     return {"config": "hex p=5, 2^20 elements, FP32 output and accumulation", **res}
 
 
-def row_batched(L, I, torch, steps, model, checks):
+def row_batched(L, I, torch, steps, model, checks, model_overlap=None):
     E = 1 << 20
     order = I.batched_orders(E)
     off = I.batched_offsets(order)
@@ -259,6 +259,8 @@ def row_batched(L, I, torch, steps, model, checks):
     pred = sum(i["predicted_s"] for i in info.values() if i["count"]) if model else None
     feats = L.batched_counts(info, torch.cuda.get_device_properties(0).multi_processor_count)
     pred_counts = model_predict(model, feats) if model else None
+    mo = model_overlap or (model if model and model.get("group") else None)
+    pred_counts_ov = model_predict(mo, feats) if mo else None
     sel = sample_elements(E)
     for p in range(1, 8):
         sp = sel[order[sel] == p]
@@ -298,6 +300,9 @@ def row_batched(L, I, torch, steps, model, checks):
                            "that ran it",
            "predicted_ms_launch_counts": pred_counts * 1e3 if pred_counts else None,
            "launch_counts_rel_error": (pred_counts - tb) / tb if pred_counts else None,
+           "predicted_ms_launch_counts_overlap_form": pred_counts_ov * 1e3 if pred_counts_ov else None,
+           "launch_counts_overlap_form_rel_error": (pred_counts_ov - tb) / tb if pred_counts_ov else None,
+           "plan": {p: {k: info[p][k] for k in ("count", "workgroups", "predicted_s")} for p in info},
            "shapes": {p: plan.info(p)["tile"] for p in range(1, 8)}}
     log(f"batched: {tb * 1e3:.3f} ms vs 7 launches {t7 * 1e3:.3f} ms, predicted "
         f"{pred * 1e3 if pred else float('nan'):.3f} ms")
@@ -429,11 +434,16 @@ def row_model(path):
                            "non-negative fit primary, unconstrained fit beside"}
 
 
-def model_vector(summary, names, family="dg"):
+def model_vector(summary, names, family="dg", form=None):
     """A family's model of a calibration summary as a per-feature cost vector
     (the non-negative fit, whose costs stay positive wherever the batch's
-    orders and sizes fall relative to the calibration set)."""
+    orders and sizes fall relative to the calibration set); form="overlap"
+    takes the family's overlap-form fit where the chosen form is linear."""
     f = summary["families"][family]
+    if form == "overlap" and f["kind"] != "overlap":
+        if "overlap_form" not in f:
+            return None
+        f = {**f, **f["overlap_form"], "kind": "overlap"}
     cost = [0.0] * len(names)
     group = [0] * len(names)
     from paper_1904_09538_amd import calibrate as C
@@ -603,9 +613,10 @@ def main():
     if "lowp" in want:
         rows["precision_p5_2e20"] = row_lowp(L, I, torch, small, checks)
     if "batched" in want:
-        mv = (model_vector(model_summary, L.feature_names(), "batched")
-              if model_summary and "batched" in model_summary["families"] else None)
-        rows["batched_mixed_p1_7_2e20"] = row_batched(L, I, torch, small, mv, checks)
+        have = model_summary and "batched" in model_summary["families"]
+        mv = model_vector(model_summary, L.feature_names(), "batched") if have else None
+        mo = model_vector(model_summary, L.feature_names(), "batched", form="overlap") if have else None
+        rows["batched_mixed_p1_7_2e20"] = row_batched(L, I, torch, small, mv, checks, mo)
     if "adjoint" in want:
         rows["adjoint_p4_2e19"] = row_adjoint(L, I, torch, small, checks)
     if "companions" in want:

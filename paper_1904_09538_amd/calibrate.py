@@ -707,6 +707,14 @@ def fit_family(meta, rows, family, L, kind=None, with_overhead_rows=True):
     prim, pred = one(True)
     out.update(prim)
     out["unconstrained"], upred = one(False)
+    if family == "batched" and kind == "linear":
+        # the overlap form beside the chosen one: a mixed launch runs its
+        # orders side by side, memory-bound low orders under MFMA-bound high
+        # ones, which a sum of per-order costs cannot express
+        chosen, kind = kind, "overlap"
+        ov, _ = one(True)
+        kind = chosen
+        out["overlap_form"] = {k: ov[k] for k in ("params", "edge", "mape_heldout", "negative_params")}
     out["heldout"] = [{"variant": {k: fam[i][k] for k in fam[i] if k not in ("features", "t")},
                        "measured_s": float(t[i]), "predicted_s": float(pred[i])} for i in held]
     if family in ("dg", "batched"):
