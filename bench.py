@@ -430,6 +430,7 @@ def row_model(path):
                "geomean_heldout_all": s["geomean_heldout_all"], "families": fams,
                "cross_kernel": cross, "fresh_heldout": fresh_row,
                "microbenchmark_calibrated": micro, "overlap_diagnosis": overlap,
+               "read_pattern_ab": s.get("pattern_ab"),
                "protocol": "cold cache, 60 event-timed trials per variant, 20% held out (seed 4); "
                            "non-negative fit primary, unconstrained fit beside"}
 

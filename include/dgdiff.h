@@ -337,6 +337,14 @@ dg_status dgdiff_resolve_backward(dg_dtype t, int32_t nmat, int64_t nelem, int32
                                                                   (tile: a resolved FP32 forward tile)
      DG_UB_TWIN_STENCIL  n              ld_u             ld_res   in[0] = u, out = res (vector path layout)
      DG_UB_TWIN_MATMUL   n              -                -        in[0] = a, in[1] = b, out = c
+     DG_UB_TILE_READ     n (mult. of 16) pattern 0 or 1  -        in[0] [n*n], out [n*n]: the square
+                                                                  matmul's tiled operand fetches of
+                                                                  Section "Global Memory Access Pattern
+                                                                  Features": 16x16 work-group (g0, g1),
+                                                                  thread (l0, l1) reads, at trip k < n/16,
+                                                                  pattern 0 (a): x[n(16 g1 + l1) + 16k + l0],
+                                                                  pattern 1 (b): x[n(16k + l1) + 16 g0 + l0],
+                                                                  and stores the sum at (16 g1 + l1, 16 g0 + l0)
    The twins' outputs carry no meaning beyond covering every element the
    original writes.  perf_ubench_count gives the launch's counts (as
    perf_features_count; twins count the original's global accesses, with the
@@ -351,7 +359,8 @@ typedef enum {
     DG_UB_OVERLAP = 6,
     DG_UB_TWIN_DG = 7,
     DG_UB_TWIN_STENCIL = 8,
-    DG_UB_TWIN_MATMUL = 9
+    DG_UB_TWIN_MATMUL = 9,
+    DG_UB_TILE_READ = 10
 } dg_ubench;
 
 typedef struct {

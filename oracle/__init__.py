@@ -219,7 +219,7 @@ def features(kernel, dtype, n0, nunit=0, nmat=0, elems_per_wave=0, waves=0, grou
 
 
 UBENCH = {"stream": 0, "strided": 1, "fma": 2, "mfma": 3, "lds": 4, "barrier": 5, "overlap": 6,
-          "twin_dg": 7, "twin_stencil": 8, "twin_matmul": 9}
+          "twin_dg": 7, "twin_stencil": 8, "twin_matmul": 9, "tile_read": 10}
 
 
 def ubench_features(kind, n, a=0, b=0, dtype="f32", tile=None, num_cu=0):

@@ -1058,7 +1058,7 @@ int orc_features(int kernel, int dtype, int64_t n0, int nunit, int nmat, int epw
 /* ---------------------------------------------------------------- measurement kernels */
 
 enum { UB_STREAM, UB_STRIDED, UB_FMA, UB_MFMA, UB_LDS, UB_BARRIER, UB_OVERLAP, UB_TWIN_DG, UB_TWIN_STENCIL,
-       UB_TWIN_MATMUL };
+       UB_TWIN_MATMUL, UB_TILE_READ };
 
 /* a twin: the original's global accesses and schedule, no on-chip work, one
    add per loaded value */
@@ -1161,6 +1161,21 @@ int orc_ubench_features(int kind, int dtype, int64_t n, int a, int b, int epw, i
             memset(c, 0, sizeof(int64_t) * F_N);
             stencil_walk(T_F32, n, c);
             twin_of(c);
+            return 0;
+        case UB_TILE_READ:
+            /* 16 x 16 work-groups over the n x n array, n/16 trips per thread */
+            if (n % 16 || (a != 0 && a != 1)) return 1;
+            c[F_WG] = (n / 16) * (n / 16);
+            for (int64_t g1 = 0; g1 < n / 16; ++g1)
+                for (int64_t g0 = 0; g0 < n / 16; ++g0)
+                    for (int t = 0; t < 256; ++t) {
+                        for (int64_t k = 0; k < n / 16; ++k) {
+                            c[a ? F_UB_LD_STRIDED : F_UB_LD] += 4;
+                            c[F_VALU_F32] += 1;
+                        }
+                        c[F_UB_ST] += 4;
+                    }
+            c[F_SERIAL] = n / 16;
             return 0;
         case UB_TWIN_MATMUL:
             memset(c, 0, sizeof(int64_t) * F_N);

@@ -14,7 +14,9 @@ a test can confirm the kernel did the work it is timed for:
             to every position it holds;
   lds       every wave's 64 values rotated by `iters` lanes;
   barrier   the barrier count;
-  overlap   every wave's 64 vectors rotated by m lanes (zeros past the end).
+  overlap   every wave's 64 vectors rotated by m lanes (zeros past the end);
+  tile_read out[i][j] = sum over k < n/16 of x[i][16k + j mod 16] (pattern a)
+            or of x[16k + i mod 16][j] (pattern b).
 Inputs of the tests are small integers or dyadic fractions, so FP64 here and
 FP32 on the GPU agree exactly.
 """
@@ -89,3 +91,15 @@ def overlap(x, n4, m):
     pad[:n4] = x
     rot = np.roll(pad.reshape(4 * blocks, 64, 4), -m, axis=1).reshape(-1, 4)
     return rot[:n4].reshape(-1)
+
+
+def tile_read(x, n, pattern):
+    x = np.asarray(x, dtype=np.float64).reshape(n, n)
+    out = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            if pattern == 0:
+                out[i, j] = sum(x[i, 16 * k + j % 16] for k in range(n // 16))
+            else:
+                out[i, j] = sum(x[16 * k + i % 16, j] for k in range(n // 16))
+    return out.reshape(-1)

@@ -56,7 +56,7 @@ class dg_ubench_desc(ctypes.Structure):
 
 
 UBENCH = {"stream": 0, "strided": 1, "fma": 2, "mfma": 3, "lds": 4, "barrier": 5, "overlap": 6,
-          "twin_dg": 7, "twin_stencil": 8, "twin_matmul": 9}
+          "twin_dg": 7, "twin_stencil": 8, "twin_matmul": 9, "tile_read": 10}
 
 _lib = None
 

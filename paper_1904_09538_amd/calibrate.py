@@ -249,7 +249,25 @@ def micro_variants(quick=False):
             out.append({"family": "micro", "kind": "barrier", "n": nwg, "a": 4 * it, "b": 0, "dtype": "f32"})
     for m in (0, 1, 2, 4, 6, 8, 12, 16, 24, 32, 48, 64):
         out.append({"family": "micro", "kind": "overlap", "n": 1 << 22, "a": m, "b": 0, "dtype": "f32"})
+    # the square matmul's two operand-fetch patterns (a: along rows, b: down
+    # rows) over the paper's range of widths
+    for n in ((2048, 2560, 3072, 3584) if not quick else (2048, 3584)):
+        for pat in (0, 1):
+            out.append({"family": "micro", "kind": "tile_read", "n": n, "a": pat, "b": 0, "dtype": "f32"})
     return out
+
+
+def pattern_costs(rows):
+    """Time per load of the tiled read patterns a and b at each width (the
+    paper's comparison, Section "Global Memory Access Pattern Features")."""
+    t = {}
+    for r in rows:
+        if r.get("family") == "micro" and r.get("kind") == "tile_read":
+            n = r["n"]
+            t.setdefault(n, {})[r["a"]] = r["t"]["mean"] / (n * n * (n // 16))
+    out = [{"n": n, "a_ns_per_load": 1e9 * v[0], "b_ns_per_load": 1e9 * v[1], "b_over_a": v[1] / v[0]}
+           for n, v in sorted(t.items()) if 0 in v and 1 in v]
+    return out or None
 
 
 def twin_variants(quick=False):
@@ -459,6 +477,9 @@ def measure_one(v, trials, flush, num_cu, seed=0):
             elif k == "overlap":
                 ins = [torch.rand(4 * n, generator=gen, device=dev)]
                 out = torch.empty(4 * n, device=dev)
+            elif k == "tile_read":
+                ins = [torch.rand(n * n, generator=gen, device=dev)]
+                out = torch.empty(n * n, device=dev)
             tm = time_launch(lambda: _lib.dg_ubench_run(k, n, ins, out, a=a_, b=b_, dtype=v["dtype"]), trials,
                              flush=flush)
             return {**v, "t": tm,
@@ -938,6 +959,7 @@ def fit_all(path, kinds=None, fresh_path=None):
     out["overlap"] = overlap_diagnosis(meta, rows, out["micro"]["dg"])
     if fresh_path:
         out["fresh"] = score_fresh(out, path, fresh_path)
+    out["pattern_ab"] = pattern_costs(rows)
     return out
 
 

@@ -81,6 +81,10 @@ dg_status check_ubench(const dg_ubench_desc* d) {
         case DG_UB_TWIN_DG:
             if (d->a < 1 || d->a > 512 || d->b < 1 || d->b > 8) return fail(DG_EUNSUPPORTED, "DG twin: sizes");
             return DG_OK;
+        case DG_UB_TILE_READ:
+            if (d->n % 16 || d->n > 65536 || (d->a != 0 && d->a != 1))
+                return fail(DG_EINVAL, "tile read: n a multiple of 16 up to 65536, pattern 0 or 1");
+            return DG_OK;
         case DG_UB_TWIN_STENCIL:
             if (d->n % 4 || d->a < d->n + 2 || d->a % 4 || d->b < d->n || d->b % 4)
                 return fail(DG_EUNSUPPORTED, "stencil twin: n and leading dimensions multiples of 4");
@@ -232,7 +236,7 @@ dg_status dg_ubench_run(const dg_ubench_desc* d, const void* const* in, void* ou
     const int nin = d->kind == DG_UB_STREAM ? d->a
                   : (d->kind == DG_UB_TWIN_DG || d->kind == DG_UB_TWIN_MATMUL) ? 2
                   : (d->kind == DG_UB_STRIDED || d->kind == DG_UB_LDS || d->kind == DG_UB_OVERLAP ||
-                     d->kind == DG_UB_TWIN_STENCIL) ? 1 : 0;
+                     d->kind == DG_UB_TWIN_STENCIL || d->kind == DG_UB_TILE_READ) ? 1 : 0;
     if (!out || (nin && !in)) return fail(DG_EINVAL, "dg_ubench_run: NULL array");
     for (int k = 0; k < nin; ++k)
         if (!in[k]) return fail(DG_EINVAL, "dg_ubench_run: NULL input");

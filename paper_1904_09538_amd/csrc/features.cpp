@@ -511,6 +511,15 @@ dg_status count_ubench(const dg_ubench_desc* d, int64_t* c) {
             c[PF_SERIAL_STEPS] = d->a;
             return DG_OK;
         }
+        case DG_UB_TILE_READ: {
+            const int64_t trips = n / 16;
+            c[PF_WORKGROUPS] = trips * trips;
+            c[d->a == 1 ? PF_GLD_UB_STRIDED : PF_GLD_UB] = n * n * trips * 4;
+            c[PF_GST_UB] = n * n * 4;
+            c[PF_VALU_F32] = n * n * trips;
+            c[PF_SERIAL_STEPS] = trips;
+            return DG_OK;
+        }
         case DG_UB_TWIN_DG: {
             perf_kernel_desc f = {};
             f.kernel = DG_K_DGDIFF;

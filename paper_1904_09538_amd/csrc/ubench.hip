@@ -144,6 +144,23 @@ __global__ void __launch_bounds__(256) ub_barrier_kernel(int iters, float* __res
 // to the next lane of its wave through LDS (one 16-byte store and load each),
 // and stores what it holds: vector g receives the input of lane (l + m) % 64
 // of the same wave, or zeros where that vector does not exist.
+// The square matmul's two operand-fetch patterns (the paper's pattern a and
+// b): a 16 x 16 work-group reads, at each of n/16 trips, sixteen 64-byte row
+// pieces -- moving along its rows (a) or down the rows (b) -- and each thread
+// stores the sum of the n/16 values it read.
+template <bool B>
+__global__ void __launch_bounds__(256) ub_tile_read_kernel(const float* __restrict__ x, int n,
+                                                           float* __restrict__ out) {
+    const int l0 = threadIdx.x & 15, l1 = threadIdx.x >> 4;
+    const int g0 = blockIdx.x, g1 = blockIdx.y;
+    float s = 0.0f;
+    for (int k = 0; k < n / 16; ++k) {
+        const int64_t idx = B ? (int64_t)n * (16 * k + l1) + 16 * g0 + l0 : (int64_t)n * (16 * g1 + l1) + 16 * k + l0;
+        s += x[idx];
+    }
+    out[(int64_t)n * (16 * g1 + l1) + 16 * g0 + l0] = s;
+}
+
 __global__ void __launch_bounds__(256) ub_overlap_kernel(const float* __restrict__ in, int64_t n4, int m,
                                                          float* __restrict__ out) {
     __shared__ f32x4 buf[2][256];
@@ -398,6 +415,16 @@ dg_status launch_ubench(const dg_ubench_desc* d, const void* const* in, void* ou
             hipLaunchKernelGGL(ub_overlap_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s,
                                static_cast<const float*>(in[0]), n, d->a, o);
             break;
+        case DG_UB_TILE_READ: {
+            const dim3 grid((unsigned)(n / 16), (unsigned)(n / 16));
+            if (d->a == 1)
+                hipLaunchKernelGGL(ub_tile_read_kernel<true>, grid, dim3(256), 0, s,
+                                   static_cast<const float*>(in[0]), (int)n, o);
+            else
+                hipLaunchKernelGGL(ub_tile_read_kernel<false>, grid, dim3(256), 0, s,
+                                   static_cast<const float*>(in[0]), (int)n, o);
+            break;
+        }
         case DG_UB_TWIN_DG:
             return launch_dg_twin(d->b, n, d->a, &d->tile, static_cast<const float*>(in[0]),
                                   static_cast<const float*>(in[1]), o, s);

@@ -281,8 +281,19 @@ def _ub_cases():
              ("fma", 3, 0, 0), ("fma", 2, 7, 0), ("mfma", 2, 5, 0), ("lds", 3, 0, 1), ("lds", 2, 9, 4),
              ("barrier", 5, 17, 0), ("overlap", 1, 3, 0), ("overlap", 257, 0, 0), ("overlap", 1000, 12, 0),
              ("twin_stencil", 1024, 1088, 1024), ("twin_stencil", 4100, 4160, 4100),
-             ("twin_matmul", 1000, 0, 0), ("twin_matmul", 1024, 0, 0)]
+             ("twin_matmul", 1000, 0, 0), ("twin_matmul", 1024, 0, 0),
+             ("tile_read", 16, 0, 0), ("tile_read", 96, 0, 0), ("tile_read", 96, 1, 0), ("tile_read", 160, 1, 0)]
     return cases
+
+
+def test_tile_read_refusals(orc, L):
+    """n not a multiple of 16, or a pattern other than a (0) or b (1): both
+    sides refuse."""
+    for n, a in ((100, 0), (64, 2)):
+        with pytest.raises(L.DGError):
+            L.perf_ubench_count("tile_read", n, a)
+        with pytest.raises(ValueError):
+            orc.ubench_features("tile_read", n, a)
 
 
 @pytest.mark.parametrize("case", _ub_cases())

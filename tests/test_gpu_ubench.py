@@ -117,3 +117,13 @@ def test_matmul_twin_writes_every_output(ops, n):
     ops.dg_ubench_run("twin_matmul", n, [a, b], c)
     torch.cuda.synchronize()
     assert torch.count_nonzero(c).item() == 0
+
+
+@pytest.mark.parametrize("pattern", [0, 1])
+@pytest.mark.parametrize("n", [16, 64, 96])
+def test_tile_read(ops, n, pattern):
+    x = _ints(n * n, 11, -50, 50)
+    out = torch.full((n * n,), float("nan"), device="cuda")
+    ops.dg_ubench_run("tile_read", n, [x], out, a=pattern)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), U.tile_read(x.cpu().numpy(), n, pattern))

@@ -59,3 +59,17 @@ def test_rotations():
     # vector 299 is lane 43 of wave 4 (256 + 43); lane 44 of that wave is past the end
     np.testing.assert_array_equal(o[299], np.zeros(4))
     np.testing.assert_array_equal(U.overlap(v, n4, 64), v)
+
+
+def test_tile_read_patterns():
+    """Pattern a sums each row's values in column class j mod 16, pattern b
+    each column's values in row class i mod 16 (built here by reshapes)."""
+    rng = np.random.default_rng(3)
+    for n in (16, 48):
+        x = rng.integers(-9, 9, (n, n)).astype(np.float64)
+        a = x.reshape(n, n // 16, 16).sum(axis=1)            # [i][j mod 16]
+        b = x.reshape(n // 16, 16, n).sum(axis=0)            # [i mod 16][j]
+        want_a = np.array([[a[i, j % 16] for j in range(n)] for i in range(n)])
+        want_b = np.array([[b[i % 16, j] for j in range(n)] for i in range(n)])
+        np.testing.assert_array_equal(U.tile_read(x, n, 0), want_a.reshape(-1))
+        np.testing.assert_array_equal(U.tile_read(x, n, 1), want_b.reshape(-1))
