@@ -435,6 +435,28 @@ def row_model(path):
                            "non-negative fit primary, unconstrained fit beside"}
 
 
+def row_variants(path):
+    """The variant-ranking study: the paper's equivalent variants (tiled and
+    untiled matmul; DG untiled, u-staged, D-staged, D-staged on transposed
+    element data; 16 x 16 and 18 x 18 stencils) predicted by a model fitted
+    on measurement kernels only (microbenchmarks, empty launches, the
+    variants' work-removed twins), each variant's model form chosen by the
+    overlap analysis."""
+    import contextlib
+    from paper_1904_09538_amd import variant_study as V
+    with contextlib.redirect_stdout(sys.stderr):      # keep stdout to the one JSON line
+        V.measure(path, trials=20)
+    s = V.fit(path)
+    return {"per_variant": {v: {k: d[k] for k in ("form", "n", "measured_ms", "predicted_ms", "geomean_rel_err",
+                                                    "overlap_index_median")}
+                            for v, d in s["per_variant"].items()},
+            "ranking": {f: {k: r[k] for k in ("groups", "kendall_tau_mean", "top1_rate", "regret_mean",
+                                              "regret_max")} for f, r in s["ranking"].items()},
+            "geomean_all": s["geomean_all"], "n_calibration": s["n_calibration"],
+            "n_variant_rows": s["n_variant_rows"],
+            "protocol": "cold cache, 20 event-timed trials per launch; no variant's time enters the fit"}
+
+
 def model_vector(summary, names, family="dg", form=None):
     """A family's model of a calibration summary as a per-feature cost vector
     (the non-negative fit, whose costs stay positive wherever the batch's
@@ -539,7 +561,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--rows", default="all",
-                    help="comma list of extra rows (orders,lowp,batched,adjoint,companions,model) "
+                    help="comma list of extra rows (orders,lowp,batched,adjoint,companions,model,variants) "
                          "or 'all' or 'none'")
     ap.add_argument("--cpu-baseline", type=int, default=1 << 21,
                     help="elements of the workload the CPU oracle runs on (0: skip the oracle leg)")
@@ -601,7 +623,7 @@ def main():
     torch.cuda.empty_cache()
 
     rows, checks = {}, []
-    want = ["orders", "lowp", "batched", "adjoint", "companions", "model"] if args.rows == "all" else \
+    want = ["orders", "lowp", "batched", "adjoint", "companions", "model", "variants"] if args.rows == "all" else \
         ([] if args.rows == "none" else args.rows.split(","))
     small = max(5, args.steps // 5)
     model_summary = None
@@ -609,6 +631,10 @@ def main():
         os.makedirs(os.path.dirname(os.path.abspath(args.calib_out)), exist_ok=True)
         model_summary, rows["model"] = row_model(args.calib_out)
         log(f"model: held-out MAPE {100 * rows['model']['mape_heldout_all']:.1f}%")
+    if "variants" in want:
+        rows["variant_ranking"] = row_variants(os.path.splitext(args.calib_out)[0] + "_variants.jsonl")
+        log("variants: geo-mean error " + ", ".join(
+            f"{v} {100 * d['geomean_rel_err']:.1f}%" for v, d in rows["variant_ranking"]["per_variant"].items()))
     if "orders" in want:
         rows["dg_fp32_orders_2e21"] = row_dg_orders(L, I, torch, small, checks)
     if "lowp" in want:

@@ -375,6 +375,127 @@ typedef struct {
 dg_status dg_ubench_run(const dg_ubench_desc* d, const void* const* in, void* out, dg_stream_t stream);
 dg_status perf_ubench_count(const dg_ubench_desc* d, int64_t* counts);
 
+/* ------------------------------------------------------------------------
+   Program variants (Sections "Matrix Multiplication", "DG Differentiation"
+   and "Finite Differences"): equivalent formulations of each evaluation
+   computation that the model is asked to rank.  FP32 vector-ALU code with
+   the paper's work-group shapes (16 x 16 work-items; the 18 x 18 stencil
+   324), lid(0) = threadIdx.x % L, lid(1) = threadIdx.x / L, gid(0) =
+   blockIdx.x, gid(1) = blockIdx.y.  All arrays row-major device FP32.
+     kind            n        operation, layout and schedule
+     DG_V_MM_PF      n        c = a b, a = in0, b = in1, c = out, [n][n], n a multiple
+                              of 16: per 16-wide k step a 16 x 16 tile of a and one of b
+                              are staged in LDS, one value per work-item
+     DG_V_MM_NOPF    n        c = a b without staging or k split: each work-item walks
+                              its row of a and column of b in global memory
+     DG_V_DG_NOPF    nelem    res[m][k][i] = sum_j D[m][i][j] u[k][j] (Section "DG
+                              Differentiation"), u = in0 [nelem][nunit], D = in1
+                              [nmat][nunit][nunit], res = out [nmat][nelem][nunit];
+                              work-item (k, i) = (16 gid(0) + lid(0), 16 gid(1) + lid(1)),
+                              operands from global memory, loop order m, j
+     DG_V_DG_PFU     nelem    as DG_V_DG_NOPF; per 16-wide j step the 16 x 16 tile of u
+                              (the work-group's 16 elements) is staged in LDS, the nmat
+                              sums are kept in registers (loop order j, m)
+     DG_V_DG_PFDM    nelem    as DG_V_DG_NOPF; per operator and 16-wide j step the 16 x 16
+                              tile of D[m] (the work-group's 16 rows) is staged in LDS
+                              (loop order m, j)
+     DG_V_DG_PFDMT   nelem    DG_V_DG_PFDM on transposed element data: u [nunit][nelem],
+                              res [nmat][nunit][nelem] (consecutive lid(0), consecutive
+                              addresses)
+     DG_V_FD16       n        res[i][j] = u[i][j+1] + u[i+1][j] - 4 u[i+1][j+1] + u[i+1][j+2]
+                              + u[i+2][j+1] (Section "Finite Differences"), u = in0
+                              [n+2][ld_u], res = out [n][ld_res]: a 16 x 16 work-group
+                              stages a 16 x 16 tile of u (one value each), 14 x 14 of its
+                              work-items compute
+     DG_V_FD18       n        the same with 18 x 18 work-groups (16 x 16 compute)
+   DG variants: nunit a multiple of 16 in 16..512, nmat 1..8.  Loads past the
+   last element (grid point) read the last one; only result stores are
+   guarded.  n == 0 (nelem == 0) is a no-op.
+   work_removed = 1 runs the variant's work-removed twin (Section "Measurement
+   Workload Synthesis by Work Removal Transformation"): the same loops and the
+   global accesses to the arrays in keep (DG_V_KEEP_* bits) only, each load
+   added to one per-work-item sum, with no LDS, barrier or other arithmetic.
+   With DG_V_KEEP_OUT the sum is stored where the variant stores its result;
+   otherwise out is a destination of one float per work-item,
+   out[(gid(1) * gx + gid(0)) * threads + threadIdx.x] (gx, work-groups and
+   threads from dg_variant_shape).  Arrays a twin does not read may be NULL.
+   DG_EINVAL: sizes outside the above, keep on a full variant, DG_V_KEEP_IN1 on
+   a stencil, NULL arrays, or an output overlapping a read input.            */
+typedef enum {
+    DG_V_MM_PF = 0,
+    DG_V_MM_NOPF = 1,
+    DG_V_DG_NOPF = 2,
+    DG_V_DG_PFU = 3,
+    DG_V_DG_PFDM = 4,
+    DG_V_DG_PFDMT = 5,
+    DG_V_FD16 = 6,
+    DG_V_FD18 = 7
+} dg_variant;
+
+#define DG_V_KEEP_IN0 1
+#define DG_V_KEEP_IN1 2
+#define DG_V_KEEP_OUT 4
+
+typedef struct {
+    dg_variant kind;
+    int64_t n;          /* matmul, stencil: n; DG: nelem */
+    int32_t nunit;      /* DG only */
+    int32_t nmat;       /* DG only */
+    int64_t ld_u;       /* stencil only */
+    int64_t ld_res;     /* stencil only */
+    int32_t work_removed;
+    int32_t keep;       /* work-removed twins only */
+} dg_variant_desc;
+
+/* Work-groups (gx * gy) and work-items per work-group of the launch.       */
+dg_status dg_variant_shape(const dg_variant_desc* d, int64_t* workgroups, int32_t* threads);
+dg_status dg_variant_run(const dg_variant_desc* d, const void* in0, const void* in1, void* out,
+                         dg_stream_t stream);
+
+/* Features of the variant study (perf_variant_count), in the paper's
+   granularities: per launch, per work-group (barriers: per work-item x
+   work-groups), per wave for vector-ALU and LDS work (a wave instruction
+   counts 64 lanes, whichever lanes are active), per work-item for global
+   accesses (bytes of the lanes that issue them).  One global-access feature
+   per access pattern of the variants (the paper's tagged patterns); the
+   microbenchmark features keep the names perf_feature_name gives them.     */
+enum {
+    VF_LAUNCH = 0,
+    VF_WORKGROUPS,
+    VF_BARRIER_X_WG,
+    VF_VALU_F32_SG,      /* FP32 flops (fused multiply-add 2, add 1) x 64 per wave instruction */
+    VF_LDS_SG,           /* LDS bytes, 4 x 64 per wave access of one float per lane */
+    VF_GLD_UB,           /* microbenchmarks: 16-byte vector loads, bytes */
+    VF_GST_UB,           /* microbenchmark stores and twin destinations: stride-1 stores, bytes */
+    VF_GLD_UB_STRIDED,   /* microbenchmarks: 4-byte loads, lanes S floats apart, bytes */
+    VF_GLD_MM_PF_A,      /* matmul, tiled: a tile loads */
+    VF_GLD_MM_PF_B,      /*                b tile loads */
+    VF_GLD_MM_NOPF_A,    /* matmul, untiled: row of a */
+    VF_GLD_MM_NOPF_B,    /*                  column of b */
+    VF_GST_MM_C,         /* matmul result stores (both) */
+    VF_GLD_DG_NOPF_U,    /* DG untiled: u[k][j] per work-item */
+    VF_GLD_DG_DM,        /* DG untiled and u-staged: D[m][i][j] per work-item */
+    VF_GLD_DG_UPF_U,     /* DG u-staged: u tile loads */
+    VF_GLD_DG_DMPF_U,    /* DG D-staged: u[k][j] per work-item */
+    VF_GLD_DG_DMPF_DM,   /* DG D-staged (both layouts): D tile loads */
+    VF_GLD_DG_DMPFT_U,   /* DG D-staged, transposed: u[j][k] per work-item */
+    VF_GST_DG_NOPF_RES,  /* DG result stores, one feature per variant */
+    VF_GST_DG_UPF_RES,
+    VF_GST_DG_DMPF_RES,
+    VF_GST_DG_DMPFT_RES,
+    VF_GLD_FD16_U,       /* stencil tile loads and result stores per work-group shape */
+    VF_GST_FD16_RES,
+    VF_GLD_FD18_U,
+    VF_GST_FD18_RES,
+    VF_COUNT
+};
+
+int32_t perf_variant_feature_count(void);            /* VF_COUNT */
+const char* perf_variant_feature_name(int32_t k);    /* "" when out of range */
+/* Exact counts of one launch of d (int64 counts[VF_COUNT], overwritten); a
+   host computation that needs no GPU.                                      */
+dg_status perf_variant_count(const dg_variant_desc* d, int64_t* counts);
+
 /* Flags of the model fits.  DG_FIT_RELATIVE: minimise the relative error
    (the paper's scale_features_by_output, Section "Computing Model
    Parameters").  DG_FIT_NONNEG: keep every cost parameter >= 0 (the paper's

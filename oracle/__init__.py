@@ -68,6 +68,8 @@ def _declare(L):
     L.orc_features.restype = _i32
     L.orc_ubench_features.argtypes = [_i32, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i64p]
     L.orc_ubench_features.restype = _i32
+    L.orc_variant_features.argtypes = [_i32, _i64, _i32, _i32, _i32, _i32, _i64p]
+    L.orc_variant_features.restype = _i32
     L.orc_count_triangle.argtypes = [_i64, _i64]
     L.orc_count_triangle.restype = _i64
 
@@ -229,6 +231,27 @@ def ubench_features(kind, n, a=0, b=0, dtype="f32", tile=None, num_cu=0):
     rc = lib().orc_ubench_features(UBENCH[kind], DTYPES[dtype], int(n), int(a), int(b),
                                    t.get("elems_per_wave", 0), t.get("waves", 0), t.get("groups_per_cu", 0),
                                    t.get("d_panels", 0), t.get("flags", 0), int(num_cu), _ptr(out, _i64p))
+    if rc != 0:
+        raise ValueError("unsupported descriptor")
+    return out
+
+
+VARIANT_FEATURES = ["launch", "workgroups", "barrier_x_wg", "valu_f32_sg", "lds_sg", "gld_ub", "gst_ub",
+                    "gld_ub_strided", "gld_mm_pf_a", "gld_mm_pf_b", "gld_mm_nopf_a", "gld_mm_nopf_b",
+                    "gst_mm_c", "gld_dg_nopf_u", "gld_dg_dm", "gld_dg_upf_u", "gld_dg_dmpf_u",
+                    "gld_dg_dmpf_dm", "gld_dg_dmpft_u", "gst_dg_nopf_res", "gst_dg_upf_res",
+                    "gst_dg_dmpf_res", "gst_dg_dmpft_res", "gld_fd16_u", "gst_fd16_res", "gld_fd18_u",
+                    "gst_fd18_res"]
+VARIANTS = {"mm_pf": 0, "mm_nopf": 1, "dg_nopf": 2, "dg_pfu": 3, "dg_pfdm": 4, "dg_pfdmt": 5,
+            "fd16": 6, "fd18": 7}
+
+
+def variant_features(kind, n, nunit=0, nmat=0, work_removed=False, keep=0):
+    """Brute-force walk of one program-variant launch's counts (int64 array,
+    VARIANT_FEATURES order)."""
+    out = np.zeros(len(VARIANT_FEATURES), dtype=np.int64)
+    rc = lib().orc_variant_features(VARIANTS[kind], int(n), int(nunit), int(nmat), int(bool(work_removed)),
+                                    int(keep), _ptr(out, _i64p))
     if rc != 0:
         raise ValueError("unsupported descriptor")
     return out

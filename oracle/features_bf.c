@@ -1194,3 +1194,193 @@ int64_t orc_count_triangle(int64_t p, int64_t n) {
         for (int64_t j = p; j < i + 1; ++j) ++cnt;
     return cnt;
 }
+
+/* ------------------------------------------------------- program variants */
+
+/* The variant kernels' schedules walked work-group by work-group, work-item
+   by work-item and loop trip by loop trip.  Global accesses add the bytes of
+   the work-item that issues them; vector-ALU and LDS statements add 64 lanes'
+   worth once per wave, taken by the first work-item of the wave that executes
+   the statement; barriers are taken by work-item 0 of each work-group (per
+   work-item, times work-groups).  Slots in the order of the library's
+   variant feature interface. */
+enum { V_MM_PF, V_MM_NOPF, V_DG_NOPF, V_DG_PFU, V_DG_PFDM, V_DG_PFDMT, V_FD16, V_FD18 };
+enum { G_LAUNCH, G_WG, G_BAR, G_VALU, G_LDS, G_UB_LD, G_UB_ST, G_UB_LD_STRIDED, G_MM_PF_A, G_MM_PF_B,
+       G_MM_NOPF_A, G_MM_NOPF_B, G_MM_C, G_DG_NOPF_U, G_DG_DM, G_DG_UPF_U, G_DG_DMPF_U, G_DG_DMPF_DM,
+       G_DG_DMPFT_U, G_DG_NOPF_RES, G_DG_UPF_RES, G_DG_DMPF_RES, G_DG_DMPFT_RES, G_FD16_U, G_FD16_RES,
+       G_FD18_U, G_FD18_RES, G_N };
+
+int orc_variant_features(int kind, int64_t n, int nunit, int nmat, int twin, int keep, int64_t* c) {
+    memset(c, 0, sizeof(int64_t) * G_N);
+    if (n < 0 || (twin != 0 && twin != 1) || keep < 0 || keep > 7 || (!twin && keep)) return 1;
+    const int in0 = twin ? (keep & 1) != 0 : 1, in1 = twin ? (keep & 2) != 0 : 1;
+    const int out = twin ? (keep & 4) != 0 : 1;
+    const int fd = kind == V_FD16 || kind == V_FD18;
+    const int L = kind == V_FD18 ? 18 : 16, B = L - 2, T = L * L;
+    int64_t gx, gy;
+    if (kind == V_MM_PF || kind == V_MM_NOPF) {
+        if (n % 16) return 1;
+        gx = gy = n / 16;
+    } else if (fd) {
+        if (twin && in1) return 1;
+        gx = gy = cdiv(n, B);
+    } else if (kind >= V_DG_NOPF && kind <= V_DG_PFDMT) {
+        if (nunit < 16 || nunit > 512 || nunit % 16 || nmat < 1 || nmat > 8) return 1;
+        gx = cdiv(n, 16);
+        gy = nunit / 16;
+    } else {
+        return 1;
+    }
+    if (gx * gy == 0) return 0;
+    c[G_LAUNCH] = 1;
+    c[G_WG] = gx * gy;
+    const int u_slot = kind == V_DG_NOPF ? G_DG_NOPF_U : kind == V_DG_PFU ? G_DG_UPF_U
+                     : kind == V_DG_PFDM ? G_DG_DMPF_U : G_DG_DMPFT_U;
+    const int res_slot = kind == V_DG_NOPF ? G_DG_NOPF_RES : kind == V_DG_PFU ? G_DG_UPF_RES
+                       : kind == V_DG_PFDM ? G_DG_DMPF_RES : G_DG_DMPFT_RES;
+    for (int64_t b1 = 0; b1 < gy; ++b1)
+        for (int64_t b0 = 0; b0 < gx; ++b0) {
+            /* first computing work-item of each wave (the stencils' inner part) */
+            int first_inner[6] = {-1, -1, -1, -1, -1, -1};
+            for (int t = T - 1; t >= 0; --t)
+                if (t % L < B && t / L < B) first_inner[t / 64] = t;
+            for (int t = 0; t < T; ++t) {
+                const int l0 = t % L, l1 = t / L;
+                const int lead = t % 64 == 0;     /* first work-item of its wave */
+                const int bar = t == 0;
+                switch (kind) {
+                    case V_MM_PF:
+                        for (int64_t ko = 0; ko < n / 16; ++ko) {
+                            if (!twin) {
+                                if (bar) c[G_BAR] += 2;
+                                c[G_MM_PF_A] += 4;
+                                c[G_MM_PF_B] += 4;
+                                if (lead) c[G_LDS] += 2 * 256;
+                                for (int ki = 0; ki < 16; ++ki)
+                                    if (lead) {
+                                        c[G_LDS] += 2 * 256;
+                                        c[G_VALU] += 2 * 64;
+                                    }
+                            } else {
+                                if (in0) { c[G_MM_PF_A] += 4; if (lead) c[G_VALU] += 64; }
+                                if (in1) { c[G_MM_PF_B] += 4; if (lead) c[G_VALU] += 64; }
+                            }
+                        }
+                        if (out) c[G_MM_C] += 4; else c[G_UB_ST] += 4;
+                        break;
+                    case V_MM_NOPF:
+                        for (int64_t k = 0; k < n; ++k) {
+                            if (!twin) {
+                                c[G_MM_NOPF_A] += 4;
+                                c[G_MM_NOPF_B] += 4;
+                                if (lead) c[G_VALU] += 2 * 64;
+                            } else {
+                                if (in0) { c[G_MM_NOPF_A] += 4; if (lead) c[G_VALU] += 64; }
+                                if (in1) { c[G_MM_NOPF_B] += 4; if (lead) c[G_VALU] += 64; }
+                            }
+                        }
+                        if (out) c[G_MM_C] += 4; else c[G_UB_ST] += 4;
+                        break;
+                    case V_DG_NOPF: {
+                        const int valid = 16 * b0 + l0 < n;
+                        for (int m = 0; m < nmat; ++m) {
+                            for (int j = 0; j < nunit; ++j) {
+                                if (!twin) {
+                                    c[G_DG_DM] += 4;
+                                    c[u_slot] += 4;
+                                    if (lead) c[G_VALU] += 2 * 64;
+                                } else {
+                                    if (in1) { c[G_DG_DM] += 4; if (lead) c[G_VALU] += 64; }
+                                    if (in0) { c[u_slot] += 4; if (lead) c[G_VALU] += 64; }
+                                }
+                            }
+                            if (out && valid) c[res_slot] += 4;
+                        }
+                        if (!out) c[G_UB_ST] += 4;
+                        break;
+                    }
+                    case V_DG_PFU: {
+                        const int valid = 16 * b0 + l0 < n;
+                        for (int jo = 0; jo < nunit / 16; ++jo) {
+                            if (!twin) {
+                                if (bar) c[G_BAR] += 2;
+                                c[u_slot] += 4;
+                                if (lead) c[G_LDS] += 256;
+                            } else if (in0) {
+                                c[u_slot] += 4;
+                                if (lead) c[G_VALU] += 64;
+                            }
+                            for (int ji = 0; ji < 16; ++ji) {
+                                if (!twin && lead) c[G_LDS] += 256;
+                                for (int m = 0; m < nmat; ++m) {
+                                    if (!twin) {
+                                        c[G_DG_DM] += 4;
+                                        if (lead) c[G_VALU] += 2 * 64;
+                                    } else if (in1) {
+                                        c[G_DG_DM] += 4;
+                                        if (lead) c[G_VALU] += 64;
+                                    }
+                                }
+                            }
+                        }
+                        if (out && valid) c[res_slot] += 4 * nmat;
+                        if (!out) c[G_UB_ST] += 4;
+                        break;
+                    }
+                    case V_DG_PFDM:
+                    case V_DG_PFDMT: {
+                        const int valid = 16 * b0 + l0 < n;
+                        for (int m = 0; m < nmat; ++m) {
+                            for (int jo = 0; jo < nunit / 16; ++jo) {
+                                if (!twin) {
+                                    if (bar) c[G_BAR] += 2;
+                                    c[G_DG_DMPF_DM] += 4;
+                                    if (lead) c[G_LDS] += 256;
+                                    for (int ji = 0; ji < 16; ++ji) {
+                                        c[u_slot] += 4;
+                                        if (lead) {
+                                            c[G_LDS] += 256;
+                                            c[G_VALU] += 2 * 64;
+                                        }
+                                    }
+                                } else {
+                                    if (in1) { c[G_DG_DMPF_DM] += 4; if (lead) c[G_VALU] += 64; }
+                                    if (in0)
+                                        for (int ji = 0; ji < 16; ++ji) {
+                                            c[u_slot] += 4;
+                                            if (lead) c[G_VALU] += 64;
+                                        }
+                                }
+                            }
+                            if (out && valid) c[res_slot] += 4;
+                        }
+                        if (!out) c[G_UB_ST] += 4;
+                        break;
+                    }
+                    case V_FD16:
+                    case V_FD18: {
+                        const int inner = l0 < B && l1 < B;
+                        const int in_range = inner && B * b1 + l1 < n && B * b0 + l0 < n;
+                        const int u_fd = kind == V_FD18 ? G_FD18_U : G_FD16_U;
+                        const int r_fd = kind == V_FD18 ? G_FD18_RES : G_FD16_RES;
+                        if (!twin) {
+                            c[u_fd] += 4;
+                            if (lead) c[G_LDS] += 256;
+                            if (bar) c[G_BAR] += 1;
+                            if (inner && first_inner[t / 64] == t) {
+                                c[G_LDS] += 5 * 256;
+                                c[G_VALU] += 5 * 64;
+                            }
+                            if (in_range) c[r_fd] += 4;
+                        } else {
+                            if (in0) { c[u_fd] += 4; if (lead) c[G_VALU] += 64; }
+                            if (out) { if (in_range) c[r_fd] += 4; }
+                            else c[G_UB_ST] += 4;
+                        }
+                        break;
+                    }
+                }
+            }
+        }
+    return 0;
+}

@@ -58,6 +58,16 @@ class dg_ubench_desc(ctypes.Structure):
 UBENCH = {"stream": 0, "strided": 1, "fma": 2, "mfma": 3, "lds": 4, "barrier": 5, "overlap": 6,
           "twin_dg": 7, "twin_stencil": 8, "twin_matmul": 9, "tile_read": 10}
 
+class dg_variant_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int64), ("nunit", ctypes.c_int32),
+                ("nmat", ctypes.c_int32), ("ld_u", ctypes.c_int64), ("ld_res", ctypes.c_int64),
+                ("work_removed", ctypes.c_int32), ("keep", ctypes.c_int32)]
+
+
+VARIANTS = {"mm_pf": 0, "mm_nopf": 1, "dg_nopf": 2, "dg_pfu": 3, "dg_pfdm": 4, "dg_pfdmt": 5,
+            "fd16": 6, "fd18": 7}
+DG_V_KEEP_IN0, DG_V_KEEP_IN1, DG_V_KEEP_OUT = 1, 2, 4
+
 _lib = None
 
 
@@ -117,6 +127,16 @@ def _declare(L):
     L.dg_ubench_run.restype = _i32
     L.dg_ubench_run.argtypes = [ctypes.POINTER(dg_ubench_desc), ctypes.POINTER(ctypes.c_void_p), _vp, _vp]
     L.perf_ubench_count.restype = _i32
+    L.dg_variant_shape.restype = _i32
+    L.dg_variant_shape.argtypes = [ctypes.POINTER(dg_variant_desc), ctypes.POINTER(_i64), ctypes.POINTER(_i32)]
+    L.dg_variant_run.restype = _i32
+    L.dg_variant_run.argtypes = [ctypes.POINTER(dg_variant_desc), _vp, _vp, _vp, _vp]
+    L.perf_variant_feature_count.restype = _i32
+    L.perf_variant_feature_count.argtypes = []
+    L.perf_variant_feature_name.restype = ctypes.c_char_p
+    L.perf_variant_feature_name.argtypes = [_i32]
+    L.perf_variant_count.restype = _i32
+    L.perf_variant_count.argtypes = [ctypes.POINTER(dg_variant_desc), ctypes.POINTER(ctypes.c_int64)]
     L.perf_ubench_count.argtypes = [ctypes.POINTER(dg_ubench_desc), ctypes.POINTER(ctypes.c_int64)]
     L.dgdiff_resolve_backward.restype = _i32
     L.dgdiff_resolve_backward.argtypes = [_i32, _i32, _i64, _i32, ctypes.POINTER(dg_tile),
@@ -345,6 +365,44 @@ def perf_ubench_count(kind, n, a=0, b=0, dtype="f32", tile=None, num_cu=0):
     d = _ub_desc(kind, n, a, b, dtype, tile, num_cu)
     out = np.zeros(lib().perf_feature_count(), dtype=np.int64)
     check(lib().perf_ubench_count(ctypes.byref(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return out
+
+
+def _v_desc(kind, n, nunit=0, nmat=0, ld_u=0, ld_res=0, work_removed=False, keep=0):
+    return dg_variant_desc(VARIANTS[kind], int(n), int(nunit), int(nmat), int(ld_u), int(ld_res),
+                           int(bool(work_removed)), int(keep))
+
+
+def variant_feature_names():
+    L = lib()
+    return [L.perf_variant_feature_name(k).decode() for k in range(L.perf_variant_feature_count())]
+
+
+def variant_shape(kind, n, nunit=0, nmat=0, ld_u=0, ld_res=0, work_removed=False, keep=0):
+    """(work-groups, work-items per work-group) of a program-variant launch."""
+    d = _v_desc(kind, n, nunit, nmat, ld_u, ld_res, work_removed, keep)
+    wg, th = _i64(), _i32()
+    check(lib().dg_variant_shape(ctypes.byref(d), ctypes.byref(wg), ctypes.byref(th)))
+    return wg.value, th.value
+
+
+def dg_variant_run(kind, n, in0, in1, out, nunit=0, nmat=0, ld_u=0, ld_res=0, work_removed=False, keep=0,
+                   stream=None):
+    """Launch a program variant (or its work-removed twin) on device tensors;
+    in0 / in1 may be None where the twin does not read them."""
+    d = _v_desc(kind, n, nunit, nmat, ld_u, ld_res, work_removed, keep)
+    p0 = in0.data_ptr() if in0 is not None else None
+    p1 = in1.data_ptr() if in1 is not None else None
+    check(lib().dg_variant_run(ctypes.byref(d), p0, p1, _ptr(out), _stream(stream)))
+    return out
+
+
+def perf_variant_count(kind, n, nunit=0, nmat=0, ld_u=0, ld_res=0, work_removed=False, keep=0):
+    """Counted features of one program-variant launch (variant_feature_names() order)."""
+    import numpy as np
+    d = _v_desc(kind, n, nunit, nmat, ld_u, ld_res, work_removed, keep)
+    out = np.zeros(lib().perf_variant_feature_count(), dtype=np.int64)
+    check(lib().perf_variant_count(ctypes.byref(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
     return out
 
 

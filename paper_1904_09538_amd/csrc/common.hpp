@@ -141,4 +141,12 @@ dg_status check_ubench(const dg_ubench_desc* d);
 dg_status launch_matmul(int64_t n, const void* a, const void* b, void* c, hipStream_t s, bool work = true);
 bool matmul_vector_ok(int64_t n, const void* a, const void* b, const void* c);
 
+// Program variants (variants.hip): grid gx x gy of `threads`-wide work-groups.
+struct VariantShape {
+    int64_t gx, gy;
+    int threads;
+};
+VariantShape variant_shape(const dg_variant_desc* d);
+dg_status check_variant(const dg_variant_desc* d);
+
 }  // namespace dg
