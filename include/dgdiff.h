@@ -287,6 +287,12 @@ enum {
     PF_GLD_UB,           /* measurement kernels: 16-byte vector loads, consecutive lanes, bytes */
     PF_GST_UB,           /* measurement kernels: stores, bytes */
     PF_GLD_UB_STRIDED,   /* measurement kernels: 4-byte loads, lanes S floats apart, bytes */
+    PF_DG_OUT_W32,       /* of the DG contraction's output bytes, those written by 32-element wave */
+    PF_DG_OUT_W64,       /* tiles, and by 64-element ones: a tag of the store pattern (a wider tile
+                            spreads each panel's 64-byte row pieces over more rows), not extra bytes */
+    PF_STAGE_CHAIN,      /* operator-staging kernels: LDS bytes one work-group stages before its first
+                            element tile (the largest over the launch's work-groups), summed over
+                            launches: a latency chain like PF_SERIAL_STEPS, not a volume */
     PF_COUNT
 };
 

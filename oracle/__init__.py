@@ -200,7 +200,8 @@ FEATURES = ["launch", "workgroups", "barrier_x_wg", "gld_dg_u", "gld_dg_u_l2", "
             "gst_dg_out", "gld_st_u", "gst_st_res", "gld_mm_ab", "gst_mm_c", "lds_bytes",
             "mfma_f64", "mfma_f32", "mfma_bf16", "mfma_fp8", "valu_f32", "valu_f64",
             "gld_dg_u_unal", "gst_dg_out_unal", "wave_tiles", "serial_steps", "lat_steps",
-            "gld_ws", "gst_ws", "gld_idx", "gld_ub", "gst_ub", "gld_ub_strided"]
+            "gld_ws", "gst_ws", "gld_idx", "gld_ub", "gst_ub", "gld_ub_strided", "dg_out_w32", "dg_out_w64",
+            "stage_chain"]
 KERNELS = {"dg": 0, "stencil": 1, "matmul": 2, "empty": 3, "bwd_u": 4, "bwd_d": 5, "quant": 6,
            "batched": 7, "batched_pool": 8}
 DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3}

@@ -26,7 +26,8 @@
 /* feature slots, in the order of the library's interface */
 enum { F_LAUNCH, F_WG, F_BAR, F_U, F_U_L2, F_D, F_OUT, F_ST_U, F_ST_RES, F_MM_AB, F_MM_C, F_LDS,
        F_MFMA_F64, F_MFMA_F32, F_MFMA_BF16, F_MFMA_FP8, F_VALU_F32, F_VALU_F64, F_U_UNAL, F_OUT_UNAL,
-       F_WAVE_TILES, F_SERIAL, F_LAT, F_WS_LD, F_WS_ST, F_IDX, F_UB_LD, F_UB_ST, F_UB_LD_STRIDED, F_N };
+       F_WAVE_TILES, F_SERIAL, F_LAT, F_WS_LD, F_WS_ST, F_IDX, F_UB_LD, F_UB_ST, F_UB_LD_STRIDED,
+       F_OUT_W32, F_OUT_W64, F_STAGE, F_N };
 
 enum { K_DG = 0, K_STENCIL = 1, K_MATMUL = 2, K_EMPTY = 3, K_BWD_U = 4, K_BWD_D = 5, K_QUANT = 6,
        K_BATCHED = 7, K_BATCHED_POOL = 8 };
@@ -59,6 +60,9 @@ static int dg_walk(int dtype, int64_t E, int n, int nseg, int M, int epw, int wa
     const int64_t eg = dtype == T_BF16 ? 2 : 1;     /* low-precision element size in HBM */
     const int64_t el = native ? 1 : 2;              /* low-precision element size in LDS */
     const int cb = epw / 16;
+    /* the FP kernel's output stores by wave tiles of 32 or 64 elements carry
+       their own pattern tag as well */
+    const int wide_tag = lowp ? -1 : cb == 2 ? F_OUT_W32 : cb == 4 ? F_OUT_W64 : -1;
     int KQ, KP, V = 0, KS = 0;
     if (lowp) {
         KS = (int)cdiv(n, 32);
@@ -114,7 +118,7 @@ static int dg_walk(int dtype, int64_t E, int n, int nseg, int M, int epw, int wa
 
     c[F_LAUNCH] += 1;
     c[F_WG] += G;
-    int64_t serial = 0;
+    int64_t serial = 0, stage_max = 0;
     for (int64_t b = 0; b < G; ++b) {
         const int64_t xcd = b % 8, kb = b / 8;
         const int pg = (int)(kb % NG);
@@ -123,6 +127,7 @@ static int dg_walk(int dtype, int64_t E, int n, int nseg, int M, int epw, int wa
         const int np = (int)mini(ppg, P - p_lo);
         /* operator staging: one lane-iteration per LDS slot */
         const int KS2 = lowp ? KP : nseg * KP;   /* staged columns per row */
+        int64_t staged = 0;
         for (int64_t idx = 0; idx < (int64_t)np * 16 * KS2; ++idx) {
             const int k = (int)(idx % KS2) % KP;
             const int rr = (int)(idx / KS2);
@@ -130,7 +135,9 @@ static int dg_walk(int dtype, int64_t E, int n, int nseg, int M, int epw, int wa
             const int o = (panel % mblk) * 16 + rr % 16;
             if (o < n && k < n) c[F_D] += lowp ? eg : sz;
             c[F_LDS] += lowp ? el : sz;
+            staged += lowp ? el : sz;
         }
+        if (!lowp && staged > stage_max) stage_max = staged;
         if (lowp) {
             /* threads 0..7 stage the operator scales (1 where none are given):
                FP8 reads the nmat given ones */
@@ -257,6 +264,7 @@ static int dg_walk(int dtype, int64_t E, int n, int nseg, int M, int epw, int wa
                             for (int64_t f = 0; f < nel_w * rows; ++f) {
                                 c[F_LDS] += sz;
                                 c[F_OUT] += sz;
+                                if (wide_tag >= 0) c[wide_tag] += sz;
                                 if (acc) c[F_WS_LD] += sz;   /* the value added to */
                             }
                         }
@@ -273,10 +281,16 @@ static int dg_walk(int dtype, int64_t E, int n, int nseg, int M, int epw, int wa
                                 for (int r = 0; r < 4; ++r)
                                     if (i + r < n) c[F_WS_LD] += osz;   /* the value added to */
                             if (vec_out) {
-                                if (i < n) c[F_OUT] += 4 * osz;
+                                if (i < n) {
+                                    c[F_OUT] += 4 * osz;
+                                    if (wide_tag >= 0) c[wide_tag] += 4 * osz;
+                                }
                             } else {
                                 for (int r = 0; r < 4; ++r)
-                                    if (i + r < n) c[F_OUT_UNAL] += osz;
+                                    if (i + r < n) {
+                                        c[F_OUT_UNAL] += osz;
+                                        if (wide_tag >= 0) c[wide_tag] += osz;
+                                    }
                             }
                         }
                 }
@@ -288,6 +302,7 @@ static int dg_walk(int dtype, int64_t E, int n, int nseg, int M, int epw, int wa
        per SIMD (per_cu work-groups of `waves` waves on 4 SIMDs), x 64 */
     c[F_SERIAL] += serial;
     c[F_LAT] += serial * 64 / ((int64_t)per_cu * waves);
+    c[F_STAGE] += stage_max;   /* the most any one work-group staged before its first tile */
     return 0;
 }
 
@@ -820,20 +835,23 @@ static int batched_walk(int64_t cnt, int n, int M, int epw, int ppg_in, int per_
     if (G % (8 * NG)) return 1;
     const int64_t nstreams = 8 * (G / (8 * NG));
     const int64_t ntiles = cdiv(cnt, 16LL * cb * 4);
-    int64_t serial = 0;
+    int64_t serial = 0, stage_max = 0;
     for (int64_t lb = 0; lb < G; ++lb) {
         const int64_t xcd = lb & 7, kb = lb >> 3;
         const int pg = (int)(kb % NG);
         const int64_t stream = (kb / NG) * 8 + xcd;
         const int p_lo = pg * ppg;
         const int np = (int)mini(ppg, P - p_lo);
+        int64_t staged = 0;
         for (int64_t idx = 0; idx < (int64_t)np * 16 * KP; ++idx) {
             const int j = (int)(idx % KP), rr = (int)(idx / KP);
             const int panel = p_lo + rr / 16;
             const int i = (panel % mblk) * 16 + rr % 16;
             if (i < n && j < n) c[F_D] += 4;
             c[F_LDS] += 4;
+            staged += 4;
         }
+        if (staged > stage_max) stage_max = staged;
         c[F_BAR] += 1;
         int64_t steps = 0;
         for (int64_t tile = stream; tile < ntiles; tile += nstreams) {
@@ -872,6 +890,7 @@ static int batched_walk(int64_t cnt, int n, int M, int epw, int ppg_in, int per_
     }
     c[F_SERIAL] += serial;
     c[F_LAT] += serial * 64 / ((int64_t)(per_cu < 1 ? 1 : per_cu) * 4);
+    c[F_STAGE] += stage_max;
     return 0;
 }
 

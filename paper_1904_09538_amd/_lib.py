@@ -418,7 +418,7 @@ def resolve_backward(dtype, nmat, nelem, nunit):
 
 
 # features that measure a chain of dependent steps rather than an amount of work
-CHAIN_FEATURES = ("serial_steps", "lat_steps")
+CHAIN_FEATURES = ("serial_steps", "lat_steps", "stage_chain")
 
 
 def batched_counts(plan_info, num_cu=0):

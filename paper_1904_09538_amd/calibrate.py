@@ -55,7 +55,8 @@ GROUP = {"launch": 0, "workgroups": 0, "barrier_x_wg": 0, "wave_tiles": 0, "seri
          "gld_st_u": 1, "gst_st_res": 1, "gld_mm_ab": 1, "gst_mm_c": 1,
          "lds_bytes": 2, "mfma_f64": 2, "mfma_f32": 2, "mfma_bf16": 2, "mfma_fp8": 2,
          "valu_f32": 2, "valu_f64": 2, "gld_ws": 1, "gst_ws": 1, "gld_idx": 1, "gld_ub": 1, "gst_ub": 1,
-         "gld_ub_strided": 1}
+         "gld_ub_strided": 1, "dg_out_w32": 1, "dg_out_w64": 1,
+         "stage_chain": 0}
 # the paper's choice: the overlap model for DG and matmul, the linear model for
 # the stencil (little overlap observed there); the batched launch and the
 # adjoint are contractions like DG (overlap), the quantiser a streaming pass
@@ -74,14 +75,16 @@ def group_of(family, feat):
 MODELS = {
     "dg": ["launch", "workgroups", "wave_tiles", "serial_steps", "lat_steps", "gld_dg_u", "gld_dg_u_unal",
            "gld_dg_u_l2",
-           "gld_dg_d", "gst_dg_out", "gst_dg_out_unal", "lds_bytes", "mfma_f32"],
+           "gld_dg_d", "gst_dg_out", "gst_dg_out_unal", "dg_out_w32", "dg_out_w64", "stage_chain", "lds_bytes",
+           "mfma_f32"],
     # serial_steps (rows of one strip): small grids are bound by the strip's
     # chain of loads rather than by bandwidth
     "stencil": ["launch", "workgroups", "serial_steps", "gld_st_u", "gst_st_res", "lds_bytes", "valu_f32"],
     "matmul": ["launch", "workgroups", "serial_steps", "barrier_x_wg", "gld_mm_ab", "gst_mm_c",
                "lds_bytes", "mfma_f32"],
     # one order alone in a batched launch, on the body that runs it
-    "batched": ["launch", "workgroups", "wave_tiles", "serial_steps", "lat_steps", "barrier_x_wg", "gld_idx",
+    "batched": ["launch", "workgroups", "wave_tiles", "serial_steps", "lat_steps", "stage_chain", "barrier_x_wg",
+                "gld_idx",
                 "gld_dg_u_unal", "gld_dg_u_l2", "gld_dg_d", "gst_dg_out_unal", "lds_bytes", "mfma_f32",
                 "valu_f32"],
     # the adjoint's two steps (grad_u on the GEMM or the contraction kernel;

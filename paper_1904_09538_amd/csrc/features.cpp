@@ -65,7 +65,10 @@ dg_status count_contraction(size_t sz, int nseg, int out_slabs, int64_t E, int n
     // unaligned rows read through the wave slab are also written through it:
     // contiguous stores (plus one LDS write and read per output value)
     const bool stage_out = P.use_slab && n % 4 != 0;
-    c[(n % 4 == 0 || stage_out) ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] += E * out_slabs * n * (int64_t)sz;
+    const int64_t out_bytes = E * out_slabs * n * (int64_t)sz;
+    c[(n % 4 == 0 || stage_out) ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] += out_bytes;
+    if (cb == 2) c[PF_DG_OUT_W32] += out_bytes;
+    if (cb == 4) c[PF_DG_OUT_W64] += out_bytes;
     if (acc) c[PF_GLD_WS] += E * out_slabs * n * (int64_t)sz;
     c[PF_WAVE_TILES] += nwt * P.ngroups;
     const int64_t serial = ceil_div(P.ntiles, 8 * P.slots);  // tiles of the busiest stream
@@ -76,6 +79,7 @@ dg_status count_contraction(size_t sz, int nseg, int out_slabs, int64_t E, int n
                        + (P.use_slab ? (int64_t)P.ngroups * 2 * E * n * (int64_t)sz * nseg : 0)
                        + (stage_out ? 2 * E * out_slabs * n * (int64_t)sz : 0);
     c[sz == 8 ? PF_MFMA_F64 : PF_MFMA_F32] += nwt * P.panels_total * kq * (int64_t)cb * 2048 * nseg;
+    c[PF_STAGE_CHAIN] += (int64_t)P.ppg * 16 * nseg * KP * (int64_t)sz;   // the first group's panels
     return DG_OK;
 }
 
@@ -440,6 +444,7 @@ dg_status count_batched(const perf_kernel_desc* d, int64_t* c) {
     const int64_t serial = ceil_div(ntiles, nstreams);
     c[PF_SERIAL_STEPS] += serial;
     c[PF_LAT_STEPS] += serial * 64 / (std::max(1, d->tile.groups_per_cu) * 4);
+    c[PF_STAGE_CHAIN] += ppg * 16 * 4 * kq * 4;
     return DG_OK;
 }
 
@@ -557,7 +562,7 @@ const char* kNames[PF_COUNT] = {
     "gld_st_u", "gst_st_res", "gld_mm_ab", "gst_mm_c", "lds_bytes", "mfma_f64", "mfma_f32",
     "mfma_bf16", "mfma_fp8", "valu_f32", "valu_f64", "gld_dg_u_unal", "gst_dg_out_unal",
     "wave_tiles", "serial_steps", "lat_steps", "gld_ws", "gst_ws", "gld_idx", "gld_ub", "gst_ub",
-    "gld_ub_strided"};
+    "gld_ub_strided", "dg_out_w32", "dg_out_w64", "stage_chain"};
 
 }  // namespace
 }  // namespace dg

@@ -76,7 +76,7 @@ def counted(orc, L, v):
         lib = L.batched_counts(plan, v["num_cu"])
         orc_ = None
         grid = 0
-        chain = [L.feature_names().index(k) for k in ("serial_steps", "lat_steps")]
+        chain = [L.feature_names().index(k) for k in L.CHAIN_FEATURES]
         for q, i in plan.items():
             if i["count"] == 0:
                 continue
