@@ -657,33 +657,38 @@ static int quant_walk(int dtype, int64_t rows, int64_t cols, int per_row, int64_
     int64_t serial = 0;
     if (cols <= 1024) {
         const int NV = cols <= 256 ? 1 : cols <= 512 ? 2 : 4;
-        const int64_t waves = mini(cdiv(rows, 4), fp8 ? 65536 : 262144);
+        /* lanes per row: 64, or for rows of up to 256 values the smallest
+           power of two SW with 4 SW >= cols; a slot is 64 / SW rows */
+        int SW = 64;
+        if (NV == 1)
+            while (SW > 1 && 4 * (SW / 2) >= cols) SW /= 2;
+        const int RPW = 64 / SW;
+        const int64_t nslots = cdiv(rows, RPW);
+        const int64_t waves = mini(cdiv(nslots, 4), fp8 ? 65536 : 262144);
         const int64_t blocks = cdiv(waves, 4), W = blocks * 4;
         const int vec = cols % 4 == 0;
         c[F_LAUNCH] += 1;
         c[F_WG] += blocks;
         for (int64_t w = 0; w < W; ++w) {
             int64_t steps = 0;
-            for (int64_t r0 = w; r0 < rows; r0 += 4 * W) {
+            for (int64_t b0 = w; b0 < nslots; b0 += 4 * W) {
                 ++steps;
-                c[F_WAVE_TILES] += 1;   /* one wave-step: four rows in flight */
+                c[F_WAVE_TILES] += 1;   /* one wave-step: four slots in flight */
                 for (int j = 0; j < 4; ++j) {
-                    const int64_t r = r0 + j * W;
-                    if (r >= rows) continue;
-                    for (int lane = 0; lane < 64; ++lane)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        const int64_t r = (b0 + j * W) * RPW + lane / SW;
+                        const int t = lane % SW;
+                        if (r >= rows) continue;
                         for (int k = 0; k < NV; ++k) {
-                            const int64_t avail = cols - 4 * (lane + 64 * k);
+                            const int64_t avail = cols - 4 * (t + 64 * k);
                             if (avail >= 4) c[vec ? F_U : F_U_UNAL] += 16;
                             else if (avail > 0) c[vec ? F_U : F_U_UNAL] += 4 * avail;
-                        }
-                    for (int lane = 0; lane < 64; ++lane)
-                        for (int k = 0; k < NV; ++k) {
-                            const int64_t avail = cols - 4 * (lane + 64 * k);
                             if (avail <= 0) continue;
                             if (fp8) c[F_VALU_F32] += 4;
                             c[vec ? F_OUT : F_OUT_UNAL] += (avail >= 4 ? 4 : avail) * esz;
                         }
-                    if (per_row) c[F_OUT_UNAL] += 4;
+                        if (per_row && t == 0) c[F_OUT_UNAL] += 4;
+                    }
                 }
             }
             if (steps > serial) serial = steps;

@@ -109,12 +109,14 @@ dg_status launch_dg_backward_noalloc(dg_dtype t, int nmat, int64_t nelem, int nu
 
 // Launch shape of dgdiff_quantize (a pure function of the sizes; shared with
 // the feature counter): kShortRows = rows of at most 1024 values in
-// registers, nv 4-value vectors per lane, four rows per wave and step;
+// registers, nv 4-value vectors per lane, rows of up to 256 values packed
+// 64 / sw to a wave (sw lanes each), four such slots per wave and step;
 // kRows = one wave per longer row; kGlobal = FP8 with one scale for the
 // whole array (init, grid-wide maximum, encode, final: four launches).
 struct QuantPlan {
     enum Kind { kShortRows, kRows, kGlobal } kind;
     int nv;
+    int sw;          // kShortRows: lanes per row (a power of two), 64 / sw rows per wave slot
     int64_t blocks;  // 256-thread work-groups of the main kernel(s)
     int64_t rows, cols;
 };

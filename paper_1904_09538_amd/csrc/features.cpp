@@ -212,10 +212,12 @@ dg_status count_quant(const perf_kernel_desc* d, int64_t* c) {
         c[vec ? PF_GLD_DG_U : PF_GLD_DG_U_UNAL] += rows * cols * 4;
         c[vec ? PF_GST_DG_OUT : PF_GST_DG_OUT_UNAL] += rows * cols * esz;
         if (fp8) c[PF_VALU_F32] += rows * 4 * ceil_div(cols, 4);   // x * s on whole 4-value vectors
-        c[PF_SERIAL_STEPS] += ceil_div(rows, 4 * nwaves);
-        // wave-steps of four rows: wave w takes rows w, w + W, w + 2W, w + 3W,
-        // then w + 4W ...: rows / 4W steps plus one while w < rows % 4W
-        c[PF_WAVE_TILES] += nwaves * (rows / (4 * nwaves)) + std::min<int64_t>(nwaves, rows % (4 * nwaves));
+        // wave-steps of four slots (a slot: 64 / sw consecutive rows): wave w
+        // takes slots w, w + W, w + 2W, w + 3W, then w + 4W ...: slots / 4W
+        // steps plus one while w < slots % 4W
+        const int64_t slots = ceil_div(rows, 64 / P.sw);
+        c[PF_SERIAL_STEPS] += ceil_div(slots, 4 * nwaves);
+        c[PF_WAVE_TILES] += nwaves * (slots / (4 * nwaves)) + std::min<int64_t>(nwaves, slots % (4 * nwaves));
     } else {
         c[PF_GLD_DG_U_UNAL] += rows * cols * 4 * (fp8 ? 2 : 1);  // FP8 reads the row twice
         c[PF_GST_DG_OUT_UNAL] += rows * cols * esz;

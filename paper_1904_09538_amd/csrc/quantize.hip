@@ -116,12 +116,14 @@ __global__ void __launch_bounds__(256) quantize_rows_kernel(int to_fp8, int64_t 
     }
 }
 
-// Rows of at most 256*NV values (every element row of the DG operands): lane
-// l owns values 4(l + 64k) .. +3, k < NV, held in registers between the max
-// pass and the encode pass; loads are 16-byte vectors from any 4-byte
-// boundary and each lane writes its four codes with one store.  A wave takes
-// four rows per step so that the later rows' loads are in flight while the
-// first is reduced and encoded.
+// Rows of at most 256*NV values (every element row of the DG operands), held
+// in registers between the max pass and the encode pass: a row takes SW
+// lanes (SW = 64 for rows over 256 values), lane t of the row owning values
+// 4(t + 64k) .. +3, k < NV, so a wave holds 64 / SW consecutive rows (a
+// "slot"); loads are 16-byte vectors from any 4-byte boundary and each lane
+// writes its four codes with one store.  A wave takes four slots per step so
+// that the later slots' loads are in flight while the first is reduced and
+// encoded.
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 // Four E4M3FN codes: the hardware FP32-to-FP8 conversion (round to nearest
@@ -155,7 +157,17 @@ __device__ inline f4v load4_any(const float* p, int avail) {
     return v;
 }
 
-template <int NV>
+// Maximum over the SW lanes of each row (SW a power of two; lanes of one row
+// are SW consecutive lanes, so every exchange stays inside the row).
+template <int SW>
+__device__ inline float row_max(float v) {
+#pragma unroll
+    for (int off = SW / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// lane: the lane's index within its row (0 .. SW - 1)
+template <int NV, int SW>
 __device__ inline void quantize_short_row(int to_fp8, int64_t r, int64_t cols, const f4v (&v)[NV],
                                           void* __restrict__ q, float* __restrict__ inv_scale, int lane) {
     if (!to_fp8) {
@@ -186,7 +198,7 @@ __device__ inline void quantize_short_row(int to_fp8, int64_t r, int64_t cols, c
             const float a = fabsf(v[k][t]);
             amax = a > amax ? a : amax;  // NaN entries do not take part in the scale
         }
-    amax = wave_max(amax);
+    amax = row_max<SW>(amax);
     const int ks = pow2_scale_exp_448(amax);
     const float sc = exp2_bits(ks);
     uint8_t* qr = static_cast<uint8_t*>(q) + r * cols;
@@ -207,31 +219,39 @@ __device__ inline void quantize_short_row(int to_fp8, int64_t r, int64_t cols, c
     if (lane == 0) inv_scale[r] = exp2_bits(-ks);
 }
 
-template <int NV>
+// Slot b of the array holds rows b * (64 / SW) + (lane / SW); wave w takes
+// slots w, w + W, w + 2W, w + 3W in one step, then w + 4W ... (W waves).
+template <int NV, int SW>
 __global__ void __launch_bounds__(256) quantize_short_rows_kernel(int to_fp8, int64_t rows, int64_t cols,
                                                                  const float* __restrict__ x,
                                                                  void* __restrict__ q,
                                                                  float* __restrict__ inv_scale) {
-    constexpr int RS = 4;  // rows in flight per wave
+    static_assert(NV == 1 || SW == 64, "rows over 256 values take a whole wave");
+    constexpr int RS = 4;            // slots in flight per wave
+    constexpr int RPW = 64 / SW;     // rows per slot
     const int lane = threadIdx.x & 63;
+    const int t = lane & (SW - 1), seg = lane / SW;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t r0 = wave; r0 < rows; r0 += RS * nwaves) {
+    const int64_t nslots = (rows + RPW - 1) / RPW;
+    for (int64_t b0 = wave; b0 < nslots; b0 += RS * nwaves) {
         f4v v[RS][NV];
 #pragma unroll
         for (int j = 0; j < RS; ++j) {
-            const int64_t r = r0 + j * nwaves;
+            const int64_t r = (b0 + j * nwaves) * RPW + seg;
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                const int64_t c = 4 * (lane + 64 * k);
+                const int64_t c = 4 * (t + 64 * k);
                 v[j][k] = r < rows ? load4_any(x + r * cols + c, (int)min<int64_t>(cols - c, 4))
                                    : f4v{0.f, 0.f, 0.f, 0.f};
             }
         }
 #pragma unroll
         for (int j = 0; j < RS; ++j) {
-            const int64_t r = r0 + j * nwaves;
-            if (r < rows) quantize_short_row<NV>(to_fp8, r, cols, v[j], q, inv_scale, lane);
+            const int64_t r = (b0 + j * nwaves) * RPW + seg;
+            // whole rows drop out past the end: the reduction's exchanges stay
+            // inside a row, so the remaining rows' lanes never read them
+            if (r < rows) quantize_short_row<NV, SW>(to_fp8, r, cols, v[j], q, inv_scale, t);
         }
     }
 }
@@ -330,11 +350,18 @@ QuantPlan quant_plan(int fp8, int64_t rows, int64_t cols, int per_row) {
         return P;
     }
     if (cols <= 1024) {
-        // four rows per wave and step; measured at 2^20 rows of 216: BF16 is
-        // fastest with one step per wave, FP8 with four (65536 waves)
+        // four row slots per wave and step; a slot is one row (sw = 64 lanes)
+        // or, for rows of at most 256 values, 64 / sw consecutive rows of sw
+        // lanes each (sw the smallest power of two with 4 sw >= cols);
+        // measured at 2^20 rows of 216: BF16 is fastest with one step per
+        // wave, FP8 with four (65536 waves)
         P.kind = QuantPlan::kShortRows;
         P.nv = cols <= 256 ? 1 : cols <= 512 ? 2 : 4;
-        const int64_t waves = std::min<int64_t>(ceil_div(rows, 4), fp8 ? 65536 : 262144);
+        P.sw = 64;
+        if (P.nv == 1)
+            while (P.sw > 1 && 4 * (P.sw / 2) >= cols) P.sw /= 2;
+        const int64_t slots = ceil_div(rows, 64 / P.sw);
+        const int64_t waves = std::min<int64_t>(ceil_div(slots, 4), fp8 ? 65536 : 262144);
         P.blocks = ceil_div(waves, 4);
     } else {
         P.kind = QuantPlan::kRows;
@@ -369,15 +396,17 @@ dg_status launch_quantize(dg_dtype to, int64_t rows, int64_t cols, int per_row, 
     // per row is written by the row kernels only when per_row is set
     float* inv_rows = per_row ? inv_scale : nullptr;
     if (P.kind == QuantPlan::kShortRows) {
-        if (P.nv == 1)
-            hipLaunchKernelGGL(quantize_short_rows_kernel<1>, dim3((unsigned)P.blocks), dim3(256), 0, s, fp8,
-                               rows, cols, x, q, inv_rows);
-        else if (P.nv == 2)
-            hipLaunchKernelGGL(quantize_short_rows_kernel<2>, dim3((unsigned)P.blocks), dim3(256), 0, s, fp8,
-                               rows, cols, x, q, inv_rows);
-        else
-            hipLaunchKernelGGL(quantize_short_rows_kernel<4>, dim3((unsigned)P.blocks), dim3(256), 0, s, fp8,
-                               rows, cols, x, q, inv_rows);
+        void (*k)(int, int64_t, int64_t, const float*, void*, float*) = nullptr;
+        if (P.nv == 2) k = quantize_short_rows_kernel<2, 64>;
+        else if (P.nv == 4) k = quantize_short_rows_kernel<4, 64>;
+        else if (P.sw == 64) k = quantize_short_rows_kernel<1, 64>;
+        else if (P.sw == 32) k = quantize_short_rows_kernel<1, 32>;
+        else if (P.sw == 16) k = quantize_short_rows_kernel<1, 16>;
+        else if (P.sw == 8) k = quantize_short_rows_kernel<1, 8>;
+        else if (P.sw == 4) k = quantize_short_rows_kernel<1, 4>;
+        else if (P.sw == 2) k = quantize_short_rows_kernel<1, 2>;
+        else k = quantize_short_rows_kernel<1, 1>;
+        hipLaunchKernelGGL(k, dim3((unsigned)P.blocks), dim3(256), 0, s, fp8, rows, cols, x, q, inv_rows);
     } else {
         hipLaunchKernelGGL(quantize_rows_kernel, dim3((unsigned)P.blocks), dim3(256), 0, s, fp8, rows, cols, x,
                            q, inv_rows);

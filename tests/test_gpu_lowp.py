@@ -88,6 +88,28 @@ def test_quantize_one_scale_grid_wide(orc, ops, to, rows, cols, misalign):
 
 
 @pytest.mark.parametrize("to", ["bf16", "e4m3"])
+@pytest.mark.parametrize("cols", [1, 2, 3, 4, 5, 8, 9, 13, 16, 17, 27, 32, 33, 63, 64, 65, 125, 128, 129, 200,
+                                  216, 255, 256, 257])
+@pytest.mark.parametrize("rows", [1, 37, 1001])
+def test_quantize_packed_rows(orc, ops, to, cols, rows):
+    """Rows of up to 256 values share a wave (64 / SW rows of SW lanes): every
+    row width and ragged last slot, codes and scales bit-equal to the oracle;
+    one row scaled far up and one holding specials, so that each row's scale
+    is its own."""
+    rng = np.random.default_rng(1000 * cols + rows)
+    x = rng.uniform(-1, 1, size=(rows, cols)).astype(np.float32)
+    x[rows // 2] *= 300.0
+    sp = _special_rows()
+    if rows > 2:
+        k = min(cols, len(sp))
+        x[1, :k] = sp[:k] if to == "bf16" else np.nan_to_num(sp[:k])
+    q, inv = _q_gpu(ops, x, to, True)
+    qo, invo = orc.quantize(x, to, True)
+    np.testing.assert_array_equal(q, qo)
+    np.testing.assert_array_equal(inv.view(np.uint32), invo.view(np.uint32))
+
+
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
 def test_quantize_random_bit_patterns(orc, ops, to):
     """2^20 random FP32 bit patterns (all exponents, NaN, inf, subnormals)
     in rows of 64: codes and scales bit-equal to the oracle."""
