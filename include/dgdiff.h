@@ -62,9 +62,9 @@ typedef struct {
     int32_t flags;
 } dg_tile;
 
-#define DG_TILE_NT_STORE 1   /* write outputs with non-temporal (streaming) stores (FP32
-                                launches of rows of a multiple of 32 nodes whose operator
-                                panels all fit one work-group stream them without it) */
+#define DG_TILE_NT_STORE 1   /* write outputs with non-temporal (streaming) stores (a
+                                forward whose operator panels all fit one work-group
+                                streams them without it) */
 #define DG_TILE_FP8_NATIVE 2 /* FP8 input: multiply on the native FP8 matrix instruction,
                                 whose internal 32-product sums are coarser than FP32
                                 (default: widen FP8 exactly to BF16 and use the BF16

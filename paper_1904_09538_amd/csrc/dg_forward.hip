@@ -35,7 +35,7 @@ dg_status launch_fwd(int nmat, int64_t nelem, int nunit, const void* D, const vo
     a.nunit = nunit;
     a.transpose = 0;
     return launch<T, 1>(a, nmat, kq, cb, tile, waves, forward_kernel<T>(kq, cb), s,
-                        forward_kernel<T>(kq, cb, true));
+                        forward_kernel<T>(kq, cb, true), nullptr, true);
 }
 
 }  // namespace

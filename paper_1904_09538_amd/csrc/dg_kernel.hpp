@@ -70,6 +70,19 @@ constexpr int kBufferWord3 = 0x00020000;
 // cache policy of streaming output stores (DG_TILE_NT_STORE): non-temporal at
 // system scope (nt sc0 sc1)
 constexpr int kStreamStore = 2 | 1 | 16;
+
+// A buffer view of [base, base + bytes) for streaming stores.  base and bytes
+// are the same in every lane of the wave (callers pass wave-tile values);
+// taking them from the first lane tells the compiler so, which keeps the
+// resource in scalar registers (a per-lane resource would be stored through
+// a loop over its distinct values).
+__device__ inline __amdgpu_buffer_rsrc_t wave_buffer(void* base, int bytes) {
+    const uint64_t b = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    void* ub = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(ub, 0, __builtin_amdgcn_readfirstlane(bytes), kBufferWord3);
+}
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
@@ -225,7 +238,7 @@ __device__ inline void stage_slab(const T* __restrict__ src, int64_t ew0, int ne
 // rows go out as runs of consecutive scalars.  ACC adds to dst.
 template <typename T, bool ACC>
 __device__ inline void write_staged(const T* st, T* __restrict__ dst, int nel, int rows, int r_lo,
-                                    int nunit, int lane) {
+                                    int nunit, int lane, bool nt) {
     typedef typename Mma<T>::vec_t vec_t;
     constexpr int V = Mma<T>::V;
     if (rows == nunit) {
@@ -233,10 +246,21 @@ __device__ inline void write_staged(const T* st, T* __restrict__ dst, int nel, i
         int done = 0;
         if (reinterpret_cast<uintptr_t>(dst) % 16 == 0) {
             const int nv = len / V;
-            for (int q = lane; q < nv; q += 64) {
-                vec_t v = reinterpret_cast<const vec_t*>(st)[q];
-                if constexpr (ACC) v += reinterpret_cast<const vec_t*>(dst)[q];
-                reinterpret_cast<vec_t*>(dst)[q] = v;
+            if (nt) {
+                // streaming stores through a buffer view of the run
+                const __amdgpu_buffer_rsrc_t rs = wave_buffer(dst, nv * 16);
+                for (int q = lane; q < nv; q += 64) {
+                    vec_t v = reinterpret_cast<const vec_t*>(st)[q];
+                    if constexpr (ACC) v += reinterpret_cast<const vec_t*>(dst)[q];
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs, q * 16, 0,
+                                                           kStreamStore);
+                }
+            } else {
+                for (int q = lane; q < nv; q += 64) {
+                    vec_t v = reinterpret_cast<const vec_t*>(st)[q];
+                    if constexpr (ACC) v += reinterpret_cast<const vec_t*>(dst)[q];
+                    reinterpret_cast<vec_t*>(dst)[q] = v;
+                }
             }
             done = nv * V;
         }
@@ -318,8 +342,8 @@ __device__ inline int paired_panels(const float (&b)[CB][KQ], int64_t e0, int p_
                 // this wave-tile's output rows of the slab (rows past the
                 // last element fall outside it and are dropped)
                 const int nel = (int)min<int64_t>(16 * CB, a.nelem - e0);
-                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                    out + ((int64_t)slab_o * a.nelem + e0) * nunit, 0, nel * nunit * 4, kBufferWord3);
+                const __amdgpu_buffer_rsrc_t rs =
+                    wave_buffer(out + ((int64_t)slab_o * a.nelem + e0) * nunit, nel * nunit * 4);
                 const int o1 = ((cb * 16 + (c & 7)) * nunit + i) * 4;
                 if (i < nunit) {
                     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x1), rs, o1, 0,
@@ -642,7 +666,7 @@ __global__ void __launch_bounds__((dg_max_threads<T, KQ, CB, NSEG>())) dg_kernel
                 if (panel + 1 == pl) {
                     wave_lds_sync();
                     write_staged<T, ACC>(slab, out + ((int64_t)slab_o * a.nelem + e0) * nunit, nel_w,
-                                         rows, r_lo, nunit, lane);
+                                         rows, r_lo, nunit, lane, a.nt_store != 0);
                     wave_lds_sync();  // staged values read before the slab is reused
                 }
                 continue;
@@ -660,10 +684,18 @@ __global__ void __launch_bounds__((dg_max_threads<T, KQ, CB, NSEG>())) dg_kernel
                 if (a.vec_out) {
                     if (i < nunit) {
                         if constexpr (V == 4) {
-                            if (a.nt_store)
-                                __builtin_nontemporal_store(acc[cb], reinterpret_cast<f32x4*>(dst));
-                            else
+                            if (a.nt_store) {
+                                // streaming store through a buffer view of the
+                                // wave-tile's rows of this slab
+                                const int nel = (int)min<int64_t>(16 * CB, a.nelem - e0);
+                                const __amdgpu_buffer_rsrc_t rs = wave_buffer(
+                                    out + ((int64_t)slab_o * a.nelem + e0) * nunit, nel * nunit * 4);
+                                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, acc[cb]), rs,
+                                                                       ((cb * 16 + c) * nunit + i) * 4, 0,
+                                                                       kStreamStore);
+                            } else {
                                 *reinterpret_cast<f32x4*>(dst) = acc[cb];
+                            }
                         } else {
                             f64x2 lo = {acc[cb][0], acc[cb][1]};
                             f64x2 hi = {acc[cb][2], acc[cb][3]};
@@ -811,9 +843,12 @@ inline bool pipelined_loads(size_t tsize, int nunit, int kq, int cb, bool vec_ou
 // Launch one contraction with the kernel fn (or fn_pair where the paired
 // stores apply); tile->groups_per_cu == 0 means "occupancy maximum" (queried
 // for the kernel launched).
+// stream_out: the launch writes an output nothing reads back before the
+// launch ends (the forward), so it may stream it (see below)
 template <typename T, int NSEG>
 dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, int waves, kern_fn fn,
-                 hipStream_t s, kern_fn fn_pair = nullptr, int* per_cu_used = nullptr) {
+                 hipStream_t s, kern_fn fn_pair = nullptr, int* per_cu_used = nullptr,
+                 bool stream_out = false) {
     if (!fn) return fail(DG_EUNSUPPORTED, "no DG kernel instance for this shape");
     DeviceInfo dev;
     dg_status st = current_device(&dev);
@@ -857,14 +892,14 @@ dg_status launch(KArgs a, int out_slabs, int kq, int cb, const dg_tile* tile, in
     a.use_slab = P.use_slab;
     a.vec_out = vec_out;
     a.stage_out = a.use_slab && !a.vec_out;
-    // streaming output stores on request, and by default on the paired-store
-    // path when one operator group holds every panel: then no other
-    // work-group re-reads an element tile, the output is never read back,
-    // and keeping it out of the L2 measured faster (FP32 p = 3, 2^21
-    // elements: 0.464 -> 0.444 ms; with many groups re-reading the tile from
-    // the L2, p = 7, it measured slower)
-    const bool paired = fn_pair && fn == fn_pair;
-    a.nt_store = ((tile && (tile->flags & DG_TILE_NT_STORE)) || (paired && P.ngroups == 1)) ? 1 : 0;
+    // streaming output stores on request, and by default for a forward
+    // whose one operator group holds every panel: then no other work-group
+    // re-reads an element tile, the output is never read back, and keeping
+    // it out of the L2 measured faster (FP32 at 2^21 elements: p = 2 0.194 ->
+    // 0.178 ms, p = 3 0.464 -> 0.444 ms; p = 1 at 2^22 0.157 -> 0.125 ms);
+    // with several groups re-reading tiles from the L2 (p = 5, 7) it
+    // measured slower
+    a.nt_store = ((tile && (tile->flags & DG_TILE_NT_STORE)) || (stream_out && P.ngroups == 1)) ? 1 : 0;
     hipLaunchKernelGGL(fn, dim3((unsigned)P.grid), dim3(64 * waves), P.smem, s, a);
     DG_HIP_CHECK(hipGetLastError());
     return DG_OK;

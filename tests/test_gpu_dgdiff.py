@@ -102,6 +102,23 @@ def test_tile_variants(orc, ops, nunit, tile):
     _check(orc, ops, D, u, torch.float32, tile=tile)
 
 
+@pytest.mark.parametrize("nunit", [8, 27, 64, 125, 216, 512])
+@pytest.mark.parametrize("nelem", [1, 777, 4099])
+def test_streaming_stores_bitwise(orc, ops, nunit, nelem):
+    """DG_TILE_NT_STORE changes only the stores' cache policy: every store path
+    (paired, single-panel vectors, rows staged through the wave's slab) gives
+    the same bits with and without it, and matches the oracle."""
+    D = _dev(I.random_dmats(nunit), torch.float32)
+    u = _dev(I.uniform_u(nelem, nunit), torch.float32)
+    t0 = ops.resolve_tile("f32", 3, nelem, nunit, None)
+    t1 = dict(t0, flags=t0["flags"] | 1)
+    a = ops.dgdiff_apply(D, u, tile=t0)
+    b = ops.dgdiff_apply(D, u, tile=t1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    _check(orc, ops, I.random_dmats(nunit), I.uniform_u(nelem, nunit), torch.float32, tile=t1)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 @pytest.mark.parametrize("nunit", [5, 27, 125])
 @pytest.mark.parametrize("tile", [dict(elems_per_wave=16, d_panels=1), dict(elems_per_wave=16, d_panels=3),
