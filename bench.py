@@ -224,6 +224,25 @@ def row_lowp(L, I, torch, steps, checks):
         log(f"dg {name} p=5 2^20: {t * 1e3:.3f} ms ({t32 / t:.2f}x fp32); "
             f"quantise+apply {te * 1e3:.3f} ms ({t32 / te:.2f}x)")
         del qD, qu, isD, isu
+    # BF16 straight from FP32 element data: the staged body rounds u to BF16
+    # as it stages it (DG_TILE_QUANT_U), one launch in place of quantise +
+    # apply, with the same result bits
+    qD, _ = L.dgdiff_quantize(Dg.reshape(3, -1), "bf16")
+    fused = dict(flags=L.DG_TILE_QUANT_U)
+    tf = timed(lambda: L.dgdiff_apply(qD.view(3, n, n), u32, out=o, tile=fused), steps, 2)
+    b, f = dg_bytes_flops(E, n, 4, 4)
+    res["bf16_rounded_in_kernel"] = {
+        "body": "staged, u FP32 rounded to BF16 while staged", "shape": L.resolve_tile("bf16", 3, E, n, fused),
+        "ms": tf * 1e3, "elements_per_s": E / tf, "speedup_vs_fp32": t32 / tf,
+        "speedup_vs_quantize_u_and_apply": res["bf16"]["quantize_u_and_apply_ms"] / (tf * 1e3),
+        "roofline": roofline(b, f, tf, "bf16")}
+    qu, _ = L.dgdiff_quantize(u32, "bf16")
+    checks.append({"at": ("precision_p5_2e20", "bf16_rounded_in_kernel"), "kind": "dg_lowp", "fmt": "bf16",
+                   "D": D64, "u": usel, "qD": _codes_to_host(torch, qD).reshape(3, n, n),
+                   "qu": _codes_to_host(torch, qu, selg), "isD": None, "isu": None,
+                   "got": gather_out(torch, o, sel)})
+    log(f"dg bf16 rounded in kernel p=5 2^20: {tf * 1e3:.3f} ms ({t32 / tf:.2f}x fp32)")
+    del qD, qu
     # the quantiser itself (element data, per-element power-of-two scales)
     tq = timed(lambda: L.dgdiff_quantize(u32, "e4m3"), steps, 2)
     res["quantize_u_fp8"] = {"ms": tq * 1e3, "GB_per_s": (E * n * (4 + 1) + E * 4) / tq / 1e9,

@@ -78,6 +78,14 @@ typedef struct {
                                    rows in registers, element and result tiles
                                    staged in LDS, whole output rows written with
                                    streaming stores whatever DG_TILE_NT_STORE says) */
+#define DG_TILE_QUANT_U 16    /* BF16 input only: u holds FP32 values, rounded to BF16
+                                (to nearest even, as dgdiff_quantize does) while the
+                                staged body copies them into LDS: the result is bit for
+                                bit dgdiff_quantize(u, BF16) followed by dgdiff_apply,
+                                without the separate pass over u.  Needs the staged body
+                                (nunit a multiple of 8, 16-byte aligned arrays, one
+                                column block per tile, no DG_TILE_LP_LDS_PANELS), else
+                                DG_EUNSUPPORTED; D stays BF16 */
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char* dg_last_error(void);

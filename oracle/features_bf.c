@@ -911,9 +911,11 @@ static int batched_walk(int64_t cnt, int n, int M, int epw, int ppg_in, int per_
    write tile k, multiply tile k + 1, copy tile k + 2 (indices past the
    stream's last tile meaning that last tile). */
 static int lp_staged_walk(int dtype, int64_t E, int n, int M, int epw, int waves, int per_cu, int rb,
-                          int num_cu, int64_t* c) {
+                          int num_cu, int fused, int64_t* c) {
     const int fp8 = dtype == T_FP8;
-    const int64_t eg = fp8 ? 1 : 2;
+    const int64_t eg = fp8 ? 1 : 2;          /* operator bytes per value */
+    const int64_t ue = fused ? 4 : eg;       /* element data: FP32 when rounded in the kernel */
+    if (fused && (dtype != T_BF16 || epw != 16)) return 1;
     const int KS = (int)cdiv(n, 32), KQ = 8 * KS;
     if (KS > 16) return 1;
     if (epw != 16 && epw != 32) return 1;
@@ -994,7 +996,7 @@ static int lp_staged_walk(int dtype, int64_t E, int n, int M, int epw, int waves
             const int64_t nel = mini(TE, E - t * TE);
             for (int64_t th = 0; th < T; ++th) {
                 for (int kk = 0; kk < cb; ++kk)
-                    if (th + kk * T < nel * nch_u) c[first ? F_U : F_U_L2] += 8 * eg;
+                    if (th + kk * T < nel * nch_u) c[first ? F_U : F_U_L2] += 8 * ue;
                 if (fp8 && th % TE < nel) c[F_U_UNAL] += 4;
             }
         }
@@ -1042,7 +1044,9 @@ int orc_features(int kernel, int dtype, int64_t n0, int nunit, int nmat, int epw
         case K_DG:
             if (n0 == 0) return 0;
             if ((dtype == T_BF16 || (dtype == T_FP8 && !(flags & 2))) && nunit % 8 == 0 && !(flags & 8))
-                return lp_staged_walk(dtype, n0, nunit, nmat, epw, waves, per_cu, d_panels, num_cu, counts);
+                return lp_staged_walk(dtype, n0, nunit, nmat, epw, waves, per_cu, d_panels, num_cu,
+                                      (flags & 16) != 0, counts);
+            if (flags & 16) return 1;   /* the fused rounding runs in the staged body only */
             return dg_walk(dtype, n0, nunit, 1, nmat, epw, waves, per_cu, d_panels, flags, num_cu, 1, 0,
                            counts);
         case K_STENCIL:

@@ -36,6 +36,7 @@ DG_TILE_NT_STORE = 1
 DG_TILE_FP8_NATIVE = 2
 DG_TILE_BATCH_GEMM = 4
 DG_TILE_LP_LDS_PANELS = 8
+DG_TILE_QUANT_U = 16
 
 (DG_K_DGDIFF, DG_K_STENCIL5, DG_K_MATMUL, DG_K_EMPTY, DG_K_BWD_U, DG_K_BWD_D, DG_K_QUANT,
  DG_K_BATCHED, DG_K_BATCHED_POOL) = range(9)
@@ -202,17 +203,22 @@ def make_tile(tile):
 def dgdiff_apply(D, u, out=None, inv_sD=None, inv_su=None, tile=None, out_dtype=None, stream=None):
     """out[m][e][i] = inv_sD[m] inv_su[e] sum_j D[m][i][j] u[e][j] on the GPU.
 
-    D: [nmat][nunit][nunit], u: [nelem][nunit] (same dtype); returns out
-    [nmat][nelem][nunit] (FP32 for BF16/FP8 inputs)."""
+    D: [nmat][nunit][nunit], u: [nelem][nunit] (same dtype, except that with
+    DG_TILE_QUANT_U in tile's flags D is BF16 and u FP32, rounded to BF16 in
+    the kernel); returns out [nmat][nelem][nunit] (FP32 for BF16/FP8 inputs)."""
     nmat, nunit, nunit2 = D.shape
     nelem = u.shape[0]
     if nunit2 != nunit or u.shape[1:] != (nunit,):
         raise ValueError("shape mismatch")
-    if D.dtype != u.dtype:
+    flags = tile.flags if isinstance(tile, dg_tile) else int((tile or {}).get("flags", 0))
+    if flags & DG_TILE_QUANT_U:
+        if D.dtype != torch.bfloat16 or u.dtype != torch.float32:
+            raise TypeError("DG_TILE_QUANT_U: D BF16, u FP32")
+    elif D.dtype != u.dtype:
         raise TypeError("D and u must share a dtype")
-    in_t = _dtype_code(u.dtype)
+    in_t = _dtype_code(D.dtype)
     if out_dtype is None:
-        out_dtype = u.dtype if u.dtype in (torch.float32, torch.float64) else torch.float32
+        out_dtype = D.dtype if D.dtype in (torch.float32, torch.float64) else torch.float32
     if out is None:
         out = torch.empty((nmat, nelem, nunit), dtype=out_dtype, device=u.device)
     check(lib().dgdiff_apply(in_t, _dtype_code(out.dtype), nmat, nelem, nunit, _ptr(D), _ptr(u),

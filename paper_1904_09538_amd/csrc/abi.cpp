@@ -145,11 +145,13 @@ dg_status dgdiff_apply(dg_dtype in_t, dg_dtype out_t, int32_t nmat, int64_t nele
     if (fp && (inv_sD || inv_su)) return fail(DG_EINVAL, "dgdiff_apply: scales are only for quantised input");
     if (in_t == DG_FP8E4M3 && (!inv_sD || !inv_su))
         return fail(DG_EINVAL, "dgdiff_apply: FP8 input needs both inverse scale arrays");
+    const bool fused = tile && (tile->flags & DG_TILE_QUANT_U);
+    if (fused && in_t != DG_BF16) return fail(DG_EINVAL, "dgdiff_apply: DG_TILE_QUANT_U is for BF16 input");
     if (nelem == 0) return DG_OK;
     if (!D || !u || !out) return fail(DG_EINVAL, "dgdiff_apply: NULL array");
     const size_t es = dtype_size(in_t), os = dtype_size(out_t);
     const size_t nD = (size_t)nmat * nunit * nunit * es;
-    const size_t nu = (size_t)nelem * nunit * es;
+    const size_t nu = (size_t)nelem * nunit * (fused ? 4 : es);   // fused: u is FP32
     const size_t no = (size_t)nmat * nelem * nunit * os;
     if (overlaps(out, no, D, nD) || overlaps(out, no, u, nu) ||
         overlaps(out, no, inv_sD, (size_t)nmat * 4) || overlaps(out, no, inv_su, (size_t)nelem * 4))

@@ -54,6 +54,16 @@ inline size_t dtype_size(dg_dtype t) {
 }
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// FP32 -> BF16 bits, round to nearest even; NaN stays NaN (made quiet),
+// overflow rounds to infinity.  The quantiser and the fused BF16 staging of
+// the low-precision DG body share it, so their codes are the same bits.
+__device__ inline uint16_t round_bf16_bits(uint32_t b) {   // b: an FP32 bit pattern
+    if ((b & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((b >> 16) | 0x40u);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+__device__ inline uint16_t round_bf16(float f) { return round_bf16_bits(__builtin_bit_cast(uint32_t, f)); }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 // ------------------------------------------------------------------ launchers

@@ -100,6 +100,30 @@ struct LP<2> {
     __device__ static inline f32x4 mma(F a, F b, f32x4 c) { return LP<0>::mma(a, b, c); }
 };
 
+// 3  BF16 operator; element data FP32 in HBM, rounded to BF16 as the staged
+//    body copies them into LDS (DG_TILE_QUANT_U): the operator loads follow
+//    format 0.  The eight values of a chunk are kept as their FP32 bit
+//    patterns and rounded on the bits (viewing the loaded words as floats
+//    made this compiler shrink the 16-byte loads to their first word).
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+
+template <>
+struct LP<3> {
+    typedef float G;
+    typedef uint16_t L;
+    typedef u32x8 GF;
+    typedef u32x4 F;
+    __device__ static inline F widen(GF v) {
+        u32x4 r;
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+            r[h] = (uint32_t)round_bf16_bits(v[2 * h]) | ((uint32_t)round_bf16_bits(v[2 * h + 1]) << 16);
+        return r;
+    }
+    __device__ static inline L widen1(G v) { return round_bf16(v); }
+    __device__ static inline f32x4 mma(F a, F b, f32x4 c) { return LP<0>::mma(a, b, c); }
+};
+
 struct LpArgs {
     const void* D;
     const void* u;
@@ -408,8 +432,11 @@ constexpr int ls_max_threads() {
 
 template <int FMT, int KS, int CB, int PW>
 __global__ void __launch_bounds__((ls_max_threads<CB, PW>())) dg_lowp_staged_kernel(LsArgs a) {
-    typedef typename LP<FMT>::G GE;
+    typedef typename LP<FMT>::G GE;     // element data in HBM
     typedef typename LP<FMT>::GF GF;
+    constexpr int DFMT = FMT == 3 ? 0 : FMT;   // the operator's format
+    typedef typename LP<DFMT>::G DE;
+    typedef typename LP<DFMT>::GF DGF;
     typedef u32x4 F;   // BF16 fragment (FP8 widened)
     constexpr int KQ = 8 * KS;
     constexpr int TE = 16 * CB;   // elements per tile
@@ -459,7 +486,7 @@ __global__ void __launch_bounds__((ls_max_threads<CB, PW>())) dg_lowp_staged_ker
     }
     F A[PW][KS];
     {
-        const GE* __restrict__ D = static_cast<const GE*>(a.D);
+        const DE* __restrict__ D = static_cast<const DE*>(a.D);
 #pragma unroll
         for (int b = 0; b < PW; ++b) {
             const int i = r0 + (wave * PW + b) * 16 + c;
@@ -467,10 +494,10 @@ __global__ void __launch_bounds__((ls_max_threads<CB, PW>())) dg_lowp_staged_ker
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
                 const int col = g * KQ + 8 * s;
-                GF v = GF(0u);
+                DGF v = DGF(0u);
                 if (rowok && col < nunit)
-                    v = *reinterpret_cast<const GF*>(D + ((int64_t)m * nunit + i) * nunit + col);
-                A[b][s] = LP<FMT>::widen(v);
+                    v = *reinterpret_cast<const DGF*>(D + ((int64_t)m * nunit + i) * nunit + col);
+                A[b][s] = LP<DFMT>::widen(v);
             }
         }
     }
@@ -515,10 +542,15 @@ __global__ void __launch_bounds__((ls_max_threads<CB, PW>())) dg_lowp_staged_ker
             const_cast<GE*>(u + e0 * nunit), 0, nel * nch_u * CHB, kBufferWord3);
 #pragma unroll
         for (int kk = 0; kk < NI; ++kk) {
-            if constexpr (CHB == 16)
+            if constexpr (CHB == 32) {
+                const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(rs, (tid + kk * T) * CHB, 0, 0);
+                const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(rs, (tid + kk * T) * CHB + 16, 0, 0);
+                pf.v[kk] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+            } else if constexpr (CHB == 16) {
                 pf.v[kk] = __builtin_amdgcn_raw_buffer_load_b128(rs, (tid + kk * T) * CHB, 0, 0);
-            else
+            } else {
                 pf.v[kk] = __builtin_amdgcn_raw_buffer_load_b64(rs, (tid + kk * T) * CHB, 0, 0);
+            }
         }
         // the element scales as a buffer of nel floats (none without scales:
         // every read out of range, 0, replaced by 1 at the commit)
@@ -668,6 +700,7 @@ ls_fn ls_kernel(int fmt, int ks, int cb, int pw) {
         if (cb == 1) return pw == 1 ? pick_ls<2, 1, 1>(ks) : pick_ls<2, 1, 2>(ks);
         return pw == 1 ? pick_ls<2, 2, 1>(ks) : pick_ls<2, 2, 2>(ks);
     }
+    if (fmt == 3 && cb == 1) return pw == 1 ? pick_ls<3, 1, 1>(ks) : pick_ls<3, 1, 2>(ks);
     return nullptr;
 }
 
@@ -675,7 +708,8 @@ ls_fn ls_kernel(int fmt, int ks, int cb, int pw) {
 
 int lp_format(dg_dtype in_t, const dg_tile* tile) {
     const bool native = tile && (tile->flags & DG_TILE_FP8_NATIVE);
-    return (in_t == DG_BF16) ? 0 : native ? 1 : 2;
+    const bool fused = tile && (tile->flags & DG_TILE_QUANT_U);
+    return (in_t == DG_BF16) ? (fused ? 3 : 0) : native ? 1 : 2;
 }
 
 // The staged body's plan (see dg_lowp_staged_kernel).  Defaults: one column
@@ -743,6 +777,14 @@ dg_status make_lp_plan(int fmt, int nmat, int64_t nelem, int nunit, const dg_til
     if (P->ks > 16) return fail(DG_EUNSUPPORTED, "nunit too large");
     P->staged = fmt != 1 && nunit % 8 == 0 && aligned && !(tile && (tile->flags & DG_TILE_LP_LDS_PANELS));
     P->pw = P->rb = P->nrg = P->upitch = 0;
+    if (fmt == 3) {
+        // the fused rounding lives in the staged body only
+        if (!P->staged)
+            return fail(DG_EUNSUPPORTED, "DG_TILE_QUANT_U needs the staged body (nunit % 8 == 0, 16-byte "
+                                         "aligned arrays, no DG_TILE_LP_LDS_PANELS)");
+        if (tile && tile->elems_per_wave && tile->elems_per_wave != 16)
+            return fail(DG_EUNSUPPORTED, "DG_TILE_QUANT_U: one column block per tile (elems_per_wave 16)");
+    }
     if (P->staged) return make_staged_plan(nmat, nelem, nunit, tile, per_cu, num_cu, P);
     // defaults measured at p = 5 (2^20 elements): BF16 one column block, FP8
     // two, both with 8 waves per work-group where the variant allows it

@@ -244,7 +244,8 @@ static dg_status count_dg_lowp_staged(const perf_kernel_desc* d, const LpPlan& P
     const int64_t E = d->n0;
     const int n = d->nunit, M = d->nmat;
     const bool fp8 = d->dtype == DG_FP8E4M3;
-    const int64_t eg = fp8 ? 1 : 2;
+    const int64_t eg = fp8 ? 1 : 2;             // operator bytes per value
+    const int64_t ue = P.fmt == 3 ? 4 : eg;     // element-data bytes per value (FP32 when fused)
     const int64_t TE = 16 * P.cb, T = 64 * P.waves, ns = 8 * P.slots;
     const int64_t streams = std::min<int64_t>(ns, P.ntiles);   // streams with tiles
     const int64_t wgs = streams * P.ngroups;                    // work-groups with tiles
@@ -255,8 +256,8 @@ static dg_status count_dg_lowp_staged(const perf_kernel_desc* d, const LpPlan& P
     c[PF_BARRIER_X_WG] = P.ngroups * P.ntiles + wgs;
     c[PF_WAVE_TILES] = P.ngroups * P.ntiles;
     c[PF_GLD_DG_D] = streams * M * (int64_t)n * n * eg + (fp8 ? wgs * P.waves * 4 : 0);
-    c[PF_GLD_DG_U] = E * n * eg;
-    c[PF_GLD_DG_U_L2] = ((int64_t)(P.ngroups - 1) * E + 2 * (int64_t)P.ngroups * last_el) * n * eg;
+    c[PF_GLD_DG_U] = E * n * ue;
+    c[PF_GLD_DG_U_L2] = ((int64_t)(P.ngroups - 1) * E + 2 * (int64_t)P.ngroups * last_el) * n * ue;
     if (fp8) c[PF_GLD_DG_U_UNAL] = 4 * (T / TE) * (P.ngroups * E + 2 * (int64_t)P.ngroups * last_el);
     c[PF_GST_DG_OUT] = E * M * (int64_t)n * 4;
     // per row group: its rows, its valid 16-row blocks, the waves holding one
@@ -282,6 +283,8 @@ static dg_status count_dg_lowp_staged(const perf_kernel_desc* d, const LpPlan& P
 }
 
 dg_status count_dg_lowp(const perf_kernel_desc* d, int64_t* c) {
+    if ((d->tile.flags & DG_TILE_QUANT_U) && d->dtype != DG_BF16)
+        return fail(DG_EINVAL, "DG_TILE_QUANT_U is for BF16 input");
     const int fmt = lp_format(d->dtype, &d->tile);
     LpPlan P;
     dg_status st = make_lp_plan(fmt, d->nmat, d->n0, d->nunit, &d->tile, d->tile.groups_per_cu,

@@ -24,12 +24,7 @@ namespace {
 
 __device__ inline uint32_t f32_bits(float f) { return __builtin_bit_cast(uint32_t, f); }
 
-__device__ inline uint16_t bf16_rne(float f) {
-    uint32_t b = f32_bits(f);
-    if ((b & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((b >> 16) | 0x40u);  // quiet NaN
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
-}
+__device__ inline uint16_t bf16_rne(float f) { return round_bf16(f); }
 
 // E4M3FN encode of an FP32 value by its bit fields.
 __device__ inline uint8_t e4m3_rne(float f) {

@@ -67,3 +67,15 @@ def test_validation_before_launch(L):
     # out overlapping u
     assert _apply(L, u=0x10000, out=0x10000 + 64) == B.DG_EINVAL
     assert b"overlap" in L.dg_last_error()
+
+
+def test_fused_rounding_flag_validation(L):
+    """DG_TILE_QUANT_U is refused for input other than BF16, before any launch."""
+    from paper_1904_09538_amd import _lib as B
+    t = B.dg_tile(0, 0, 0, 0, 16)
+    vp = ctypes.c_void_p
+    st = L.dgdiff_apply(B.DG_FP8E4M3, B.DG_F32, 3, 10, 64, vp(1), vp(2), vp(3), vp(4), vp(5),
+                        ctypes.byref(t), None)
+    assert st == B.DG_EINVAL
+    st = L.dgdiff_apply(B.DG_F32, B.DG_F32, 3, 10, 64, vp(1), vp(2), vp(3), None, None, ctypes.byref(t), None)
+    assert st == B.DG_EINVAL

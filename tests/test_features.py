@@ -59,6 +59,15 @@ def _dg_cases():
                 (256, 8, 200, 8, 16, 2, 8), (216, 3, 300, 4, 16, 2, 8), (216, 3, 300, 2, 16, 2, 4),
                 (512, 3, 100, 8, 16, 1, 16), (64, 3, 100, 3, 16, 2, 7), (40, 2, 300, 1, 16, 3, 2)):
             cases.append((dtype, nunit, nmat, E, waves, epw, per_cu, rb, 0))
+    # BF16 with the element data rounded in the kernel (FP32 u, 4 bytes a
+    # value): staged shapes, and its refusals (two column blocks, the LDS-panel
+    # body, rows off a multiple of 8, FP8 input)
+    for nunit, nmat, E, waves, epw, per_cu, rb, flags in (
+            (8, 3, 4097, 1, 16, 2, 1, 16), (64, 3, 1001, 2, 16, 2, 4, 16), (216, 3, 5001, 7, 16, 2, 14, 16),
+            (216, 3, 1 << 16, 7, 16, 2, 14, 16), (512, 3, 700, 16, 16, 1, 16, 16), (216, 3, 300, 12, 16, 2, 12, 16),
+            (216, 3, 300, 7, 32, 2, 14, 16), (216, 3, 300, 7, 16, 2, 14, 24), (27, 3, 300, 4, 16, 2, 2, 16)):
+        cases.append(("bf16", nunit, nmat, E, waves, epw, per_cu, rb, flags))
+    cases.append(("fp8", 216, 3, 300, 7, 16, 2, 14, 16))
     return cases
 
 

@@ -323,6 +323,70 @@ def test_lowp_staged_refusals(ops):
             ops.resolve_tile("bf16", 3, 1000, nunit, tile)
 
 
+_QU = 16   # DG_TILE_QUANT_U
+
+
+@pytest.mark.parametrize("nunit", [8, 40, 64, 216, 256, 512])
+@pytest.mark.parametrize("nelem", [1, 17, 4099])
+def test_fused_bf16_rounding_is_quantise_then_apply(orc, ops, nunit, nelem):
+    """FP32 element data rounded to BF16 inside the staged body: bit for bit
+    the two-step path (dgdiff_quantize to BF16, then dgdiff_apply), specials
+    included, and within the kernel bound of the oracle on the rounded data."""
+    rng = np.random.default_rng(nunit * 7 + nelem)
+    D32 = (rng.standard_normal((3, nunit, nunit)) / np.sqrt(nunit)).astype(np.float32)
+    u32 = rng.uniform(-1, 1, (nelem, nunit)).astype(np.float32)
+    u32[0, :min(nunit, 6)] = np.array([np.nan, np.inf, -np.inf, 3.0e38, 1e-40, -0.0], np.float32)[:min(nunit, 6)]
+    if nelem > 2:
+        u32[2] *= 1e5
+    qD, _ = ops.dgdiff_quantize(torch.from_numpy(D32.reshape(3, -1)).cuda(), "bf16", per_row=True)
+    qD = qD.view(3, nunit, nunit)
+    ug = torch.from_numpy(u32).cuda()
+    qu, _ = ops.dgdiff_quantize(ug, "bf16", per_row=True)
+    two = ops.dgdiff_apply(qD, qu)
+    one = ops.dgdiff_apply(qD, ug, tile=dict(flags=_QU))
+    torch.cuda.synchronize()
+    assert torch.equal(one.view(torch.int32), two.view(torch.int32))
+    # the oracle on the rounded data (rows free of specials: all but 0 and 2)
+    rows = np.array([r for r in range(nelem) if r not in (0, 2)], dtype=np.int64)
+    if rows.size:
+        quo, _ = orc.quantize(u32[rows], "bf16", True)
+        qDo, _ = orc.quantize(D32.reshape(3, -1), "bf16", True)
+        Dd = orc.bf16_decode_array(qDo).astype(np.float64).reshape(3, nunit, nunit)
+        ud = orc.bf16_decode_array(quo).astype(np.float64)
+        got = one.double().cpu().numpy()[:, rows, :]
+        assert _dot_scaled(orc, got, orc.dg_forward(Dd, ud), Dd, ud) <= nunit * 2.0 ** -23
+
+
+def test_fused_bf16_refusals(ops):
+    """The fused rounding runs in the staged body only."""
+    qD = torch.zeros(3, 27, 27, dtype=torch.bfloat16, device="cuda:0")
+    u = torch.zeros(10, 27, device="cuda:0")
+    with pytest.raises(ops.DGError):                      # rows off a multiple of 8
+        ops.dgdiff_apply(qD, u, tile=dict(flags=_QU))
+    qD = torch.zeros(3, 64, 64, dtype=torch.bfloat16, device="cuda:0")
+    u = torch.zeros(10, 64, device="cuda:0")
+    for tile in (dict(flags=_QU | 8), dict(flags=_QU, elems_per_wave=32)):
+        with pytest.raises(ops.DGError):
+            ops.dgdiff_apply(qD, u, tile=tile)
+    with pytest.raises(TypeError):                        # u must be FP32
+        ops.dgdiff_apply(qD, u.bfloat16(), tile=dict(flags=_QU))
+
+
+def test_fused_bf16_full_size(ops):
+    """p = 5, 2^20 elements (the low-precision workload): fused equals two-step."""
+    from paper_1904_09538_amd import inputs as I
+    n, E = 216, 1 << 20
+    D = torch.from_numpy(I.gll_dmats(5).astype(np.float32)).cuda()
+    u = torch.from_numpy(I.uniform_u(E, n).astype(np.float32)).cuda()
+    qD, _ = ops.dgdiff_quantize(D.reshape(3, -1), "bf16", per_row=True)
+    qD = qD.view(3, n, n)
+    qu, _ = ops.dgdiff_quantize(u, "bf16", per_row=True)
+    two = ops.dgdiff_apply(qD, qu)
+    one = ops.dgdiff_apply(qD, u, tile=dict(flags=_QU))
+    torch.cuda.synchronize()
+    assert torch.equal(one, two)
+
+
 def test_fp8_requires_scales(ops):
     q = torch.zeros(3, 64, 64, dtype=torch.float8_e4m3fn, device="cuda:0")
     u = torch.zeros(10, 64, dtype=torch.float8_e4m3fn, device="cuda:0")
