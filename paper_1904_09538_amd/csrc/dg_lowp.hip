@@ -103,8 +103,10 @@ struct LP<2> {
 // 3  BF16 operator; element data FP32 in HBM, rounded to BF16 as the staged
 //    body copies them into LDS (DG_TILE_QUANT_U): the operator loads follow
 //    format 0.  The eight values of a chunk are kept as their FP32 bit
-//    patterns and rounded on the bits (viewing the loaded words as floats
-//    made this compiler shrink the 16-byte loads to their first word).
+//    patterns and rounded on the bits.  (A __builtin_bit_cast applied to a
+//    vector component, bit_cast(float, v[i]), read component 0 whatever i
+//    with this compiler, in the assembly; values leave a vector by value,
+//    through a function parameter or an element copy, before any bit cast.)
 typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
 
 template <>
