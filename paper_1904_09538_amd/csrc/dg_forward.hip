@@ -66,6 +66,15 @@ dg_status resolve_forward_fp(dg_dtype t, int nmat, int64_t nelem, int nunit, dg_
                    nunit % (int)(16 / ts) == 0, &P);
     if (st != DG_OK) return st;
     tile->d_panels = P.ppg;
+    {
+        // the launch's own check: the work-group must fit the kernel's bound
+        kern_fn f0 = t == DG_F64 ? forward_kernel<double>(kq, cb) : forward_kernel<float>(kq, cb);
+        if (!f0) return fail(DG_EUNSUPPORTED, "no DG kernel instance");
+        hipFuncAttributes fa;
+        DG_HIP_CHECK(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(f0)));
+        if (64 * tile->waves > fa.maxThreadsPerBlock)
+            return fail(DG_EINVAL, "tile.waves above 4 needs a shape whose element data fit 64 registers");
+    }
     if (tile->groups_per_cu == 0) {
         // the kernel a launch into 16-byte aligned output would take
         const bool pair = pair_eligible(ts, nunit, nunit % 4 == 0, P);

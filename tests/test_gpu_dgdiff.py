@@ -102,6 +102,18 @@ def test_tile_variants(orc, ops, nunit, tile):
     _check(orc, ops, D, u, torch.float32, tile=tile)
 
 
+@pytest.mark.parametrize("nunit,tile", [(216, dict(elems_per_wave=32, waves=8)),
+                                        (216, dict(elems_per_wave=32, waves=8, d_panels=6, groups_per_cu=1))])
+def test_resolve_refuses_what_launch_refuses(ops, nunit, tile):
+    """A shape whose work-group exceeds the kernel's bound is refused by the
+    resolver as by the launch (same message), not resolved then refused."""
+    with pytest.raises(ops.DGError, match="fit 64 registers"):
+        ops.resolve_tile("f32", 3, 1000, nunit, tile)
+    with pytest.raises(ops.DGError, match="fit 64 registers"):
+        ops.dgdiff_apply(_dev(I.random_dmats(nunit), torch.float32),
+                         _dev(I.uniform_u(1000, nunit), torch.float32), tile=tile)
+
+
 @pytest.mark.parametrize("nunit", [8, 27, 64, 125, 216, 512])
 @pytest.mark.parametrize("nelem", [1, 777, 4099])
 def test_streaming_stores_bitwise(orc, ops, nunit, nelem):
