@@ -186,13 +186,16 @@ def test_bwd_u_counts_match_brute_force(orc, L, case):
         np.testing.assert_array_equal(got, ref)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("n,M", [(1, 1), (8, 3), (27, 3), (64, 2), (125, 3), (129, 1), (216, 3), (512, 1)])
-@pytest.mark.parametrize("E", [0, 1, 16, 255, 256, 4097, 70001])
-@pytest.mark.parametrize("per_cu", [1, 2, 4])
+# shapes whose brute-force walk stays within the CPU suite's time (n^2 M E
+# <= 2e9; the larger ones are covered by the same code paths at smaller E)
+_BWD_D_CASES = [(dtype, n, M, E, per_cu) for dtype in ("f32", "f64")
+                for n, M in ((1, 1), (8, 3), (27, 3), (64, 2), (125, 3), (129, 1), (216, 3), (512, 1))
+                for E in (0, 1, 16, 255, 256, 4097, 70001) for per_cu in (1, 2, 4)
+                if n * n * M * E <= 2e9]
+
+
+@pytest.mark.parametrize("dtype,n,M,E,per_cu", _BWD_D_CASES)
 def test_bwd_d_counts_match_brute_force(orc, L, dtype, n, M, E, per_cu):
-    if n * n * M * E > 2e9:
-        pytest.skip("walk too long for the CPU suite (covered by smaller shapes)")
     got, ref = _both(orc, L, "bwd_d", dtype, E, n, M, dict(groups_per_cu=per_cu))
     np.testing.assert_array_equal(got, ref)
 
