@@ -66,6 +66,14 @@ VARIANTS = [
     ("dg_bf16_p5_100003_split", "dg", {"dtype": "bf16", "p": 5, "E": 100003,
                                        "tile": {"waves": 9, "d_panels": 9}}),
     ("dg_fp8native_p5_2e20", "dg", {"dtype": "fp8", "p": 5, "E": 1 << 20, "tile": {"flags": 2}}),
+    # the staged body with fewer operators (fewer groups re-reading each
+    # element tile from L2), and with grids of several rounds of work-groups
+    ("dg_bf16_p5_2e20_nmat1", "dg", {"dtype": "bf16", "p": 5, "E": 1 << 20, "nmat": 1}),
+    ("dg_bf16_p5_2e20_nmat2", "dg", {"dtype": "bf16", "p": 5, "E": 1 << 20, "nmat": 2}),
+    ("dg_fp8_p5_2e20_nmat1", "dg", {"dtype": "fp8", "p": 5, "E": 1 << 20, "nmat": 1}),
+    ("dg_fp8_p5_2e20_nmat2", "dg", {"dtype": "fp8", "p": 5, "E": 1 << 20, "nmat": 2}),
+    ("dg_bf16_p5_2e20_grid8", "dg", {"dtype": "bf16", "p": 5, "E": 1 << 20, "tile": {"groups_per_cu": 8}}),
+    ("dg_bf16_p5_2e20_grid24", "dg", {"dtype": "bf16", "p": 5, "E": 1 << 20, "tile": {"groups_per_cu": 24}}),
     ("quant_fp8_rows_2e20x216", "quant", {"to": "fp8", "rows": 1 << 20, "cols": 216}),
     ("quant_bf16_2e20x216", "quant", {"to": "bf16", "rows": 1 << 20, "cols": 216}),
     ("batched_p1_7_2e20", "batched", {"E": 1 << 20}),
@@ -125,10 +133,15 @@ def run(out_path):
             keep = (src, dst)
         elif kind == "dg":
             D, u, n, extra = _dg_inputs(torch, I, prm["dtype"], prm["p"], prm["E"], dev, L)
-            tile = L.resolve_tile(prm["dtype"], 3, prm["E"], n, prm.get("tile"))
+            M = prm.get("nmat", 3)
+            if M < 3:
+                D = D[:M].contiguous()
+                if extra:
+                    extra = {"inv_sD": extra["inv_sD"][:M].contiguous(), "inv_su": extra["inv_su"]}
+            tile = L.resolve_tile(prm["dtype"], M, prm["E"], n, prm.get("tile"))
             rec["tile"] = tile
             rec["nunit"] = n
-            out = torch.empty((3, prm["E"], n), device=dev,
+            out = torch.empty((M, prm["E"], n), device=dev,
                               dtype=torch.float64 if prm["dtype"] == "f64" else torch.float32)
             fn = lambda: L.dgdiff_apply(D, u, out=out, tile=tile, **extra)  # noqa: E731
             keep = (D, u, out, extra)
@@ -257,7 +270,8 @@ def counted(rec, L):
     None where there is no count (the copy probe)."""
     k, p = rec["kind"], rec["params"]
     if k == "dg":
-        return L.perf_features_count("dg", p["dtype"], p["E"], rec["nunit"], 3, rec["tile"], rec["num_cu"])
+        return L.perf_features_count("dg", p["dtype"], p["E"], rec["nunit"], p.get("nmat", 3), rec["tile"],
+                                     rec["num_cu"])
     if k == "stencil":
         return L.perf_features_count("stencil", "f32", p["n"])
     if k == "matmul":
