@@ -364,7 +364,9 @@ def _write_md(out, md_out, command):
              "x 1 KiB and FETCH_SIZE x 2 KiB, the factors at which the counters read a plain 1 GiB",
              "device copy (row copy_1GiB: FETCH 0.5 GiB, WRITE 1 GiB).  Counted loads exclude the",
              "tags for element tiles re-read by later operator groups (`*_l2`), which the schedule",
-             "expects from the XCD's L2.", "",
+             "expects from the XCD's L2.  They do include every lane's read of what the caches serve:",
+             "the FP8 element scale each lane of an element reads (same 4 bytes), and the operator",
+             "rows each work-group loads (far above the fetch on grids of many rounds).", "",
              "| variant | kernels | waves: counter / launched | MFMA flops: counter / counted | "
              "LDS bytes: counter / counted | HBM written: counter / counted stores | "
              "HBM read: counter / counted loads |", "|---|---|---|---|---|---|---|"]
