@@ -102,6 +102,20 @@ def test_tile_variants(orc, ops, nunit, tile):
     _check(orc, ops, D, u, torch.float32, tile=tile)
 
 
+@pytest.mark.parametrize("nunit", [27, 64, 216])
+def test_grids_of_several_rounds_bitwise(orc, ops, nunit):
+    """groups_per_cu above the occupancy gives a grid of several rounds of
+    work-groups (each with fewer tiles): every element still gets the same
+    schedule per tile, so the result equals the resident grid's bit for bit,
+    and the oracle's."""
+    D = I.random_dmats(nunit).astype(np.float32)
+    u = I.uniform_u(50021, nunit).astype(np.float32)
+    base = _run(ops, D, u, torch.float32)
+    for g in (8, 24):
+        assert np.array_equal(_run(ops, D, u, torch.float32, dict(groups_per_cu=g)), base), g
+    _check(orc, ops, D.astype(np.float64), u.astype(np.float64), torch.float32, tile=dict(groups_per_cu=24))
+
+
 @pytest.mark.parametrize("nunit,tile", [(216, dict(elems_per_wave=32, waves=8)),
                                         (216, dict(elems_per_wave=32, waves=8, d_panels=6, groups_per_cu=1))])
 def test_resolve_refuses_what_launch_refuses(ops, nunit, tile):

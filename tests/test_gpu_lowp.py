@@ -387,6 +387,22 @@ def test_fused_bf16_full_size(ops):
     assert torch.equal(one, two)
 
 
+@pytest.mark.parametrize("to", ["bf16", "e4m3"])
+@pytest.mark.parametrize("nunit", [64, 216])
+def test_lowp_grids_of_several_rounds_bitwise(ops, to, nunit):
+    """groups_per_cu above the occupancy (several rounds of work-groups on
+    the staged body) equals the resident grid bit for bit."""
+    p = round(nunit ** (1 / 3)) - 1
+    D32 = I.gll_dmats(p).astype(np.float32)
+    u32 = I.uniform_u(50021, nunit).astype(np.float32)
+    qD, qu, sc = _quantised(ops, D32, u32, to)
+    base = ops.dgdiff_apply(qD, qu, **sc)
+    for g in (8, 24):
+        got = ops.dgdiff_apply(qD, qu, tile=dict(groups_per_cu=g), **sc)
+        torch.cuda.synchronize()
+        assert torch.equal(got, base), g
+
+
 def test_fp8_requires_scales(ops):
     q = torch.zeros(3, 64, 64, dtype=torch.float8_e4m3fn, device="cuda:0")
     u = torch.zeros(10, 64, dtype=torch.float8_e4m3fn, device="cuda:0")
