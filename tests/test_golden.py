@@ -1,0 +1,55 @@
+"""Golden values the paper prints for its matrix-multiplication example
+(tests/golden/matmul_prefetch_counts.txt, citations in the file): the
+prefetching 16 x 16 variant performs 2 n^3 local loads and 2 n^3 / 16 local
+stores that the non-prefetching variant does not, 16 times fewer global loads
+(2 n^3 / 16 against 2 n^3), and n^3 multiply-adds.  Checked against the
+oracle's brute-force walk of the variants' schedules and the library's closed
+form (which must equal the walk).  Counts there are bytes of the lanes that
+issue them (4 per value), a multiply-add being 2 flops; the tiled variant's
+LDS feature holds its loads and stores together."""
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "matmul_prefetch_counts.txt")
+
+
+def _golden():
+    out = {}
+    with open(GOLDEN) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, v = line.split()
+                out[k] = float(v)
+    return out
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1904_09538_amd import _lib
+    _lib.lib()
+    return _lib
+
+
+@pytest.mark.parametrize("n", [16, 48, 128, 1024])
+def test_matmul_variant_counts_are_the_papers(orc, L, n):
+    g = _golden()
+    n3 = n ** 3
+    names = orc.VARIANT_FEATURES
+    pf = dict(zip(names, orc.variant_features("mm_pf", n, 0, 0, False, 0)))
+    nopf = dict(zip(names, orc.variant_features("mm_nopf", n, 0, 0, False, 0)))
+    # the library's closed form is the walk
+    assert np.array_equal(L.perf_variant_count("mm_pf", n), [pf[k] for k in names])
+    assert np.array_equal(L.perf_variant_count("mm_nopf", n), [nopf[k] for k in names])
+    # local memory: loads and stores of the prefetching variant, none without
+    assert pf["lds_sg"] == 4 * (g["lmem_loads_prefetch"] + g["lmem_stores_prefetch"]) * n3
+    assert nopf["lds_sg"] == 0
+    # global loads: 2 n^3 / 16 against 2 n^3, a factor of 16
+    assert pf["gld_mm_pf_a"] + pf["gld_mm_pf_b"] == 4 * g["gmem_loads_prefetch"] * n3
+    assert nopf["gld_mm_nopf_a"] + nopf["gld_mm_nopf_b"] == 4 * g["gmem_loads_noprefetch"] * n3
+    # multiply-adds, 2 flops each, the same in both
+    assert pf["valu_f32_sg"] == nopf["valu_f32_sg"] == 2 * g["madd"] * n3
+    # one store of c per element
+    assert pf["gst_mm_c"] == nopf["gst_mm_c"] == 4 * n * n
