@@ -53,3 +53,39 @@ def test_matmul_variant_counts_are_the_papers(orc, L, n):
     assert pf["valu_f32_sg"] == nopf["valu_f32_sg"] == 2 * g["madd"] * n3
     # one store of c per element
     assert pf["gst_mm_c"] == nopf["gst_mm_c"] == 4 * n * n
+
+
+def _stencil_golden():
+    path = os.path.join(os.path.dirname(GOLDEN), "stencil_workgroup_counts.txt")
+    rows = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                v, *nums = line.split()
+                rows[v] = dict(zip(("threads", "computing", "idle", "stride"), map(int, nums)))
+    return rows
+
+
+@pytest.mark.parametrize("kind", ["fd16", "fd18"])
+def test_stencil_variant_work_groups_are_the_papers(orc, L, kind):
+    from oracle import variants as OV
+    g = _stencil_golden()[kind]
+    assert g["computing"] + g["idle"] == g["threads"]
+    # one work-group over exactly one stride of interior points: every
+    # work-item fetches once, the computing ones store once
+    n = g["stride"]
+    gx, gy, T = OV.shape(kind, n)
+    assert (gx, gy, T) == (1, 1, g["threads"])
+    f = dict(zip(orc.VARIANT_FEATURES, orc.variant_features(kind, n, 0, 0, False, 0)))
+    assert f["workgroups"] == 1
+    assert f[f"gld_{kind}_u"] == 4 * g["threads"]
+    assert f[f"gst_{kind}_res"] == 4 * g["computing"]
+    # larger grids: work-groups start `stride` points apart in both directions
+    for m in (3 * n, 3 * n + 1):
+        gx, gy, _ = OV.shape(kind, m)
+        assert gx == gy == -(-m // g["stride"])
+        f = dict(zip(orc.VARIANT_FEATURES, orc.variant_features(kind, m, 0, 0, False, 0)))
+        assert f["workgroups"] == gx * gy
+        assert np.array_equal(L.perf_variant_count(kind, m, ld_u=m + 2, ld_res=m),
+                              orc.variant_features(kind, m, 0, 0, False, 0))
