@@ -89,3 +89,26 @@ def test_stencil_variant_work_groups_are_the_papers(orc, L, kind):
         assert f["workgroups"] == gx * gy
         assert np.array_equal(L.perf_variant_count(kind, m, ld_u=m + 2, ld_res=m),
                               orc.variant_features(kind, m, 0, 0, False, 0))
+
+
+def test_dg_variant_configuration_is_the_papers(orc, L):
+    from oracle import variants as OV
+    from paper_1904_09538_amd import variant_study as V
+    g = {}
+    with open(os.path.join(os.path.dirname(GOLDEN), "dg_variant_config.txt")) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, v = line.split()
+                g[k] = int(v)
+    assert (V.NUNIT, V.NMAT) == (g["nunit_nodes"], g["nmatrices"])
+    for kind in ("dg_nopf", "dg_pfu", "dg_pfdm", "dg_pfdmt"):
+        E = 5 * g["tile"] + 3
+        gx, gy, T = OV.shape(kind, E, g["nunit_nodes"])
+        assert T == g["workgroup"] == g["tile"] ** 2
+        assert (gx, gy) == (-(-E // g["tile"]), g["nunit_nodes"] // g["tile"])
+        f = dict(zip(orc.VARIANT_FEATURES, orc.variant_features(kind, E, g["nunit_nodes"], g["nmatrices"],
+                                                                False, 0)))
+        assert f["workgroups"] == gx * gy
+        # every variant does the same 2 nmat nunit^2 flops per element slot of its grid
+        assert f["valu_f32_sg"] == 2 * g["nmatrices"] * g["nunit_nodes"] ** 2 * g["tile"] * gx
